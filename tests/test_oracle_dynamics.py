@@ -1,0 +1,193 @@
+"""Pins of the oracle's dynamics: the BKL step and clock against the exact
+master equation, the phase splitting against the exact product of phase
+propagators, and closed forms for diffusion and drift."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests import brute
+
+A = 3.905
+
+
+def _rate_fn(p: O.RateParams, a=A):
+    def fn(ion, d, src, dst):
+        Ea = p.Ea_O if ion == 0 else p.Ea_H
+        return brute.arrhenius(p.nu, Ea, p.T, p.E_z, p.q, d[2], a)
+    return fn
+
+
+def _run_plain_ensemble(L, occ0, p, t, R, key0=1000):
+    """Final occupancies of R independent plain-BKL runs to time t."""
+    finals = []
+    for r in range(R):
+        lat = O.Lattice(O.Geometry(L=L, seed=key0, lattice_id=r))
+        lat.occ[:] = occ0
+        lat.set_rates(p)
+        lat.advance_plain(10**9, t_horizon=t)
+        assert lat.t == t
+        finals.append(lat.occ.copy())
+    return finals
+
+
+@pytest.mark.parametrize("case", ["1V", "1V_field", "1V1H"])
+def test_bkl_transient_matches_master_equation(case):
+    """P(state, t) of plain BKL (Eqs. TransitionProb, eventSelection and
+    TimeStep) equals row s0 of expm(Q t) of the exact generator on 2x2x2."""
+    L = (2, 2, 2)
+    if case == "1V":
+        p = O.RateParams(nu=1e13, T=600.0, Ea_O=0.6)
+        nv, nh = 1, 0
+    elif case == "1V_field":
+        p = O.RateParams(nu=1e13, T=600.0, Ea_O=0.6, E_z=3e8, q=2.0)
+        nv, nh = 1, 0
+    else:
+        p = O.RateParams(nu=1e13, T=600.0, Ea_O=0.6, Ea_H=0.5)
+        nv, nh = 1, 1
+    states, index, Q = brute.generator(L, nv, nh, _rate_fn(p))
+    occ0 = states[5]
+    k_o = brute.arrhenius(p.nu, p.Ea_O, p.T)
+    t = 0.6 / k_o
+    prob = brute.propagate(Q, t)[index[occ0.tobytes()]]
+    R = 12000 if nh else 6000
+    counts = np.zeros(len(states))
+    for occ in _run_plain_ensemble(L, occ0, p, t, R):
+        counts[index[occ.tobytes()]] += 1
+    stat, pval = brute.chi2_pvalue(counts, prob)
+    assert pval > 1e-4, (stat, pval)
+
+
+def _phase_filter(L, F, colour):
+    """Edges whose midpoint cell lies in a sub-block of the given colour
+    (fragments of F cells per axis, each halved; here F divides L)."""
+    def sub_colour(cell):
+        c = 0
+        for a in range(3):
+            x = cell[a] % F[a]
+            c |= (1 if x >= (F[a] + 1) // 2 else 0) << a
+        return c
+    S = brute.sites(L)
+    Lv = np.array(L, float)
+    pos = [s[3] for s in S]
+
+    def filt(src, dst):
+        d = pos[dst] - pos[src]
+        d -= Lv * np.round(d / Lv)
+        mid = np.mod(pos[src] + d / 2.0, Lv)
+        cell = tuple(int(math.floor(x + 1e-9)) for x in mid)
+        return sub_colour(cell) == colour
+    return filt
+
+
+@pytest.mark.parametrize("L,F,nv,field", [((4, 4, 4), (4, 4, 4), 1, 0.0),
+                                          ((4, 2, 2), (2, 2, 2), 2, 0.0),
+                                          ((4, 2, 2), (2, 2, 2), 2, 3e8)])
+def test_fragment_cycle_matches_phase_propagators(L, F, nv, field):
+    """One fragment-kMC cycle equals prod_c expm(t_sync Q_c) over the 8
+    colour classes in order, where Q_c holds the hops whose edge midpoint
+    lies in a sub-block of colour c; several tiles of one colour run at
+    once, vacancies block each other, the window ends at t_sync."""
+    p = O.RateParams(nu=1e13, T=600.0, Ea_O=0.6, E_z=field, q=2.0)
+    rf = _rate_fn(p)
+    states, index, _ = brute.generator(L, nv, 0, rf)
+    P = np.eye(len(states))
+    k_o = brute.arrhenius(p.nu, p.Ea_O, p.T)
+    t_sync = 0.7 / k_o
+    for c in range(8):
+        _, _, Qc = brute.generator(L, nv, 0, rf, edge_filter=_phase_filter(L, F, c))
+        P = P @ brute.propagate(Qc, t_sync)
+    occ0 = states[len(states) // 3]
+    prob = P[index[occ0.tobytes()]]
+    R = 6000
+    counts = np.zeros(len(states))
+    for r in range(R):
+        lat = O.Lattice(O.Geometry(L=L, frag=F, seed=77, lattice_id=r))
+        lat.occ[:] = occ0
+        lat.set_rates(p)
+        lat.advance(t_sync, max_cycles=1)
+        counts[index[lat.occ.tobytes()]] += 1
+    stat, pval = brute.chi2_pvalue(counts, prob)
+    assert pval > 1e-4, (stat, pval)
+
+
+def test_single_vacancy_diffusion_closed_form():
+    """One vacancy: MSD(t) = Gamma_tot d^2 t exactly in expectation, so
+    D = Gamma_tot d^2 / 6 with Gamma_tot = 8 nu exp(-Ea/kB T), d = a/sqrt(2)."""
+    p = O.RateParams(nu=1e13, T=600.0, Ea_O=0.6)
+    k = brute.arrhenius(p.nu, p.Ea_O, p.T)
+    gam = 8 * k
+    t = 300.0 / gam
+    L = (4, 4, 4)
+    occ0 = np.zeros(3 * 64, np.int8)
+    occ0[7] = 2
+    R = 5000
+    r2 = np.zeros(R)
+    for r in range(R):
+        lat = O.Lattice(O.Geometry(L=L, seed=5, lattice_id=r))
+        lat.occ[:] = occ0
+        lat.set_rates(p)
+        lat.advance_plain(10**9, t_horizon=t)
+        v = np.nonzero(lat.occ == 2)[0][0]
+        r2[r] = (lat.disp[v].astype(float) ** 2).sum() * (A / 2) ** 2
+        assert lat.disp.sum(axis=0).tolist() == [0, 0, 0]
+    D_est = r2.mean() / (6 * t)
+    se = r2.std(ddof=1) / math.sqrt(R) / (6 * t)
+    D_ref = gam * (A / math.sqrt(2)) ** 2 / 6
+    assert abs(D_est - D_ref) < 4 * se, (D_est, D_ref, se)
+    assert se / D_ref < 0.03
+
+
+def test_biased_drift_closed_form():
+    """One vacancy under a field along z from a uniform start: the uniform
+    law is stationary, so E[z(t)] = v t with v = (4a/3)(k+ - k-)."""
+    p = O.RateParams(nu=1e13, T=600.0, Ea_O=0.6, E_z=2e8, q=2.0)
+    kp = brute.arrhenius(p.nu, p.Ea_O, p.T, p.E_z, p.q, 0.5)
+    km = brute.arrhenius(p.nu, p.Ea_O, p.T, p.E_z, p.q, -0.5)
+    v_ref = 4 * A / 3 * (kp - km)
+    t = 200.0 / (8 * kp)
+    R = 3000
+    z = np.zeros(R)
+    for r in range(R):
+        lat = O.Lattice(O.Geometry(L=(3, 3, 3), seed=9, lattice_id=r))
+        lat.init_random(1, 0)
+        lat.set_rates(p)
+        lat.advance_plain(10**9, t_horizon=t)
+        v = np.nonzero(lat.occ == 2)[0][0]
+        z[r] = lat.disp[v, 2] * A / 2
+    v_est = z.mean() / t
+    se = z.std(ddof=1) / math.sqrt(R) / t
+    assert abs(v_est - v_ref) < 4 * se, (v_est, v_ref, se)
+    assert se / v_ref < 0.05
+
+
+def test_displacements_conserved_and_observables():
+    """Every hop adds h to the vacancy and -h to the ion, so the sum of all
+    displacements stays zero; per-species sums then satisfy
+    N_V <r_V> = -(N_O <r_O> + N_H <r_H>).  Observables follow their
+    definitions on a small hand-made configuration."""
+    g = O.Geometry(L=(6, 6, 6), frag=(3, 3, 3))
+    lat = O.Lattice(g)
+    lat.init_random(20, 60)
+    lat.set_rates(O.RateParams(T=700.0, Ea_O=0.6, Ea_H=0.4, E_z=1e8, q=2.0))
+    lat.advance(2e-8, max_cycles=3)
+    assert lat.disp.sum(axis=0).tolist() == [0, 0, 0]
+    st = lat.stats()
+    assert (st.sum_r.sum(axis=0) == 0).all()
+    assert st.count.tolist() == [648 - 80, 60, 20]
+    # hand-made: two vacancies, one H
+    occ = np.zeros(24, np.int8)
+    occ[[0, 5]] = 2
+    occ[7] = 1
+    disp = np.zeros((24, 3), np.int32)
+    disp[0] = [2, 0, -1]
+    disp[5] = [0, 1, 1]
+    disp[7] = [-2, -1, 0]
+    st = O.observables(occ, disp, 4.0, 2.0)
+    assert st.count.tolist() == [21, 1, 2]
+    assert st.sum_r[2].tolist() == [2, 1, 0]
+    assert st.msd[2] == pytest.approx(4.0 * (5 + 2) / 2)
+    assert st.D[2] == pytest.approx(st.msd[2] / 12.0)
+    assert st.drift[2, 0] == pytest.approx(2.0 * 2 / (2 * 2.0))
+    assert st.Dtensor[2, 0, 0] == pytest.approx(4.0 * ((4 + 0) / 2 - 1.0) / 4.0)
