@@ -1,0 +1,226 @@
+/*
+ * fkmc.h - C ABI of the MI355X fragment kinetic Monte Carlo library.
+ *
+ * The library simulates vacancy-mediated diffusion of O and H on the anion
+ * sublattice of a cubic ABO3 perovskite with rejection-free (BKL) kinetic
+ * Monte Carlo (Nakata, arXiv:2004.09081, Sec. "Summary of the conventional
+ * kMC method", Eqs. RateCnst1, TransitionProb, eventSelection, TimeStep),
+ * split into spatial fragments that advance independently to a
+ * synchronisation time (Sec. "Atomic-based fragment kMC method"; the
+ * boundary rule is an 8-colour edge splitting, below).
+ *
+ * A handle holds a SET of n >= 1 independent lattices that advance together
+ * (n = 1 is a single lattice; n > 1 is the batched ensemble).  All device
+ * memory is owned by the caller (e.g. allocated through PyTorch) and passed in
+ * at creation; the library keeps only host-side plans and tables.  Nothing in
+ * this header uses C++ or framework types.
+ *
+ * Conventions
+ *  - Every function returns fkmc_status: FKMC_OK (0) or a negative code.
+ *    A failed call leaves the handle's state unchanged, except that an
+ *    asynchronous device error is reported by the next fkmc_sync/read call.
+ *    fkmc_last_error() returns a message for the calling thread.
+ *  - Device work is enqueued on the HIP stream given at creation; calls that
+ *    return data to the host synchronise that stream.
+ *  - Handles are not thread-safe.  Two handles may share a device.
+ *
+ * Physics conventions
+ *  - Species codes (int8): O = 0, H = 1, vacancy V = 2.
+ *  - Lattice of L[0] x L[1] x L[2] cubic cells, periodic, 3 anion sites per
+ *    cell: type 0 at (0, a/2, a/2), type 1 at (a/2, 0, a/2), type 2 at
+ *    (a/2, a/2, 0) relative to the cell corner.  CANONICAL site order:
+ *    n = ((k*L[1] + j)*L[0] + i)*3 + type.  Each site has 8 neighbours at
+ *    a/sqrt(2); a hop swaps a vacancy with a neighbouring O or H.
+ *  - Displacements are int32 triples in units of a/2, unwrapped; each site's
+ *    entry travels with its occupant (the vacancy gains h, the ion -h).
+ *  - Rate of a hop (Eq. RateCnst1 with the ESP term of the biased run):
+ *    k = nu exp(-(Ea_X + dE/2 + g dE_gb)/(k_B T)), X the ion species,
+ *    dE = -q E_z dz (a/2) the vacancy's electrostatic energy change for a z
+ *    step dz in {-1,0,+1} (units of a/2), g = 1 when either end lies on a
+ *    grain-boundary site.  Rates are rounded to integer multiples of a power
+ *    of two q chosen so that any sum of the rates of one domain is exact in
+ *    binary64; results are therefore independent of summation order.
+ *  - Fragment mode (frag > 0): fragments of frag[a] cells per axis (a last
+ *    remainder of >= 2 cells is its own fragment, 1 cell joins the last),
+ *    each halved per axis into 8 sub-blocks of colour bx + 2 by + 4 bz.  A
+ *    hop edge belongs to the sub-block holding its midpoint.  One CYCLE runs
+ *    colours 0..7 in order; in each PHASE every sub-block of that colour
+ *    advances its own BKL clock from 0 to t_sync (a draw landing after
+ *    t_sync is discarded), and the sub-blocks of one colour never share a
+ *    site.  The lattice clock then advances by t_sync per cycle.
+ *  - Plain mode (frag all 0): one BKL domain over the whole lattice with a
+ *    continuous clock (the conventional kMC of the paper).
+ *  - Random numbers: Philox4x32-10 with key (seed, lattice_id).
+ */
+#ifndef FKMC_H
+#define FKMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fkmc_status;
+#define FKMC_OK 0
+#define FKMC_E_INVALID -1     /* bad argument (null pointer, size, range) */
+#define FKMC_E_STATE -2       /* call not valid in the current state */
+#define FKMC_E_DEVICE -3      /* HIP runtime error */
+#define FKMC_E_RANGE -4       /* rate below the quantisation floor, slot or
+                                 counter overflow detected on the device */
+#define FKMC_E_NOMEM -5       /* caller buffer too small or misaligned */
+#define FKMC_E_UNSUPPORTED -6 /* configuration outside the supported limits */
+
+typedef struct fkmc_lattice fkmc_lattice; /* opaque handle */
+
+/* Geometry of one lattice.  L[a] >= 2.  frag[a] = 0 for all a selects plain
+ * mode; otherwise every frag[a] must be > 0 (a value >= L[a] means one
+ * fragment along that axis).  Sub-block edges must not exceed 100 cells. */
+typedef struct {
+    int32_t L[3];
+    int32_t frag[3];
+    double a_angstrom;   /* lattice constant, Angstrom */
+    uint32_t seed;       /* Philox key word 0 */
+    uint32_t lattice_id; /* Philox key word 1 */
+} fkmc_geometry;
+
+/* Rate parameters of one lattice (Eq. RateCnst1 plus field and boundary
+ * terms).  Grain-boundary planes: normal to axis a when bit a of
+ * gb_axes_mask is set, through every cell whose index along a is a multiple
+ * of gb_period_cells (0 = none); the sites on such a plane are those of type
+ * a in those cells. */
+typedef struct {
+    double nu;     /* attempt frequency, 1/s */
+    double T;      /* temperature, K */
+    double Ea_O;   /* O-vacancy exchange barrier, eV */
+    double Ea_H;   /* H-vacancy exchange barrier, eV */
+    double E_z;    /* uniform field along z, V/m */
+    double q;      /* vacancy charge, units of e (+2 for an oxygen vacancy) */
+    int32_t gb_period_cells;
+    int32_t gb_axes_mask;
+    double gb_dE;  /* extra barrier on boundary hops, eV */
+} fkmc_rate_params;
+
+/* Caller-owned device buffers (one allocation each, covering all lattices).
+ * occ and work must be 256-byte aligned, disp 16-byte aligned. */
+typedef struct {
+    void* occ;   /* int8 occupancy, library storage order (not canonical) */
+    void* disp;  /* int32x4 per site (x, y, z, unused), library order */
+    void* work;  /* descriptors, counters, tables */
+    size_t bytes[3];
+} fkmc_buffers;
+
+/* Statistics of one lattice, species index 0 = O, 1 = H, 2 = V. */
+typedef struct {
+    double t;              /* simulated time, s */
+    uint64_t cycles;       /* fragment cycles completed (0 in plain mode) */
+    uint64_t draws;        /* plain-mode random draws consumed */
+    uint64_t hops[2];      /* hops of O and of H (vacancy hops = sum) */
+    uint64_t count[3];     /* particles per species */
+    int64_t sum_r[3][3];   /* sum of displacements, units of a/2 */
+    int64_t sum_rr[3][6];  /* sum of r_a r_b: xx yy zz xy xz yz, (a/2)^2 */
+    double msd[3];         /* mean square displacement, Angstrom^2 */
+    double D[3];           /* tracer diffusion coefficient MSD/(6t), A^2/s */
+    double drift[3][3];    /* mean velocity, Angstrom/s */
+    double Dtensor[3][6];  /* (<r_a r_b> - <r_a><r_b>)/(2t), A^2/s */
+} fkmc_stats;
+
+/* Required byte sizes of the occ, disp and work buffers for n lattices. */
+fkmc_status fkmc_query_sizes(const fkmc_geometry* geoms, uint32_t n, size_t bytes_out[3]);
+
+/* Create a handle over n lattices in the given buffers; hip_stream may be
+ * NULL (the null stream).  Zeroes occupancy (all O) and displacements. */
+fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffers* buf,
+                        void* hip_stream, fkmc_lattice** out);
+
+/* Never frees the caller's buffers. */
+fkmc_status fkmc_destroy(fkmc_lattice* lat);
+
+uint32_t fkmc_count(const fkmc_lattice* lat);
+
+/* Place exactly n_vac[i] vacancies then n_h[i] H on uniformly chosen
+ * distinct sites of lattice i (all others O) and zero its displacements,
+ * clock and counters.  Draw d uses Philox counter (d_lo, d_hi, 0, 1); its
+ * first two words form a 64-bit w mapped to a site by the upper half of the
+ * 128-bit product w*N, rejecting the low halves below 2^64 mod N, and
+ * rejecting occupied sites.  Invalidates the rate tables. */
+fkmc_status fkmc_init_random(fkmc_lattice* lat, const uint64_t* n_vac, const uint64_t* n_h);
+
+/* Copy occupancy (canonical order, n bytes = 3 L0 L1 L2) into lattice i and
+ * zero its displacements, clock and counters.  Values must be 0, 1 or 2.
+ * Invalidates the rate tables. */
+fkmc_status fkmc_set_occupancy(fkmc_lattice* lat, uint32_t i, const int8_t* host, size_t n);
+
+/* Build and quantise the 12-entry rate table of every lattice from params[i]
+ * (entry (X*3 + dz+1)*2 + g).  The quantum is q = 2^e with
+ * e = ceil(log2 kmax) - 53 + ceil(log2 n_ev), n_ev = 8 min(N_V, S), S the
+ * largest number of sites in one BKL domain.  FKMC_E_RANGE when a nonzero
+ * rate would keep fewer than 10 significant bits. */
+fkmc_status fkmc_set_rates(fkmc_lattice* lat, const fkmc_rate_params* params);
+
+/* Same quantisation applied to a caller-supplied raw table of lattice i. */
+fkmc_status fkmc_set_rate_table(fkmc_lattice* lat, uint32_t i, const double* k12, size_t n);
+
+/* Current quantised table of lattice i (12 doubles). */
+fkmc_status fkmc_get_rate_table(const fkmc_lattice* lat, uint32_t i, double* k12, size_t n);
+
+/* Host-only: raw rates and their quantisation for one parameter set, the way
+ * fkmc_set_rates computes them (no device needed).  q_out and max_rel_out
+ * (maximum relative rounding error) may be NULL. */
+fkmc_status fkmc_rate_table_host(const fkmc_rate_params* p, double a_angstrom, uint64_t n_ev,
+                                 double raw_out[12], double quant_out[12], double* q_out,
+                                 double* max_rel_out);
+
+/* Largest number of sites of one BKL domain of a geometry (whole lattice in
+ * plain mode, else the largest sub-block plus its three +faces). */
+fkmc_status fkmc_max_domain_sites(const fkmc_geometry* g, uint64_t* out);
+
+/* Advance every lattice (asynchronous on the stream).
+ * Fragment lattices: run cycles with window t_sync[i] until the hops made in
+ * this call reach min_hops (checked after each cycle; min_hops = 0 means no
+ * hop target) or max_cycles cycles have run.  Cycle numbers continue across
+ * calls.  Phase c of cycle n in fragment f, BKL step s uses Philox counter
+ * (s, f, n, c*256 + 2).
+ * Plain lattices: make exactly min_hops hops, stopping early when the next
+ * event would land after t_start + t_sync[i] (t_sync[i] > 0; the clock is then
+ * set to that time) or no event is possible.  Draw d uses Philox counter
+ * (d_lo, d_hi, 0xFFFFFFFF, 3).  max_cycles is ignored.
+ * t_sync may be NULL for plain-only sets (no horizon). */
+fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_cycles,
+                         uint64_t min_hops);
+
+/* Run exactly one phase (colour c of the current cycle) on every fragment
+ * lattice, without completing the cycle: the lattice is left mid-cycle, and
+ * only fkmc_run_phase or reads may follow until the 8 colours are done.
+ * For checking single phases against the reference. */
+fkmc_status fkmc_run_phase(fkmc_lattice* lat, const double* t_sync, int32_t colour);
+
+/* Wait for the stream; report device-side errors. */
+fkmc_status fkmc_sync(fkmc_lattice* lat);
+
+/* Occupancy (n bytes) and displacements (3n int32) of lattice i in canonical
+ * order; synchronises.  disp may be NULL. */
+fkmc_status fkmc_read_state(fkmc_lattice* lat, uint32_t i, int8_t* occ, int32_t* disp, size_t n);
+
+/* Statistics of every lattice (out[n]); synchronises. */
+fkmc_status fkmc_read_stats(fkmc_lattice* lat, fkmc_stats* out);
+
+/* Enable (1) or disable (0) HIP-event timing of each phase launch of the
+ * following fkmc_advance calls (at most 2048 launches per call are timed). */
+fkmc_status fkmc_set_timing(fkmc_lattice* lat, int32_t enable);
+
+/* Average duration in milliseconds of the timed phase kernels of the last
+ * fkmc_advance call, measured with HIP events on the handle's stream, and
+ * the number of timed launches (0 if timing was off). */
+fkmc_status fkmc_phase_timing(const fkmc_lattice* lat, double* avg_ms, uint64_t* launches);
+
+/* Rate quantum q and maximum relative rounding error of lattice i's table. */
+fkmc_status fkmc_quantisation(const fkmc_lattice* lat, uint32_t i, double* q, double* max_rel);
+
+const char* fkmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

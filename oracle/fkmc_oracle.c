@@ -642,8 +642,8 @@ int or_advance_frag(const or_geom* g, const double k12[12], int8_t* occ, int32_t
  * persistent counter) uses Philox counter (d_lo, d_hi, 0xFFFFFFFF,
  * TAG_PLAIN).  The clock t advances by -ln(u)/R per hop (Eq. TimeStep).
  * Performs exactly n_hops hops, unless t_horizon > 0 and the next event would
- * fall after t_horizon (then t = t_horizon, the draw is consumed), or no
- * event is possible. */
+ * fall after t_end = t + t_horizon (then t = t_end, the draw is consumed),
+ * or no event is possible. */
 int or_advance_plain(const or_geom* g, const double k12[12], int8_t* occ, int32_t* disp,
                      uint64_t* draws, double* t, double t_horizon, uint64_t n_hops, uint64_t hops[2])
 {
@@ -653,6 +653,7 @@ int or_advance_plain(const or_geom* g, const double k12[12], int8_t* occ, int32_
     step_ctx S;
     uint32_t key[2], ctr[4];
     uint64_t done = 0;
+    double t_end;
     or_hops();
     for (s = 0; s < N; s++) n_slots += (occ[s] == SP_V);
     slots = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_slots > 0 ? n_slots : 1));
@@ -663,15 +664,16 @@ int or_advance_plain(const or_geom* g, const double k12[12], int8_t* occ, int32_
     S.slot_site = slots; S.n_slots = n_slots; S.lo = NULL; S.hi = NULL;
     key[0] = g->seed; key[1] = g->lattice_id;
     hops[0] = hops[1] = 0;
+    t_end = t_horizon > 0.0 ? *t + t_horizon : 0.0;
     while (done < n_hops) {
         int r;
         double tau = *t;
         ctr[0] = (uint32_t)*draws; ctr[1] = (uint32_t)(*draws >> 32);
         ctr[2] = 0xFFFFFFFFu; ctr[3] = TAG_PLAIN;
-        r = bkl_step(&S, ctr, key, &tau, t_horizon, hops);
+        r = bkl_step(&S, ctr, key, &tau, t_end, hops);
         if (r == 1) break;
         *draws = *draws + 1;
-        if (r == 2) { *t = t_horizon; break; }
+        if (r == 2) { *t = t_end; break; }
         *t = tau;
         done++;
     }

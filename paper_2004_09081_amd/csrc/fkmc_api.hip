@@ -1,0 +1,795 @@
+// C ABI of the fragment kMC library (declared in include/fkmc.h): argument
+// checks, the brick plan of each lattice, rate tables, and the host loop
+// that enqueues cycles of 8 phase launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fkmc.h"
+#include "fkmc_internal.h"
+
+using namespace fkmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+fkmc_status fail(fkmc_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(FKMC_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
+                        __FILE__, __LINE__);                                             \
+    } while (0)
+
+#define LAUNCH_OK(expr)                                                                  \
+    do {                                                                                 \
+        int e_ = (expr);                                                                 \
+        if (e_ != 0)                                                                     \
+            return fail(FKMC_E_DEVICE, "%s: %s", #expr, hipGetErrorString((hipError_t)e_)); \
+    } while (0)
+
+// Boltzmann constant in eV/K: k_B/e of the exact SI values (1.380649e-23 J/K,
+// 1.602176634e-19 C), nearest binary64.
+constexpr double kKB = 0x1.696fe94e2cf9ep-14;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Sub-block boundaries along one axis: fragments of F cells (remainder of
+// >= 2 cells its own fragment, 1 cell merged into the last), each halved
+// (lower half ceil, upper floor).  Plain mode: one block [0, L).
+std::vector<int32_t> axis_bounds(int L, int F, bool plain)
+{
+    std::vector<int32_t> b;
+    if (plain) return {0, L};
+    std::vector<int> sizes;
+    if (F >= L) {
+        sizes.push_back(L);
+    } else {
+        const int nf = L / F, r = L - nf * F;
+        sizes.assign(nf, F);
+        if (r >= 2) sizes.push_back(r);
+        else if (r == 1) sizes.back() += 1;
+    }
+    int x = 0;
+    b.push_back(0);
+    for (int s : sizes) {
+        b.push_back(x + (s + 1) / 2);
+        x += s;
+        b.push_back(x);
+    }
+    return b;
+}
+
+bool is_plain(const fkmc_geometry& g) { return g.frag[0] == 0 && g.frag[1] == 0 && g.frag[2] == 0; }
+
+fkmc_status check_geometry(const fkmc_geometry& g, uint32_t idx)
+{
+    for (int a = 0; a < 3; a++)
+        if (g.L[a] < 2 || g.L[a] > 65535)
+            return fail(FKMC_E_INVALID, "lattice %u: L[%d]=%d outside [2, 65535]", idx, a, g.L[a]);
+    const bool plain = is_plain(g);
+    if (!plain)
+        for (int a = 0; a < 3; a++)
+            if (g.frag[a] <= 0)
+                return fail(FKMC_E_INVALID, "lattice %u: frag must be all 0 (plain) or all > 0", idx);
+    if (!(g.a_angstrom > 0.0) || !std::isfinite(g.a_angstrom))
+        return fail(FKMC_E_INVALID, "lattice %u: a_angstrom must be positive", idx);
+    const double n = 3.0 * g.L[0] * (double)g.L[1] * g.L[2];
+    if (n > 9.0e15) return fail(FKMC_E_UNSUPPORTED, "lattice %u too large", idx);
+    return FKMC_OK;
+}
+
+// Largest sub-block footprint (sites) of a fragment geometry.
+uint64_t max_footprint(const fkmc_geometry& g, int* wmax = nullptr)
+{
+    std::vector<int> w[3];
+    for (int a = 0; a < 3; a++) {
+        auto b = axis_bounds(g.L[a], g.frag[a], false);
+        for (size_t i = 0; i + 1 < b.size(); i++) w[a].push_back(b[i + 1] - b[i]);
+    }
+    uint64_t best = 0;
+    int wm = 0;
+    for (int x : w[0])
+        for (int y : w[1])
+            for (int z : w[2]) {
+                const uint64_t s = 3ull * x * y * z + (uint64_t)y * z + (uint64_t)z * x + (uint64_t)x * y;
+                best = std::max(best, s);
+                wm = std::max(wm, std::max(x, std::max(y, z)));
+            }
+    if (wmax) *wmax = wm;
+    return best;
+}
+
+uint64_t domain_sites(const fkmc_geometry& g)
+{
+    if (is_plain(g)) return 3ull * g.L[0] * g.L[1] * g.L[2];
+    return max_footprint(g);
+}
+
+void raw_rates(const fkmc_rate_params& p, double a, double out[12])
+{
+    for (int X = 0; X < 2; X++)
+        for (int dzi = 0; dzi < 3; dzi++)
+            for (int g = 0; g < 2; g++) {
+                const double Ea = X == 0 ? p.Ea_O : p.Ea_H;
+                const double dz = (double)(dzi - 1);
+                const double hs = a * 1e-10 / 2.0;
+                const double dEf = -(p.q * p.E_z * dz * hs);
+                const double b = Ea + dEf / 2.0 + (double)g * p.gb_dE;
+                out[(X * 3 + dzi) * 2 + g] = p.nu * std::exp(-b / (kKB * p.T));
+            }
+}
+
+// Round to multiples of q = 2^e, e = ceil(log2 kmax) - 53 + ceil(log2 n_ev).
+fkmc_status quantise(const double raw[12], uint64_t n_ev, double out[12], double* q_out,
+                     double* rel_out)
+{
+    double kmax = 0.0;
+    for (int i = 0; i < 12; i++) {
+        if (!(raw[i] >= 0.0) || std::isinf(raw[i]))
+            return fail(FKMC_E_INVALID, "rate %d is negative or not finite", i);
+        kmax = std::max(kmax, raw[i]);
+    }
+    if (n_ev < 1) n_ev = 1;
+    double rel = 0.0, q = 0.0;
+    if (kmax == 0.0) {
+        for (int i = 0; i < 12; i++) out[i] = 0.0;
+    } else {
+        int ex;
+        std::frexp(kmax, &ex);
+        if (std::ldexp(1.0, ex - 1) == kmax) ex -= 1;
+        int lg = 0;
+        while ((1ull << lg) < n_ev) lg++;
+        q = std::ldexp(1.0, ex - 53 + lg);
+        for (int i = 0; i < 12; i++) {
+            const double m = std::rint(raw[i] / q);
+            out[i] = m * q;
+            if (raw[i] > 0.0) {
+                if (m < 1024.0)
+                    return fail(FKMC_E_RANGE,
+                                "rate %d = %g keeps fewer than 10 bits at quantum %g (rate ratio "
+                                "too large for exact sums over %llu events)",
+                                i, raw[i], q, (unsigned long long)n_ev);
+                rel = std::max(rel, std::fabs(out[i] - raw[i]) / raw[i]);
+            }
+        }
+    }
+    if (q_out) *q_out = q;
+    if (rel_out) *rel_out = rel;
+    return FKMC_OK;
+}
+
+struct Layout {
+    size_t occ_bytes, disp_bytes, work_bytes;
+    std::vector<int64_t> occ_off, disp_off;
+    size_t o_desc, o_call, o_state, o_buckets, o_stat, o_counts, o_plain, o_tile2lat, o_bounds, o_c2s;
+    int32_t n_tiles;
+    std::vector<std::vector<int32_t>> bounds[3];
+};
+
+Layout plan(const fkmc_geometry* g, uint32_t n)
+{
+    Layout Y;
+    size_t occ = 0, disp = 0;
+    int32_t tiles = 0, nb = 0, nc = 0;
+    for (int a = 0; a < 3; a++) Y.bounds[a].resize(n);
+    for (uint32_t i = 0; i < n; i++) {
+        const uint64_t N = 3ull * g[i].L[0] * g[i].L[1] * g[i].L[2];
+        Y.occ_off.push_back((int64_t)occ);
+        occ = align_up(occ + N, 256);
+        Y.disp_off.push_back((int64_t)disp);
+        disp = align_up(disp + N, 16);
+        const bool pl = is_plain(g[i]);
+        int nf = 1;
+        for (int a = 0; a < 3; a++) {
+            Y.bounds[a][i] = axis_bounds(g[i].L[a], g[i].frag[a], pl);
+            nf *= (int)(Y.bounds[a][i].size() - 1) / (pl ? 1 : 2);
+            nb += (int)Y.bounds[a][i].size();
+            nc += g[i].L[a];
+        }
+        if (!pl) tiles += nf;
+    }
+    Y.n_tiles = tiles;
+    Y.occ_bytes = occ + 64;             // tail slack for 16-byte chunk reads
+    Y.disp_bytes = (disp + 1) * sizeof(int4);
+    size_t w = 0;
+    auto take = [&](size_t bytes) { size_t o = w; w = align_up(w + bytes, 256); return o; };
+    Y.o_desc = take(n * sizeof(LatDesc));
+    Y.o_call = take(n * sizeof(LatCall));
+    Y.o_state = take(n * sizeof(LatState));
+    Y.o_buckets = take((size_t)n * kHopBuckets * 2 * sizeof(unsigned long long));
+    Y.o_stat = take((size_t)n * 3 * kStatFields * sizeof(long long));
+    Y.o_counts = take((size_t)n * 2 * sizeof(uint64_t));
+    Y.o_plain = take((size_t)n * sizeof(int32_t));
+    Y.o_tile2lat = take((size_t)std::max(tiles, 1) * sizeof(int32_t));
+    Y.o_bounds = take((size_t)nb * sizeof(int32_t));
+    Y.o_c2s = take((size_t)nc * sizeof(int32_t));
+    Y.work_bytes = w;
+    return Y;
+}
+
+}  // namespace
+
+struct fkmc_lattice {
+    uint32_t n = 0;
+    std::vector<fkmc_geometry> geo;
+    hipStream_t stream = nullptr;
+    fkmc_buffers buf{};
+    Layout Y;
+    DevPtrs P{};
+    std::vector<LatDesc> desc;
+    std::vector<int32_t> plain_ids;
+    int32_t* d_plain_ids = nullptr;
+    uint64_t* d_counts = nullptr;
+    int lds_per_wave = 0;
+    std::vector<uint64_t> n_vac;
+    std::vector<char> rates_ok;
+    std::vector<double> t_frag;           // fragment-mode clock
+    std::vector<uint64_t> cycles_host;    // cycles at the end of the last call
+    std::vector<LatCall> call;
+    std::vector<double> qstep, qrel;
+    LatState* h_state = nullptr;          // pinned mirror
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    double last_avg_ms = 0.0;
+    uint64_t last_launches = 0;
+};
+
+namespace {
+
+fkmc_status upload_desc(fkmc_lattice* L)
+{
+    HIP_OK(hipMemcpyAsync((char*)L->buf.work + L->Y.o_desc, L->desc.data(),
+                          L->n * sizeof(LatDesc), hipMemcpyHostToDevice, L->stream));
+    HIP_OK(hipStreamSynchronize(L->stream));
+    return FKMC_OK;
+}
+
+fkmc_status reset_counters(fkmc_lattice* L, int64_t only = -1)
+{
+    char* w = (char*)L->buf.work;
+    for (uint32_t i = 0; i < L->n; i++) {
+        if (only >= 0 && (int64_t)i != only) continue;
+        HIP_OK(hipMemsetAsync(w + L->Y.o_state + i * sizeof(LatState), 0, sizeof(LatState), L->stream));
+        HIP_OK(hipMemsetAsync(w + L->Y.o_buckets + (size_t)i * kHopBuckets * 2 * 8, 0,
+                              (size_t)kHopBuckets * 2 * 8, L->stream));
+        L->t_frag[i] = 0.0;
+        L->cycles_host[i] = 0;
+    }
+    return FKMC_OK;
+}
+
+fkmc_status read_states(fkmc_lattice* L)
+{
+    HIP_OK(hipMemcpyAsync(L->h_state, (char*)L->buf.work + L->Y.o_state, L->n * sizeof(LatState),
+                          hipMemcpyDeviceToHost, L->stream));
+    HIP_OK(hipStreamSynchronize(L->stream));
+    for (uint32_t i = 0; i < L->n; i++)
+        if (L->h_state[i].err & 1u)
+            return fail(FKMC_E_RANGE, "lattice %u: too many vacancies in one BKL domain", i);
+    return FKMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fkmc_last_error(void) { return g_err.c_str(); }
+
+fkmc_status fkmc_query_sizes(const fkmc_geometry* geoms, uint32_t n, size_t bytes_out[3])
+{
+    if (!geoms || !bytes_out || n == 0) return fail(FKMC_E_INVALID, "null argument or n = 0");
+    for (uint32_t i = 0; i < n; i++) {
+        fkmc_status s = check_geometry(geoms[i], i);
+        if (s) return s;
+    }
+    Layout Y = plan(geoms, n);
+    bytes_out[0] = Y.occ_bytes;
+    bytes_out[1] = Y.disp_bytes;
+    bytes_out[2] = Y.work_bytes;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_max_domain_sites(const fkmc_geometry* g, uint64_t* out)
+{
+    if (!g || !out) return fail(FKMC_E_INVALID, "null argument");
+    fkmc_status s = check_geometry(*g, 0);
+    if (s) return s;
+    *out = domain_sites(*g);
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_rate_table_host(const fkmc_rate_params* p, double a_angstrom, uint64_t n_ev,
+                                 double raw_out[12], double quant_out[12], double* q_out,
+                                 double* max_rel_out)
+{
+    if (!p || !raw_out || !quant_out) return fail(FKMC_E_INVALID, "null argument");
+    if (!(p->T > 0.0) || !(p->nu >= 0.0)) return fail(FKMC_E_INVALID, "T must be > 0, nu >= 0");
+    raw_rates(*p, a_angstrom, raw_out);
+    return quantise(raw_out, n_ev, quant_out, q_out, max_rel_out);
+}
+
+fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffers* buf,
+                        void* hip_stream, fkmc_lattice** out)
+{
+    if (!geoms || !buf || !out || n == 0) return fail(FKMC_E_INVALID, "null argument or n = 0");
+    *out = nullptr;
+    for (uint32_t i = 0; i < n; i++) {
+        fkmc_status s = check_geometry(geoms[i], i);
+        if (s) return s;
+    }
+    Layout Y = plan(geoms, n);
+    if (!buf->occ || !buf->disp || !buf->work) return fail(FKMC_E_INVALID, "null device buffer");
+    if (buf->bytes[0] < Y.occ_bytes || buf->bytes[1] < Y.disp_bytes || buf->bytes[2] < Y.work_bytes)
+        return fail(FKMC_E_NOMEM, "buffers too small: need %zu/%zu/%zu bytes", Y.occ_bytes,
+                    Y.disp_bytes, Y.work_bytes);
+    if (((uintptr_t)buf->occ & 255) || ((uintptr_t)buf->work & 255) || ((uintptr_t)buf->disp & 15))
+        return fail(FKMC_E_NOMEM, "misaligned device buffer");
+    int maxfp = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        if (is_plain(geoms[i])) continue;
+        int wm = 0;
+        const uint64_t fp = max_footprint(geoms[i], &wm);
+        if (wm > kMaxWidth) return fail(FKMC_E_UNSUPPORTED, "lattice %u: sub-block edge %d > %d", i, wm, kMaxWidth);
+        maxfp = std::max<int>(maxfp, (int)fp);
+    }
+    const int lpw = maxfp ? phase_lds_per_wave(maxfp) : 0;
+    if (lpw > kMaxLdsPerBlock)
+        return fail(FKMC_E_UNSUPPORTED, "sub-block footprint of %d sites exceeds the LDS budget", maxfp);
+
+    fkmc_lattice* L = new fkmc_lattice();
+    L->n = n;
+    L->geo.assign(geoms, geoms + n);
+    L->stream = (hipStream_t)hip_stream;
+    L->buf = *buf;
+    L->Y = Y;
+    L->lds_per_wave = lpw;
+    L->n_vac.assign(n, 0);
+    L->rates_ok.assign(n, 0);
+    L->t_frag.assign(n, 0.0);
+    L->cycles_host.assign(n, 0);
+    L->call.resize(n);
+    L->qstep.assign(n, 0.0);
+    L->qrel.assign(n, 0.0);
+    if (hipHostMalloc((void**)&L->h_state, n * sizeof(LatState), hipHostMallocDefault) != hipSuccess) {
+        delete L;
+        return fail(FKMC_E_DEVICE, "pinned host allocation failed");
+    }
+    char* w = (char*)buf->work;
+    // host tables
+    std::vector<int32_t> bounds, c2s, tile2lat;
+    L->desc.resize(n);
+    for (uint32_t i = 0; i < n; i++) {
+        LatDesc& D = L->desc[i];
+        std::memset(&D, 0, sizeof D);
+        const fkmc_geometry& g = geoms[i];
+        for (int a = 0; a < 3; a++) {
+            D.L[a] = g.L[a];
+            D.nsb[a] = (int32_t)Y.bounds[a][i].size() - 1;
+        }
+        D.plain = is_plain(g) ? 1 : 0;
+        D.seed = g.seed;
+        D.lattice_id = g.lattice_id;
+        D.bounds_off = (int32_t)bounds.size();
+        for (int a = 0; a < 3; a++)
+            bounds.insert(bounds.end(), Y.bounds[a][i].begin(), Y.bounds[a][i].end());
+        D.c2s_off = (int32_t)c2s.size();
+        for (int a = 0; a < 3; a++) {
+            const auto& b = Y.bounds[a][i];
+            for (int x = 0, s = 0; x < g.L[a]; x++) {
+                while (b[s + 1] <= x) s++;
+                c2s.push_back(s);
+            }
+        }
+        D.occ_off = Y.occ_off[i];
+        D.disp_off = Y.disp_off[i];
+        D.n_sites = 3ll * g.L[0] * g.L[1] * g.L[2];
+        if (D.plain) {
+            L->plain_ids.push_back((int32_t)i);
+        } else {
+            D.tile0 = (int32_t)tile2lat.size();
+            const int nf = (D.nsb[0] / 2) * (D.nsb[1] / 2) * (D.nsb[2] / 2);
+            for (int f = 0; f < nf; f++) tile2lat.push_back((int32_t)i);
+        }
+    }
+    L->P.occ = (int8_t*)buf->occ;
+    L->P.disp = (int4*)buf->disp;
+    L->P.desc = (const LatDesc*)(w + Y.o_desc);
+    L->P.call = (LatCall*)(w + Y.o_call);
+    L->P.state = (LatState*)(w + Y.o_state);
+    L->P.buckets = (unsigned long long*)(w + Y.o_buckets);
+    L->P.tile2lat = (const int32_t*)(w + Y.o_tile2lat);
+    L->P.bounds = (const int32_t*)(w + Y.o_bounds);
+    L->P.c2s = (const int32_t*)(w + Y.o_c2s);
+    L->P.stat_acc = (long long*)(w + Y.o_stat);
+    L->P.n_lat = (int32_t)n;
+    L->P.n_tiles = Y.n_tiles;
+    L->d_plain_ids = (int32_t*)(w + Y.o_plain);
+    L->d_counts = (uint64_t*)(w + Y.o_counts);
+
+    auto cleanup = [&](fkmc_status s) { (void)hipHostFree(L->h_state); delete L; return s; };
+#define CREATE_OK(expr)                                                             \
+    do {                                                                            \
+        hipError_t e_ = (expr);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return cleanup(fail(FKMC_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+    CREATE_OK(hipMemsetAsync(buf->work, 0, Y.work_bytes, L->stream));
+    CREATE_OK(hipMemsetAsync(buf->occ, 0, Y.occ_bytes, L->stream));
+    CREATE_OK(hipMemsetAsync(buf->disp, 0, Y.disp_bytes, L->stream));
+    CREATE_OK(hipMemcpyAsync(w + Y.o_desc, L->desc.data(), n * sizeof(LatDesc), hipMemcpyHostToDevice, L->stream));
+    if (!bounds.empty())
+        CREATE_OK(hipMemcpyAsync(w + Y.o_bounds, bounds.data(), bounds.size() * 4, hipMemcpyHostToDevice, L->stream));
+    CREATE_OK(hipMemcpyAsync(w + Y.o_c2s, c2s.data(), c2s.size() * 4, hipMemcpyHostToDevice, L->stream));
+    if (!tile2lat.empty())
+        CREATE_OK(hipMemcpyAsync(w + Y.o_tile2lat, tile2lat.data(), tile2lat.size() * 4, hipMemcpyHostToDevice, L->stream));
+    if (!L->plain_ids.empty())
+        CREATE_OK(hipMemcpyAsync(L->d_plain_ids, L->plain_ids.data(), L->plain_ids.size() * 4, hipMemcpyHostToDevice, L->stream));
+    CREATE_OK(hipStreamSynchronize(L->stream));
+#undef CREATE_OK
+    *out = L;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_destroy(fkmc_lattice* L)
+{
+    if (!L) return FKMC_OK;
+    (void)hipStreamSynchronize(L->stream);
+    for (auto e : L->ev) (void)hipEventDestroy(e);
+    if (L->h_state) (void)hipHostFree(L->h_state);
+    delete L;
+    return FKMC_OK;
+}
+
+uint32_t fkmc_count(const fkmc_lattice* L) { return L ? L->n : 0; }
+
+fkmc_status fkmc_init_random(fkmc_lattice* L, const uint64_t* n_vac, const uint64_t* n_h)
+{
+    if (!L || !n_vac || !n_h) return fail(FKMC_E_INVALID, "null argument");
+    std::vector<uint64_t> cnt(2 * L->n);
+    for (uint32_t i = 0; i < L->n; i++) {
+        const uint64_t N = (uint64_t)L->desc[i].n_sites;
+        if (n_vac[i] > N || n_h[i] > N - n_vac[i])
+            return fail(FKMC_E_INVALID, "lattice %u: %llu + %llu particles exceed %llu sites", i,
+                        (unsigned long long)n_vac[i], (unsigned long long)n_h[i], (unsigned long long)N);
+        cnt[2 * i] = n_vac[i];
+        cnt[2 * i + 1] = n_h[i];
+    }
+    HIP_OK(hipMemsetAsync(L->buf.occ, 0, L->Y.occ_bytes, L->stream));
+    HIP_OK(hipMemsetAsync(L->buf.disp, 0, L->Y.disp_bytes, L->stream));
+    fkmc_status s = reset_counters(L);
+    if (s) return s;
+    HIP_OK(hipMemcpyAsync(L->d_counts, cnt.data(), cnt.size() * 8, hipMemcpyHostToDevice, L->stream));
+    LAUNCH_OK(launch_init(L->P, L->d_counts, (int)L->n, L->stream));
+    HIP_OK(hipStreamSynchronize(L->stream));
+    for (uint32_t i = 0; i < L->n; i++) {
+        L->n_vac[i] = n_vac[i];
+        L->rates_ok[i] = 0;
+    }
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_set_occupancy(fkmc_lattice* L, uint32_t i, const int8_t* host, size_t n)
+{
+    if (!L || !host) return fail(FKMC_E_INVALID, "null argument");
+    if (i >= L->n) return fail(FKMC_E_INVALID, "lattice index %u out of range", i);
+    const size_t N = (size_t)L->desc[i].n_sites;
+    if (n != N) return fail(FKMC_E_INVALID, "occupancy has %zu entries, lattice has %zu sites", n, N);
+    uint64_t nv = 0;
+    for (size_t k = 0; k < N; k++) {
+        if (host[k] < 0 || host[k] > 2) return fail(FKMC_E_INVALID, "species code %d at %zu", host[k], k);
+        nv += host[k] == kSpV;
+    }
+    int8_t* tmp = nullptr;
+    HIP_OK(hipMalloc((void**)&tmp, N));
+    hipError_t e = hipMemcpyAsync(tmp, host, N, hipMemcpyHostToDevice, L->stream);
+    int le = e == hipSuccess ? launch_scatter(L->P, (int)i, (int64_t)N, tmp, L->stream) : 0;
+    hipError_t e2 = hipStreamSynchronize(L->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess || le != 0 || e2 != hipSuccess)
+        return fail(FKMC_E_DEVICE, "set_occupancy copy failed");
+    fkmc_status s = reset_counters(L, i);
+    if (s) return s;
+    HIP_OK(hipStreamSynchronize(L->stream));
+    L->n_vac[i] = nv;
+    L->rates_ok[i] = 0;
+    return FKMC_OK;
+}
+
+static fkmc_status set_table(fkmc_lattice* L, uint32_t i, const double raw[12])
+{
+    const uint64_t nev = 8ull * std::min<uint64_t>(std::max<uint64_t>(L->n_vac[i], 1), domain_sites(L->geo[i]));
+    double k[12], q, rel;
+    fkmc_status s = quantise(raw, nev, k, &q, &rel);
+    if (s) return fail(s, "lattice %u: %s", i, g_err.c_str());
+    std::memcpy(L->desc[i].k12, k, sizeof k);
+    L->qstep[i] = q;
+    L->qrel[i] = rel;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_set_rates(fkmc_lattice* L, const fkmc_rate_params* params)
+{
+    if (!L || !params) return fail(FKMC_E_INVALID, "null argument");
+    std::vector<LatDesc> backup = L->desc;
+    for (uint32_t i = 0; i < L->n; i++) {
+        const fkmc_rate_params& p = params[i];
+        if (!(p.T > 0.0) || !(p.nu >= 0.0) || !std::isfinite(p.E_z) || !std::isfinite(p.q) ||
+            p.gb_period_cells < 0)
+            return fail(FKMC_E_INVALID, "lattice %u: invalid rate parameters", i);
+        double raw[12];
+        raw_rates(p, L->geo[i].a_angstrom, raw);
+        fkmc_status s = set_table(L, i, raw);
+        if (s) {
+            L->desc = backup;
+            return s;
+        }
+        L->desc[i].gb_period = p.gb_period_cells;
+        L->desc[i].gb_mask = p.gb_axes_mask;
+    }
+    fkmc_status s = upload_desc(L);
+    if (s) {
+        L->desc = backup;
+        return s;
+    }
+    for (uint32_t i = 0; i < L->n; i++) L->rates_ok[i] = 1;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_set_rate_table(fkmc_lattice* L, uint32_t i, const double* k12, size_t n)
+{
+    if (!L || !k12) return fail(FKMC_E_INVALID, "null argument");
+    if (i >= L->n || n != 12) return fail(FKMC_E_INVALID, "bad index or table size");
+    LatDesc backup = L->desc[i];
+    fkmc_status s = set_table(L, i, k12);
+    if (s) return s;
+    s = upload_desc(L);
+    if (s) {
+        L->desc[i] = backup;
+        return s;
+    }
+    L->rates_ok[i] = 1;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_get_rate_table(const fkmc_lattice* L, uint32_t i, double* k12, size_t n)
+{
+    if (!L || !k12) return fail(FKMC_E_INVALID, "null argument");
+    if (i >= L->n || n < 12) return fail(FKMC_E_INVALID, "bad index or table size");
+    std::memcpy(k12, L->desc[i].k12, 12 * sizeof(double));
+    return FKMC_OK;
+}
+
+static fkmc_status record_phase(fkmc_lattice* L, int colour, size_t& ev_used)
+{
+    if (L->timing && ev_used + 2 <= L->ev.size()) {
+        HIP_OK(hipEventRecord(L->ev[ev_used], L->stream));
+        LAUNCH_OK(launch_phase(L->P, colour, L->lds_per_wave, L->stream));
+        HIP_OK(hipEventRecord(L->ev[ev_used + 1], L->stream));
+        ev_used += 2;
+    } else {
+        LAUNCH_OK(launch_phase(L->P, colour, L->lds_per_wave, L->stream));
+    }
+    return FKMC_OK;
+}
+
+static fkmc_status prepare_call(fkmc_lattice* L, const double* t_sync, uint64_t max_cycles,
+                                uint64_t min_hops, bool need_tsync_frag)
+{
+    for (uint32_t i = 0; i < L->n; i++) {
+        if (!L->rates_ok[i]) return fail(FKMC_E_STATE, "lattice %u: rates not set", i);
+        const bool pl = L->desc[i].plain;
+        const double ts = t_sync ? t_sync[i] : 0.0;
+        if (!pl && need_tsync_frag && !(ts > 0.0 && std::isfinite(ts)))
+            return fail(FKMC_E_INVALID, "lattice %u: t_sync must be positive and finite", i);
+        if (pl && !(ts >= 0.0)) return fail(FKMC_E_INVALID, "lattice %u: negative horizon", i);
+        L->call[i] = LatCall{ts, min_hops, max_cycles, 0, 0};
+    }
+    HIP_OK(hipMemcpyAsync(L->P.call, L->call.data(), L->n * sizeof(LatCall), hipMemcpyHostToDevice,
+                          L->stream));
+    HIP_OK(hipStreamSynchronize(L->stream));
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cycles, uint64_t min_hops)
+{
+    if (!L) return fail(FKMC_E_INVALID, "null handle");
+    const bool any_frag = L->Y.n_tiles > 0;
+    if (any_frag && !t_sync) return fail(FKMC_E_INVALID, "t_sync required for fragment lattices");
+    fkmc_status s = prepare_call(L, t_sync, max_cycles, min_hops, true);
+    if (s) return s;
+    LAUNCH_OK(launch_plain(L->P, L->d_plain_ids, (int)L->plain_ids.size(), L->stream));
+    size_t ev_used = 0;
+    uint64_t launched = 0;
+    if (L->timing && any_frag && L->ev.empty()) {
+        L->ev.resize(2 * 2048);
+        for (auto& e : L->ev) HIP_OK(hipEventCreate(&e));
+    }
+    if (any_frag && max_cycles > 0) {
+        LAUNCH_OK(launch_cycle_begin(L->P, L->stream));
+        uint64_t batch = min_hops > 0 ? 1 : max_cycles;
+        uint64_t cyc = 0;
+        while (cyc < max_cycles) {
+            const uint64_t nb = std::min(batch, max_cycles - cyc);
+            for (uint64_t b = 0; b < nb; b++) {
+                for (int c = 0; c < 8; c++) {
+                    s = record_phase(L, c, ev_used);
+                    if (s) return s;
+                }
+                LAUNCH_OK(launch_cycle_end(L->P, L->stream));
+            }
+            cyc += nb;
+            launched += 8 * nb;
+            if (cyc >= max_cycles) break;
+            s = read_states(L);
+            if (s) return s;
+            bool all = true;
+            for (uint32_t i = 0; i < L->n; i++)
+                if (!L->desc[i].plain && !L->h_state[i].done) all = false;
+            if (all) break;
+            batch = std::min<uint64_t>(batch * 2, 64);
+        }
+    }
+    s = read_states(L);
+    if (s) return s;
+    for (uint32_t i = 0; i < L->n; i++) {
+        if (L->desc[i].plain) continue;
+        const uint64_t nc = L->h_state[i].cycles - L->cycles_host[i];
+        L->t_frag[i] = L->t_frag[i] + (double)nc * L->call[i].t_sync;
+        L->cycles_host[i] = L->h_state[i].cycles;
+    }
+    L->last_launches = 0;
+    L->last_avg_ms = 0.0;
+    if (L->timing && ev_used) {
+        double tot = 0.0;
+        for (size_t k = 0; k < ev_used; k += 2) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, L->ev[k], L->ev[k + 1]));
+            tot += ms;
+        }
+        L->last_launches = ev_used / 2;
+        L->last_avg_ms = tot / (double)(ev_used / 2);
+    }
+    (void)launched;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_run_phase(fkmc_lattice* L, const double* t_sync, int32_t colour)
+{
+    if (!L || !t_sync) return fail(FKMC_E_INVALID, "null argument");
+    if (colour < 0 || colour > 7) return fail(FKMC_E_INVALID, "colour must be 0..7");
+    fkmc_status s = prepare_call(L, t_sync, 1, 0, true);
+    if (s) return s;
+    LAUNCH_OK(launch_cycle_begin(L->P, L->stream));
+    LAUNCH_OK(launch_phase(L->P, colour, L->lds_per_wave, L->stream));
+    return read_states(L);
+}
+
+fkmc_status fkmc_sync(fkmc_lattice* L)
+{
+    if (!L) return fail(FKMC_E_INVALID, "null handle");
+    return read_states(L);
+}
+
+fkmc_status fkmc_read_state(fkmc_lattice* L, uint32_t i, int8_t* occ, int32_t* disp, size_t n)
+{
+    if (!L || !occ) return fail(FKMC_E_INVALID, "null argument");
+    if (i >= L->n) return fail(FKMC_E_INVALID, "lattice index out of range");
+    const size_t N = (size_t)L->desc[i].n_sites;
+    if (n != N) return fail(FKMC_E_INVALID, "buffer has %zu entries, lattice has %zu sites", n, N);
+    fkmc_status s = read_states(L);
+    if (s) return s;
+    int8_t* t_occ = nullptr;
+    int32_t* t_disp = nullptr;
+    HIP_OK(hipMalloc((void**)&t_occ, N));
+    if (disp && hipMalloc((void**)&t_disp, N * 12) != hipSuccess) {
+        (void)hipFree(t_occ);
+        return fail(FKMC_E_DEVICE, "temporary allocation failed");
+    }
+    int le = launch_gather(L->P, (int)i, (int64_t)N, t_occ, t_disp, L->stream);
+    hipError_t e1 = hipMemcpyAsync(occ, t_occ, N, hipMemcpyDeviceToHost, L->stream);
+    hipError_t e2 = disp ? hipMemcpyAsync(disp, t_disp, N * 12, hipMemcpyDeviceToHost, L->stream) : hipSuccess;
+    hipError_t e3 = hipStreamSynchronize(L->stream);
+    (void)hipFree(t_occ);
+    if (t_disp) (void)hipFree(t_disp);
+    if (le || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+        return fail(FKMC_E_DEVICE, "read_state failed");
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_read_stats(fkmc_lattice* L, fkmc_stats* out)
+{
+    if (!L || !out) return fail(FKMC_E_INVALID, "null argument");
+    HIP_OK(hipMemsetAsync(L->P.stat_acc, 0, (size_t)L->n * 3 * kStatFields * 8, L->stream));
+    for (uint32_t i = 0; i < L->n; i++)
+        LAUNCH_OK(launch_stats(L->P, (int)i, L->desc[i].n_sites, L->stream));
+    std::vector<long long> acc((size_t)L->n * 3 * kStatFields);
+    std::vector<unsigned long long> bk((size_t)L->n * kHopBuckets * 2);
+    HIP_OK(hipMemcpyAsync(acc.data(), L->P.stat_acc, acc.size() * 8, hipMemcpyDeviceToHost, L->stream));
+    HIP_OK(hipMemcpyAsync(bk.data(), L->P.buckets, bk.size() * 8, hipMemcpyDeviceToHost, L->stream));
+    fkmc_status s = read_states(L);
+    if (s) return s;
+    for (uint32_t i = 0; i < L->n; i++) {
+        fkmc_stats& o = out[i];
+        std::memset(&o, 0, sizeof o);
+        const LatState& S = L->h_state[i];
+        if (L->desc[i].plain) {
+            o.t = S.t;
+            o.draws = S.draws;
+            o.hops[0] = S.hops[0];
+            o.hops[1] = S.hops[1];
+        } else {
+            o.t = L->t_frag[i];
+            o.cycles = S.cycles;
+            for (int b = 0; b < kHopBuckets; b++) {
+                o.hops[0] += bk[((size_t)i * kHopBuckets + b) * 2];
+                o.hops[1] += bk[((size_t)i * kHopBuckets + b) * 2 + 1];
+            }
+        }
+        const double h = L->geo[i].a_angstrom / 2.0;
+        for (int sp = 0; sp < 3; sp++) {
+            const long long* a = &acc[((size_t)i * 3 + sp) * kStatFields];
+            o.count[sp] = (uint64_t)a[0];
+            for (int c = 0; c < 3; c++) o.sum_r[sp][c] = a[1 + c];
+            for (int c = 0; c < 6; c++) o.sum_rr[sp][c] = a[4 + c];
+            const double nX = a[0] > 0 ? (double)a[0] : 1.0;
+            o.msd[sp] = h * h * (double)(a[4] + a[5] + a[6]) / nX;
+            const double t = o.t;
+            o.D[sp] = t > 0 ? o.msd[sp] / (6.0 * t) : NAN;
+            double mean[3];
+            for (int c = 0; c < 3; c++) {
+                mean[c] = (double)a[1 + c] / nX;
+                o.drift[sp][c] = t > 0 ? h * mean[c] / t : NAN;
+            }
+            const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+            for (int c = 0; c < 6; c++) {
+                const double cov = (double)a[4 + c] / nX - mean[pa[c]] * mean[pb[c]];
+                o.Dtensor[sp][c] = t > 0 ? h * h * cov / (2.0 * t) : NAN;
+            }
+        }
+    }
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_set_timing(fkmc_lattice* L, int32_t enable)
+{
+    if (!L) return fail(FKMC_E_INVALID, "null handle");
+    L->timing = enable != 0;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_phase_timing(const fkmc_lattice* L, double* avg_ms, uint64_t* launches)
+{
+    if (!L || !avg_ms || !launches) return fail(FKMC_E_INVALID, "null argument");
+    *avg_ms = L->last_avg_ms;
+    *launches = L->last_launches;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_quantisation(const fkmc_lattice* L, uint32_t i, double* q, double* max_rel)
+{
+    if (!L || !q || !max_rel || i >= L->n) return fail(FKMC_E_INVALID, "bad argument");
+    *q = L->qstep[i];
+    *max_rel = L->qrel[i];
+    return FKMC_OK;
+}
+
+}  // extern "C"

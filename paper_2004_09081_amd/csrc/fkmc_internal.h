@@ -1,0 +1,99 @@
+// Internal layout shared by the library's kernels and host code.
+//
+// HBM layout of one lattice (occupancy int8, displacement int32x4 with the
+// same site numbering): the lattice is cut into the sub-blocks of the
+// fragment decomposition (plain mode: one block).  Sub-block (bi, bj, bk)
+// with cell ranges [x0,x0+wx) x [y0,y0+wy) x [z0,z0+wz) is one contiguous
+// brick at offset 3 (z0 Ly Lx + wz (y0 Lx + wy x0)).  Inside a brick the
+// three site types are stored as planes of V = wx wy wz bytes, each with
+// its own face axis slowest:
+//   type 0: (x wz + z) wy + y        (x = 0 face first)
+//   type 1: V + (y wz + z) wx + x    (y = 0 face first)
+//   type 2: 2V + (z wy + y) wx + x   (z = 0 face first)
+// so the +x, +y and +z faces a phase needs from the neighbouring bricks are
+// each one contiguous run of bytes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fkmc {
+
+constexpr int kSpO = 0;
+constexpr int kSpH = 1;
+constexpr int kSpV = 2;
+
+constexpr int kMaxWidth = 100;      // largest sub-block edge (cells)
+constexpr int kMaxLdsPerBlock = 65536;  // dynamic LDS of one phase workgroup
+constexpr int kMaxSlots = 128;      // vacancies per fragment-mode footprint
+constexpr int kMaxPlainSlots = 4096;  // vacancies per plain-mode lattice
+constexpr int kHopBuckets = 256;    // spread of the per-lattice hop counters
+constexpr int kStatFields = 10;     // count, r(3), rr(6)
+
+// Static description of one lattice (device copy in the work buffer).
+struct LatDesc {
+    int32_t L[3];
+    int32_t nsb[3];       // sub-blocks per axis (2 per fragment; 1 in plain mode)
+    int32_t plain;
+    uint32_t seed;
+    uint32_t lattice_id;
+    int32_t gb_period;
+    int32_t gb_mask;
+    int32_t tile0;        // first global tile index of this lattice (fragment mode)
+    int32_t bounds_off;   // sub-block boundaries: [nsb0+1][nsb1+1][nsb2+1]
+    int32_t c2s_off;      // cell -> sub-block index: [L0][L1][L2]
+    int64_t occ_off;      // byte offset in the occupancy buffer
+    int64_t disp_off;     // element (int4) offset in the displacement buffer
+    int64_t n_sites;
+    double k12[12];       // quantised rates, (X*3 + dz+1)*2 + g
+};
+
+// Per-call parameters.
+struct LatCall {
+    double t_sync;
+    uint64_t min_hops;
+    uint64_t max_cycles;
+    uint64_t hops_start;
+    uint64_t cycles_start;
+};
+
+// Dynamic state.
+struct LatState {
+    uint64_t cycles;
+    uint32_t done;
+    uint32_t err;         // bit 0: slot overflow, bit 1: displacement overflow
+    double t;             // plain-mode clock
+    uint64_t draws;       // plain-mode draw counter
+    uint64_t hops[2];     // plain-mode hop counters (O, H)
+    uint64_t pad[2];
+};
+
+struct DevPtrs {
+    int8_t* occ;
+    int4* disp;
+    const LatDesc* desc;
+    LatCall* call;
+    LatState* state;
+    unsigned long long* buckets;   // [n][kHopBuckets][2]
+    const int32_t* tile2lat;       // [n_tiles]
+    const int32_t* bounds;
+    const int32_t* c2s;
+    long long* stat_acc;           // [n][3][kStatFields]
+    int32_t n_lat;
+    int32_t n_tiles;               // fragment-mode tiles per colour, all lattices
+};
+
+// Kernel launchers (fkmc_device.hip).  All return a hipError_t value.
+int launch_init(const DevPtrs& P, const uint64_t* d_counts, int n_lat, void* stream);
+int launch_phase(const DevPtrs& P, int colour, int lds_per_wave, void* stream);
+int launch_cycle_begin(const DevPtrs& P, void* stream);
+int launch_cycle_end(const DevPtrs& P, void* stream);
+int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void* stream);
+int launch_stats(const DevPtrs& P, int lat, int64_t n_sites, void* stream);
+int launch_gather(const DevPtrs& P, int lat, int64_t n_sites, int8_t* d_occ_canon,
+                  int32_t* d_disp_canon, void* stream);
+int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_occ_canon,
+                   void* stream);
+// LDS bytes one wave of the phase kernel needs for a footprint of the given size.
+int phase_lds_per_wave(int max_footprint_bytes);
+
+}  // namespace fkmc

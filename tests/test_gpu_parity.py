@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle,
+element by element, on the same seeded inputs.  Integer state
+(occupancy, displacements, hop counts, cycle counts) must be identical, and
+so must the binary64 clock, because both sides follow the same sequence of
+correctly rounded operations on exactly summable rates."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.common import Case, assert_same_state, gpu_set, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_09081_amd import fkmc
+    fkmc.lib()
+
+
+# Geometries: ragged remainders (>= 2 and == 1), single fragment along an
+# axis, minimal L = 2, several tiles of each colour, H present, field, GB.
+FRAG_CASES = {
+    "cube12_w3": Case((12, 12, 12), (6, 6, 6), seed=1, nv=30, nh=100, T=700.0, Ea_O=0.6,
+                      Ea_H=0.45),
+    "ragged": Case((11, 9, 10), (4, 4, 3), seed=2, lattice_id=5, nv=25, nh=60, T=650.0,
+                   Ea_O=0.55, Ea_H=0.5),
+    "single_frag_axis": Case((8, 6, 4), (16, 3, 2), seed=3, nv=12, nh=0, T=600.0),
+    "minimal_L2": Case((2, 2, 2), (2, 2, 2), seed=4, nv=3, nh=2, T=600.0, Ea_H=0.55),
+    "field_gb": Case((16, 16, 20), (8, 8, 10), seed=5, nv=40, nh=0, T=500.0, Ea_O=0.5,
+                     E_z=3e8, gb_period=5, gb_mask=4, gb_dE=0.1),
+    "gb_all_axes": Case((12, 12, 12), (4, 4, 4), seed=6, nv=30, nh=30, T=600.0, Ea_O=0.55,
+                        Ea_H=0.5, gb_period=3, gb_mask=7, gb_dE=0.05),
+    "dense_vac": Case((8, 8, 8), (8, 8, 8), seed=7, nv=120, nh=40, T=600.0, Ea_H=0.5),
+}
+
+
+@pytest.mark.parametrize("name", list(FRAG_CASES))
+def test_init_matches_oracle(name):
+    c = FRAG_CASES[name]
+    say("init parity", name)
+    g = gpu_set([c])
+    assert_same_state(g, 0, c.oracle(), name)
+
+
+@pytest.mark.parametrize("name", list(FRAG_CASES))
+def test_fragment_cycles_match_oracle(name):
+    c = FRAG_CASES[name]
+    say("fragment parity", name)
+    lat = c.oracle()
+    k = lat.k12
+    t_sync = 1.0 / (8.0 * k[0]) * 2.0
+    g = gpu_set([c])
+    assert g.get_rate_table(0).tobytes() == k.tobytes()
+    for rep in range(2):
+        lat.advance(t_sync, max_cycles=3)
+        g.advance([t_sync], max_cycles=3)
+        st = g.read_stats()[0]
+        assert st["cycles"] == lat.cycles
+        assert st["hops"].tolist() == [int(x) for x in lat.hops]
+        assert st["t"] == lat.t
+        assert_same_state(g, 0, lat, "%s rep %d" % (name, rep))
+    assert int(lat.hops.sum()) > 0
+
+
+def test_min_hops_stop_rule():
+    c = FRAG_CASES["cube12_w3"]
+    say("min_hops stop rule")
+    lat = c.oracle()
+    t_sync = 0.5 / (8.0 * lat.k12[0])
+    lat.advance(t_sync, max_cycles=1000, min_hops=500)
+    g = gpu_set([c])
+    g.advance([t_sync], max_cycles=1000, min_hops=500)
+    st = g.read_stats()[0]
+    assert st["cycles"] == lat.cycles and st["hops"].tolist() == [int(x) for x in lat.hops]
+    assert int(lat.hops.sum()) >= 500
+    assert_same_state(g, 0, lat, "min_hops")
+
+
+@pytest.mark.parametrize("name", ["ragged", "field_gb"])
+def test_single_phase_matches_oracle(name):
+    c = FRAG_CASES[name]
+    say("single phase parity", name)
+    lat = c.oracle()
+    t_sync = 3.0 / (8.0 * lat.k12[0])
+    g = gpu_set([c])
+    for colour in (0, 5):
+        for f in range(lat.n_fragments):
+            lat.phase(t_sync, 0, colour, f)
+        g.run_phase([t_sync], colour)
+        assert_same_state(g, 0, lat, "%s colour %d" % (name, colour))
+
+
+PLAIN_CASES = {
+    "cfg1_8cube": Case((8, 8, 8), seed=0, nv=15, nh=0, T=600.0, Ea_O=0.6),
+    "plain_H": Case((6, 5, 7), seed=9, lattice_id=3, nv=20, nh=50, T=650.0, Ea_O=0.6, Ea_H=0.45),
+    "plain_field_gb": Case((6, 6, 6), seed=10, nv=8, nh=0, T=500.0, Ea_O=0.5, E_z=2e8,
+                           gb_period=3, gb_dE=0.1),
+}
+
+
+@pytest.mark.parametrize("name", list(PLAIN_CASES))
+def test_plain_matches_oracle(name):
+    c = PLAIN_CASES[name]
+    say("plain parity", name)
+    lat = c.oracle()
+    g = gpu_set([c])
+    for n_hops in (1000, 2500):
+        lat.advance_plain(n_hops)
+        g.advance([0.0], 0, n_hops)
+        st = g.read_stats()[0]
+        assert st["draws"] == lat.draws
+        assert st["t"] == lat.t
+        assert st["hops"].tolist() == [int(x) for x in lat.hops]
+        assert_same_state(g, 0, lat, name)
+    # horizon stop: the clock lands exactly on the horizon
+    horizon = 50.0 / (8 * lat.k12[0])
+    t0 = lat.t
+    lat.advance_plain(10**9, t_horizon=horizon)
+    g.advance([horizon - 0.0], 0, 10**9)
+    st = g.read_stats()[0]
+    assert lat.t == t0 + horizon
+    assert st["t"] == lat.t and st["draws"] == lat.draws
+    assert_same_state(g, 0, lat, name + " horizon")
+
+
+def test_batched_set_matches_oracle():
+    """Lattices of different sizes, modes and parameters in one set, each
+    identical to its own oracle run."""
+    cases = [FRAG_CASES["cube12_w3"], FRAG_CASES["ragged"], PLAIN_CASES["plain_H"],
+             FRAG_CASES["field_gb"], Case((20, 14, 9), (5, 7, 4), seed=11, lattice_id=77,
+                                          nv=50, nh=120, T=800.0, Ea_O=0.7, Ea_H=0.5)]
+    say("batched parity", len(cases))
+    lats = [c.oracle() for c in cases]
+    ts = [2.0 / (8.0 * l.k12[0]) for l in lats]
+    g = gpu_set(cases)
+    for lat, c, t in zip(lats, cases, ts):
+        if lat.g.plain:
+            lat.advance_plain(700)
+        else:
+            lat.advance(t, max_cycles=4)
+    g.advance(ts, max_cycles=4, min_hops=0)
+    # plain members make exactly min_hops hops; min_hops=0 means none
+    for i, (lat, c) in enumerate(zip(lats, cases)):
+        if lat.g.plain:
+            continue
+        assert_same_state(g, i, lat, "batch member %d" % i)
+    stats = g.read_stats()
+    for i, lat in enumerate(lats):
+        if lat.g.plain:
+            continue
+        assert stats[i]["cycles"] == lat.cycles and stats[i]["t"] == lat.t
+
+
+def test_stats_match_oracle_observables():
+    c = FRAG_CASES["field_gb"]
+    say("stats parity")
+    lat = c.oracle()
+    t_sync = 2.0 / (8.0 * lat.k12[0])
+    lat.advance(t_sync, max_cycles=5)
+    g = gpu_set([c])
+    g.advance([t_sync], max_cycles=5)
+    st = g.read_stats()[0]
+    ref = lat.stats()
+    assert st["count"].tolist() == ref.count.tolist()
+    assert st["sum_r"].tolist() == ref.sum_r.tolist()
+    rr = ref.sum_rr
+    six = np.stack([rr[:, 0, 0], rr[:, 1, 1], rr[:, 2, 2], rr[:, 0, 1], rr[:, 0, 2], rr[:, 1, 2]], 1)
+    assert st["sum_rr"].tolist() == six.tolist()
+    np.testing.assert_allclose(st["msd"], ref.msd, rtol=1e-14)
+    np.testing.assert_allclose(st["D"], ref.D, rtol=1e-14)
+    np.testing.assert_allclose(st["drift"], ref.drift, rtol=1e-14)
+
+
+def test_set_occupancy_and_rate_table_paths():
+    """Caller-supplied occupancy and raw rate table give the oracle's run."""
+    say("set_occupancy / set_rate_table")
+    from paper_2004_09081_amd import fkmc as F
+    c = FRAG_CASES["ragged"]
+    lat = c.oracle()
+    rng = np.random.default_rng(4)
+    occ = np.zeros(lat.g.n_sites, np.int8)
+    idx = rng.choice(lat.g.n_sites, 80, replace=False)
+    occ[idx[:30]] = 2
+    occ[idx[30:]] = 1
+    lat.occ[:] = occ
+    lat.disp[:] = 0
+    raw = O.rate_raw(O.RateParams(T=700.0, Ea_O=0.5, Ea_H=0.45, E_z=1e8), lat.g.a_angstrom)
+    nev = 8 * min(30, O.max_domain_sites(lat.g))
+    lat.k12, _, _ = O.quantise(raw, nev)
+    g = F.LatticeSet([c.gpu_geometry()])
+    g.set_occupancy(0, occ)
+    g.set_rate_table(0, raw)
+    assert g.get_rate_table(0).tobytes() == lat.k12.tobytes()
+    t_sync = 1.0 / (8 * lat.k12[0])
+    lat.advance(t_sync, max_cycles=4)
+    g.advance([t_sync], max_cycles=4)
+    assert_same_state(g, 0, lat, "set_occupancy")
+
+
+def test_no_vacancy_and_errors():
+    say("edge cases: empty lattice, state errors")
+    from paper_2004_09081_amd import fkmc as F
+    c = Case((6, 6, 6), (3, 3, 3), nv=0, nh=10)
+    g = gpu_set([c])
+    g.advance([1e-9], max_cycles=3)
+    st = g.read_stats()[0]
+    assert st["cycles"] == 3 and st["hops"].tolist() == [0, 0]
+    # rates invalidated by init_random: advance must refuse
+    g.init_random([5], [0])
+    with pytest.raises(F.FkmcError) as e:
+        g.advance([1e-9], max_cycles=1)
+    assert e.value.code == -2
+    with pytest.raises(F.FkmcError):
+        g.set_occupancy(0, np.full(g.geoms[0].n_sites, 3, np.int8))
