@@ -124,6 +124,8 @@ typedef struct {
     double D[3];           /* tracer diffusion coefficient MSD/(6t), A^2/s */
     double drift[3][3];    /* mean velocity, Angstrom/s */
     double Dtensor[3][6];  /* (<r_a r_b> - <r_a><r_b>)/(2t), A^2/s */
+    double busy_ms;        /* persistent schedule: device time this lattice's
+                              workgroup took in the last fkmc_advance (ms) */
 } fkmc_stats;
 
 /* Required byte sizes of the occ, disp and work buffers for n lattices. */
@@ -189,6 +191,21 @@ fkmc_status fkmc_max_domain_sites(const fkmc_geometry* g, uint64_t* out);
  * t_sync may be NULL for plain-only sets (no horizon). */
 fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_cycles,
                          uint64_t min_hops);
+
+/* Scheduling of fragment lattices (results are identical under every
+ * schedule):
+ *  FKMC_SCHEDULE_LOCKSTEP: one kernel launch per phase covering every tile
+ *    of every lattice, all lattices advancing cycle by cycle together (best
+ *    for one large lattice);
+ *  FKMC_SCHEDULE_PERSISTENT: one launch per fkmc_advance call, one
+ *    workgroup of `waves` wavefronts per lattice running all its cycles,
+ *    small lattices held entirely in LDS (best for ensembles);
+ *  FKMC_SCHEDULE_AUTO (default): persistent when the set has more than one
+ *    fragment lattice.  waves in 1..8; 0 keeps the current value (default 8). */
+#define FKMC_SCHEDULE_AUTO 0
+#define FKMC_SCHEDULE_LOCKSTEP 1
+#define FKMC_SCHEDULE_PERSISTENT 2
+fkmc_status fkmc_set_schedule(fkmc_lattice* lat, int32_t schedule, int32_t waves);
 
 /* Run exactly one phase (colour c of the current cycle) on every fragment
  * lattice, without completing the cycle: the lattice is left mid-cycle, and

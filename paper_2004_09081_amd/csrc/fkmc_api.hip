@@ -180,7 +180,7 @@ fkmc_status quantise(const double raw[12], uint64_t n_ev, double out[12], double
 struct Layout {
     size_t occ_bytes, disp_bytes, work_bytes;
     std::vector<int64_t> occ_off, disp_off;
-    size_t o_desc, o_call, o_state, o_buckets, o_stat, o_counts, o_plain, o_tile2lat, o_bounds, o_c2s;
+    size_t o_desc, o_call, o_state, o_buckets, o_stat, o_counts, o_plain, o_batch, o_tile2lat, o_bounds, o_c2s;
     int32_t n_tiles;
     std::vector<std::vector<int32_t>> bounds[3];
 };
@@ -219,6 +219,7 @@ Layout plan(const fkmc_geometry* g, uint32_t n)
     Y.o_stat = take((size_t)n * 3 * kStatFields * sizeof(long long));
     Y.o_counts = take((size_t)n * 2 * sizeof(uint64_t));
     Y.o_plain = take((size_t)n * sizeof(int32_t));
+    Y.o_batch = take((size_t)n * sizeof(int32_t));
     Y.o_tile2lat = take((size_t)std::max(tiles, 1) * sizeof(int32_t));
     Y.o_bounds = take((size_t)nb * sizeof(int32_t));
     Y.o_c2s = take((size_t)nc * sizeof(int32_t));
@@ -238,8 +239,15 @@ struct fkmc_lattice {
     std::vector<LatDesc> desc;
     std::vector<int32_t> plain_ids;
     int32_t* d_plain_ids = nullptr;
+    int32_t* d_batch_ids = nullptr;
+    std::vector<int32_t> batch_ids;       // fragment lattices
     uint64_t* d_counts = nullptr;
-    int lds_per_wave = 0;
+    int lds_per_wave = 0;                 // lockstep kernel
+    int schedule = FKMC_SCHEDULE_AUTO;
+    int batch_waves = 8;
+    int lds_budget = 65536;               // persistent kernel, per workgroup
+    int batch_wave_bytes = 0;
+    int batch_slab_bytes = 0;
     std::vector<uint64_t> n_vac;
     std::vector<char> rates_ok;
     std::vector<double> t_frag;           // fragment-mode clock
@@ -386,6 +394,10 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
             D.nsb[a] = (int32_t)Y.bounds[a][i].size() - 1;
         }
         D.plain = is_plain(g) ? 1 : 0;
+        for (int a = 0; a < 3; a++) {
+            D.nf[a] = D.plain ? 1 : D.nsb[a] / 2;
+            D.F[a] = (D.plain || g.frag[a] >= g.L[a]) ? g.L[a] : g.frag[a];
+        }
         D.seed = g.seed;
         D.lattice_id = g.lattice_id;
         D.bounds_off = (int32_t)bounds.size();
@@ -405,6 +417,7 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
         if (D.plain) {
             L->plain_ids.push_back((int32_t)i);
         } else {
+            L->batch_ids.push_back((int32_t)i);
             D.tile0 = (int32_t)tile2lat.size();
             const int nf = (D.nsb[0] / 2) * (D.nsb[1] / 2) * (D.nsb[2] / 2);
             for (int f = 0; f < nf; f++) tile2lat.push_back((int32_t)i);
@@ -423,6 +436,16 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
     L->P.n_lat = (int32_t)n;
     L->P.n_tiles = Y.n_tiles;
     L->d_plain_ids = (int32_t*)(w + Y.o_plain);
+    L->d_batch_ids = (int32_t*)(w + Y.o_batch);
+    L->P.batch_ids = L->d_batch_ids;
+    L->P.lds_wave_bytes = lpw;
+    {
+        int dev = 0, smem = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            smem > 0)
+            L->lds_budget = std::min(smem, 163840) / 2;  // two workgroups per CU
+    }
     L->d_counts = (uint64_t*)(w + Y.o_counts);
 
     auto cleanup = [&](fkmc_status s) { (void)hipHostFree(L->h_state); delete L; return s; };
@@ -443,6 +466,8 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
         CREATE_OK(hipMemcpyAsync(w + Y.o_tile2lat, tile2lat.data(), tile2lat.size() * 4, hipMemcpyHostToDevice, L->stream));
     if (!L->plain_ids.empty())
         CREATE_OK(hipMemcpyAsync(L->d_plain_ids, L->plain_ids.data(), L->plain_ids.size() * 4, hipMemcpyHostToDevice, L->stream));
+    if (!L->batch_ids.empty())
+        CREATE_OK(hipMemcpyAsync(L->d_batch_ids, L->batch_ids.data(), L->batch_ids.size() * 4, hipMemcpyHostToDevice, L->stream));
     CREATE_OK(hipStreamSynchronize(L->stream));
 #undef CREATE_OK
     *out = L;
@@ -580,6 +605,7 @@ fkmc_status fkmc_get_rate_table(const fkmc_lattice* L, uint32_t i, double* k12, 
 
 static fkmc_status record_phase(fkmc_lattice* L, int colour, size_t& ev_used)
 {
+    L->P.lds_wave_bytes = L->lds_per_wave;
     if (L->timing && ev_used + 2 <= L->ev.size()) {
         HIP_OK(hipEventRecord(L->ev[ev_used], L->stream));
         LAUNCH_OK(launch_phase(L->P, colour, L->lds_per_wave, L->stream));
@@ -609,6 +635,41 @@ static fkmc_status prepare_call(fkmc_lattice* L, const double* t_sync, uint64_t 
     return FKMC_OK;
 }
 
+// Persistent-kernel plan: which lattices stay in LDS, and the LDS sizes.
+static fkmc_status plan_batch(fkmc_lattice* L)
+{
+    const int waves = L->batch_waves;
+    int fp_max = 0, slab = 0;
+    const int scratch = phase_lds_per_wave(0) - ((0 + 4 * 32 + 15) & ~15);
+    for (int32_t i : L->batch_ids) {
+        const int64_t bytes = L->desc[i].n_sites;
+        const int need_res = (int)(((bytes + 15) & ~15) + 32);
+        if (need_res + waves * scratch <= L->lds_budget && bytes < 65536 - 64) {
+            L->desc[i].resident = 1;
+            slab = std::max(slab, need_res);
+        } else {
+            L->desc[i].resident = 0;
+            fp_max = std::max<int>(fp_max, (int)max_footprint(L->geo[i]));
+        }
+    }
+    const int wave_bytes = fp_max ? phase_lds_per_wave(fp_max) : scratch;
+    if (slab + waves * wave_bytes > 163840)
+        return fail(FKMC_E_UNSUPPORTED,
+                    "persistent kernel needs %d bytes of LDS (resident slab %d, %d waves x %d; budget %d)",
+                    slab + waves * wave_bytes, slab, waves, wave_bytes, L->lds_budget);
+    L->batch_slab_bytes = slab;
+    L->batch_wave_bytes = wave_bytes;
+    return upload_desc(L);
+}
+
+static bool use_persistent(const fkmc_lattice* L)
+{
+    if (L->batch_ids.empty()) return false;
+    if (L->schedule == FKMC_SCHEDULE_LOCKSTEP) return false;
+    if (L->schedule == FKMC_SCHEDULE_PERSISTENT) return true;
+    return L->batch_ids.size() > 1;
+}
+
 fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cycles, uint64_t min_hops)
 {
     if (!L) return fail(FKMC_E_INVALID, "null handle");
@@ -618,12 +679,23 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
     if (s) return s;
     LAUNCH_OK(launch_plain(L->P, L->d_plain_ids, (int)L->plain_ids.size(), L->stream));
     size_t ev_used = 0;
-    uint64_t launched = 0;
     if (L->timing && any_frag && L->ev.empty()) {
         L->ev.resize(2 * 2048);
         for (auto& e : L->ev) HIP_OK(hipEventCreate(&e));
     }
-    if (any_frag && max_cycles > 0) {
+    if (any_frag && max_cycles > 0 && use_persistent(L)) {
+        s = plan_batch(L);
+        if (s) return s;
+        DevPtrs P = L->P;
+        P.lds_resident_bytes = L->batch_slab_bytes;
+        P.lds_wave_bytes = L->batch_wave_bytes;
+        if (L->timing) HIP_OK(hipEventRecord(L->ev[0], L->stream));
+        LAUNCH_OK(launch_batch(P, (int)L->batch_ids.size(), L->batch_waves, L->stream));
+        if (L->timing) {
+            HIP_OK(hipEventRecord(L->ev[1], L->stream));
+            ev_used = 2;
+        }
+    } else if (any_frag && max_cycles > 0) {
         LAUNCH_OK(launch_cycle_begin(L->P, L->stream));
         uint64_t batch = min_hops > 0 ? 1 : max_cycles;
         uint64_t cyc = 0;
@@ -637,7 +709,6 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
                 LAUNCH_OK(launch_cycle_end(L->P, L->stream));
             }
             cyc += nb;
-            launched += 8 * nb;
             if (cyc >= max_cycles) break;
             s = read_states(L);
             if (s) return s;
@@ -668,7 +739,18 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         L->last_launches = ev_used / 2;
         L->last_avg_ms = tot / (double)(ev_used / 2);
     }
-    (void)launched;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_set_schedule(fkmc_lattice* L, int32_t schedule, int32_t waves)
+{
+    if (!L) return fail(FKMC_E_INVALID, "null handle");
+    if (schedule < FKMC_SCHEDULE_AUTO || schedule > FKMC_SCHEDULE_PERSISTENT)
+        return fail(FKMC_E_INVALID, "unknown schedule %d", schedule);
+    if (waves != 0 && (waves < 1 || waves > 8))
+        return fail(FKMC_E_INVALID, "waves per workgroup must be 1..8");
+    L->schedule = schedule;
+    if (waves) L->batch_waves = waves;
     return FKMC_OK;
 }
 
@@ -739,6 +821,7 @@ fkmc_status fkmc_read_stats(fkmc_lattice* L, fkmc_stats* out)
         } else {
             o.t = L->t_frag[i];
             o.cycles = S.cycles;
+            o.busy_ms = (double)S.busy_ticks / 100000.0;  // 100 MHz real-time counter
             for (int b = 0; b < kHopBuckets; b++) {
                 o.hops[0] += bk[((size_t)i * kHopBuckets + b) * 2];
                 o.hops[1] += bk[((size_t)i * kHopBuckets + b) * 2 + 1];

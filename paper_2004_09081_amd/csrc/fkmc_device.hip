@@ -44,7 +44,8 @@ __device__ __forceinline__ int site_type(int X, int Y)
 // Philox4x32-10 (Salmon et al., SC'11): multipliers 0xD2511F53, 0xCD9E8D57,
 // key increments 0x9E3779B9, 0xBB67AE85.
 __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                         uint32_t k0, uint32_t k1, uint32_t out[4])
+                                         uint32_t k0, uint32_t k1, uint32_t& o0, uint32_t& o1,
+                                         uint32_t& o2, uint32_t& o3)
 {
 #pragma unroll
     for (int r = 0; r < 10; r++) {
@@ -61,10 +62,10 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
-    out[0] = c0;
-    out[1] = c1;
-    out[2] = c2;
-    out[3] = c3;
+    o0 = c0;
+    o1 = c1;
+    o2 = c2;
+    o3 = c3;
 }
 
 // Uniform in [0,1) and in (0,1] from 53 bits of a 64-bit word.
@@ -179,247 +180,429 @@ __device__ __forceinline__ int is_gb(const LatDesc& D, int t, int cell_t)
 }
 
 // ----------------------------------------------------------------------------
-// Per-wave LDS layout of the fragment phase kernel.
-struct WaveLds {
-    int* cnt;            // vacancy count
-    double* k12;         // rate table copy
-    uint16_t* raw_pos;   // unsorted slots: LDS byte position
-    uint32_t* raw_xyz;   //   local doubled coordinates
-    uint64_t* raw_key;   //   canonical site index
-    uint16_t* pos;       // sorted slots
-    uint32_t* xyz;
-    unsigned char* occ;  // footprint bytes
-};
-
-__device__ __forceinline__ WaveLds wave_lds(unsigned char* base)
+// Inclusive wavefront prefix sum of a binary64 value with DPP moves of its
+// two 32-bit halves: row_shr 1,2,4,8 inside each 16-lane row, then
+// row_bcast:15 and row_bcast:31 across rows.  The summands are exact
+// multiples of one power of two, so every association gives the same sum.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_shifted(double v)
 {
-    WaveLds w;
-    w.cnt = (int*)base;
-    w.k12 = (double*)(base + 16);
-    w.raw_key = (uint64_t*)(base + 112);
-    w.raw_xyz = (uint32_t*)(base + 112 + 8 * kMaxSlots);
-    w.xyz = (uint32_t*)(base + 112 + 12 * kMaxSlots);
-    w.raw_pos = (uint16_t*)(base + 112 + 16 * kMaxSlots);
-    w.pos = (uint16_t*)(base + 112 + 18 * kMaxSlots);
-    w.occ = base + ((112 + 20 * kMaxSlots + 15) & ~15);
-    return w;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, true);
+    return __hiloint2double(hi, lo);
 }
 
-__host__ __device__ constexpr int slot_area_bytes() { return (112 + 20 * kMaxSlots + 15) & ~15; }
+__device__ __forceinline__ double wave_scan_dpp(double v)
+{
+    v += dpp_shifted<0x111, 0xF>(v);
+    v += dpp_shifted<0x112, 0xF>(v);
+    v += dpp_shifted<0x114, 0xF>(v);
+    v += dpp_shifted<0x118, 0xF>(v);
+    v += dpp_shifted<0x142, 0xA>(v);
+    v += dpp_shifted<0x143, 0xC>(v);
+    return v;
+}
 
-// Footprint: segment 0 = brick, 1 = +x face (type 0, x = wx), 2 = +y face
-// (type 1, y = wy), 3 = +z face (type 2, z = wz).
-struct Footprint {
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// ----------------------------------------------------------------------------
+// Tile geometry.  A tile is the sub-block of fragment f with colour c; its
+// footprint is the sub-block plus the +x face (type-0 sites of the next
+// sub-block along x), the +y face (type 1) and the +z face (type 2).
+// Segment k of the footprint: 0 = brick, 1..3 = faces; local index li of
+// segment k lives at storage offset st[k] + li and at LDS byte lds[k] + li.
+struct TileGeo {
     int wx, wy, wz;
-    int ox, oy, oz;        // global cell of local (0,0,0)
-    int64_t g[4];          // absolute byte offset of local index 0 (occ buffer)
-    int len[4];
-    int lds[4];            // LDS offset of local index 0
+    int ox, oy, oz;  // global cell of local cell (0,0,0)
+    int64_t st0, st1, st2, st3;
+    int lds0, lds1, lds2, lds3;
+    int len0, len1, len2, len3;
 };
 
-// Local cell + type -> (segment, local index).
-__device__ __forceinline__ int fp_local(const Footprint& F, int lx, int ly, int lz, int t, int& li)
+// Segment accessors (selects, never a runtime-indexed local array).
+__device__ __forceinline__ int64_t seg_st(const TileGeo& G, int k)
 {
-    if (t == 0 && lx == F.wx) { li = lz * F.wy + ly; return 1; }
-    if (t == 1 && ly == F.wy) { li = lz * F.wx + lx; return 2; }
-    if (t == 2 && lz == F.wz) { li = ly * F.wx + lx; return 3; }
-    li = brick_local(t, lx, ly, lz, F.wx, F.wy, F.wz);
+    return k == 0 ? G.st0 : (k == 1 ? G.st1 : (k == 2 ? G.st2 : G.st3));
+}
+__device__ __forceinline__ int seg_lds(const TileGeo& G, int k)
+{
+    return k == 0 ? G.lds0 : (k == 1 ? G.lds1 : (k == 2 ? G.lds2 : G.lds3));
+}
+__device__ __forceinline__ int seg_len(const TileGeo& G, int k)
+{
+    return k == 0 ? G.len0 : (k == 1 ? G.len1 : (k == 2 ? G.len2 : G.len3));
+}
+
+// Sub-block b (2 per fragment) along one axis: start and width.
+__device__ __forceinline__ void axis_sub(int L, int F, int nf, int b, int& lo, int& w)
+{
+    const int fr = b >> 1;
+    const int flo = fr * F;
+    const int fhi = fr == nf - 1 ? L : flo + F;
+    const int mid = flo + ((fhi - flo + 1) >> 1);
+    if (b & 1) {
+        lo = mid;
+        w = fhi - mid;
+    } else {
+        lo = flo;
+        w = mid - flo;
+    }
+}
+
+__device__ __forceinline__ int64_t brick_base(const LatDesc& D, int x0, int y0, int z0, int wy, int wz)
+{
+    return 3 * ((int64_t)z0 * D.L[1] * D.L[0] + (int64_t)wz * ((int64_t)y0 * D.L[0] + (int64_t)wy * x0));
+}
+
+__device__ __forceinline__ TileGeo tile_geo(const LatDesc& D, int f, int colour)
+{
+    const int fx = f % D.nf[0], fy = (f / D.nf[0]) % D.nf[1], fz = f / (D.nf[0] * D.nf[1]);
+    const int bi = 2 * fx + (colour & 1), bj = 2 * fy + ((colour >> 1) & 1),
+              bk = 2 * fz + ((colour >> 2) & 1);
+    TileGeo G;
+    axis_sub(D.L[0], D.F[0], D.nf[0], bi, G.ox, G.wx);
+    axis_sub(D.L[1], D.F[1], D.nf[1], bj, G.oy, G.wy);
+    axis_sub(D.L[2], D.F[2], D.nf[2], bk, G.oz, G.wz);
+    int x1, wx1, y1, wy1, z1, wz1;
+    axis_sub(D.L[0], D.F[0], D.nf[0], bi + 1 == D.nsb[0] ? 0 : bi + 1, x1, wx1);
+    axis_sub(D.L[1], D.F[1], D.nf[1], bj + 1 == D.nsb[1] ? 0 : bj + 1, y1, wy1);
+    axis_sub(D.L[2], D.F[2], D.nf[2], bk + 1 == D.nsb[2] ? 0 : bk + 1, z1, wz1);
+    G.st0 = brick_base(D, G.ox, G.oy, G.oz, G.wy, G.wz);
+    G.st1 = brick_base(D, x1, G.oy, G.oz, G.wy, G.wz);
+    G.st2 = brick_base(D, G.ox, y1, G.oz, wy1, G.wz) + (int64_t)G.wx * wy1 * G.wz;
+    G.st3 = brick_base(D, G.ox, G.oy, z1, G.wy, wz1) + 2 * (int64_t)G.wx * G.wy * wz1;
+    G.len0 = 3 * G.wx * G.wy * G.wz;
+    G.len1 = G.wy * G.wz;
+    G.len2 = G.wz * G.wx;
+    G.len3 = G.wy * G.wx;
+    G.lds0 = G.lds1 = G.lds2 = G.lds3 = 0;
+    return G;
+}
+
+// LDS positions of the four segments in a wave's private footprint copy:
+// consecutive 16-byte-aligned runs keeping each segment's HBM alignment.
+__device__ __forceinline__ void tile_lds_private(TileGeo& G)
+{
+    int off = 0;
+    G.lds0 = off + (int)(G.st0 & 15);
+    off += ((int)(G.st0 & 15) + G.len0 + 15) & ~15;
+    G.lds1 = off + (int)(G.st1 & 15);
+    off += ((int)(G.st1 & 15) + G.len1 + 15) & ~15;
+    G.lds2 = off + (int)(G.st2 & 15);
+    off += ((int)(G.st2 & 15) + G.len2 + 15) & ~15;
+    G.lds3 = off + (int)(G.st3 & 15);
+}
+
+// LDS positions when the whole lattice sits in LDS at its storage offsets.
+__device__ __forceinline__ void tile_lds_resident(TileGeo& G)
+{
+    G.lds0 = (int)G.st0;
+    G.lds1 = (int)G.st1;
+    G.lds2 = (int)G.st2;
+    G.lds3 = (int)G.st3;
+}
+
+__device__ __forceinline__ int fp_local(const TileGeo& G, int lx, int ly, int lz, int t, int& li)
+{
+    if (t == 0 && lx == G.wx) { li = lz * G.wy + ly; return 1; }
+    if (t == 1 && ly == G.wy) { li = lz * G.wx + lx; return 2; }
+    if (t == 2 && lz == G.wz) { li = ly * G.wx + lx; return 3; }
+    li = brick_local(t, lx, ly, lz, G.wx, G.wy, G.wz);
     return 0;
 }
 
-__device__ __forceinline__ int sel4(const int* a, int k)
-{
-    return k == 0 ? a[0] : (k == 1 ? a[1] : (k == 2 ? a[2] : a[3]));
-}
-__device__ __forceinline__ int64_t sel4(const int64_t* a, int k)
-{
-    return k == 0 ? a[0] : (k == 1 ? a[1] : (k == 2 ? a[2] : a[3]));
-}
 
 __device__ __forceinline__ uint32_t pack_xyz(int X, int Y, int Z)
 {
     return (uint32_t)X | ((uint32_t)Y << 10) | ((uint32_t)Z << 20);
 }
 
-// Copy one segment HBM -> LDS in aligned 16-byte chunks and record its
-// vacancies (unsorted).
-__device__ __forceinline__ void load_segment(const Footprint& F, int k, const int8_t* occ_all,
-                                             const WaveLds& W, const LatDesc& D, int lane)
+// LDS position / storage offset of the site at packed local doubled coords.
+__device__ __forceinline__ void xyz_where(const TileGeo& G, uint32_t xyz, int& lds, int64_t& st)
 {
-    const int64_t g = F.g[k];
-    const int al = (int)(g & 15);
-    const int len = F.len[k];
-    const int nch = (al + len + 15) >> 4;
-    const uint4* src = (const uint4*)(occ_all + (g - al));
-    uint4* dst = (uint4*)(W.occ + F.lds[k] - al);
-    for (int j = lane; j < nch; j += 64) {
-        const uint4 v = src[j];
-        dst[j] = v;
-        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+    const int X = xyz & 1023, Y = (xyz >> 10) & 1023, Z = xyz >> 20;
+    int li;
+    const int k = fp_local(G, X >> 1, Y >> 1, Z >> 1, site_type(X, Y), li);
+    lds = seg_lds(G, k) + li;
+    st = seg_st(G, k) + li;
+}
+
+// ----------------------------------------------------------------------------
+// Per-wave LDS scratch: vacancy count, rate table, unsorted slots (canonical
+// key + packed coordinates), sorted slot coordinates; then, for a tile whose
+// lattice is not LDS-resident, the private footprint copy.
+struct WaveScratch {
+    int* cnt;
+    double* k12;
+    uint64_t* raw_key;
+    uint32_t* raw_xyz;
+    uint32_t* xyz;
+    unsigned char* occ;
+};
+
+__host__ __device__ constexpr int scratch_bytes() { return 112 + kMaxSlots * 16; }
+
+__device__ __forceinline__ WaveScratch wave_scratch(unsigned char* base)
+{
+    WaveScratch w;
+    w.cnt = (int*)base;
+    w.k12 = (double*)(base + 16);
+    w.raw_key = (uint64_t*)(base + 112);
+    w.raw_xyz = (uint32_t*)(base + 112 + 8 * kMaxSlots);
+    w.xyz = (uint32_t*)(base + 112 + 12 * kMaxSlots);
+    w.occ = base + scratch_bytes();
+    return w;
+}
+
+// Record vacancy found at segment k, local index li.
+__device__ __forceinline__ void add_slot(const TileGeo& G, const LatDesc& D, const WaveScratch& W,
+                                         int k, int li)
+{
+    int lx, ly, lz, t;
+    if (k == 0) {
+        const int V = G.wx * G.wy * G.wz;
+        t = li / V;
+        const int r = li - t * V;
+        if (t == 0) { ly = r % G.wy; lz = (r / G.wy) % G.wz; lx = r / (G.wy * G.wz); }
+        else if (t == 1) { lx = r % G.wx; lz = (r / G.wx) % G.wz; ly = r / (G.wx * G.wz); }
+        else { lx = r % G.wx; ly = (r / G.wx) % G.wy; lz = r / (G.wx * G.wy); }
+    } else if (k == 1) {
+        t = 0; lx = G.wx; ly = li % G.wy; lz = li / G.wy;
+    } else if (k == 2) {
+        t = 1; ly = G.wy; lx = li % G.wx; lz = li / G.wx;
+    } else {
+        t = 2; lz = G.wz; lx = li % G.wx; ly = li / G.wx;
+    }
+    int gi = G.ox + lx, gj = G.oy + ly, gk = G.oz + lz;
+    if (gi >= D.L[0]) gi -= D.L[0];
+    if (gj >= D.L[1]) gj -= D.L[1];
+    if (gk >= D.L[2]) gk -= D.L[2];
+    const uint64_t key = ((((uint64_t)gk * D.L[1] + gj) * D.L[0] + gi) * 3) + t;
+    const int slot = atomicAdd(W.cnt, 1);
+    if (slot < kMaxSlots) {
+        W.raw_xyz[slot] = pack_xyz(2 * lx + (t != 0), 2 * ly + (t != 1), 2 * lz + (t != 2));
+        W.raw_key[slot] = key;
+    }
+}
+
+// Vacancy bytes (value 2) of one 16-byte chunk of segment k.
+__device__ __forceinline__ void scan_chunk(const TileGeo& G, const LatDesc& D, const WaveScratch& W,
+                                           int k, int chunk, int al, uint4 v)
+{
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const uint32_t x = w4[q] ^ 0x02020202u;
-            if (((x - 0x01010101u) & ~x & 0x80808080u) == 0) continue;
+    for (int q = 0; q < 4; q++) {
+        const uint32_t wq = q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
+        const uint32_t x = wq ^ 0x02020202u;
+        if (((x - 0x01010101u) & ~x & 0x80808080u) == 0) continue;
 #pragma unroll
-            for (int bb = 0; bb < 4; bb++) {
-                if (((w4[q] >> (8 * bb)) & 0xff) != kSpV) continue;
-                const int li = 16 * j + 4 * q + bb - al;
-                if (li < 0 || li >= len) continue;
-                int lx, ly, lz, t;
-                if (k == 0) {
-                    const int V = F.wx * F.wy * F.wz;
-                    t = li / V;
-                    const int r = li - t * V;
-                    if (t == 0) { ly = r % F.wy; lz = (r / F.wy) % F.wz; lx = r / (F.wy * F.wz); }
-                    else if (t == 1) { lx = r % F.wx; lz = (r / F.wx) % F.wz; ly = r / (F.wx * F.wz); }
-                    else { lx = r % F.wx; ly = (r / F.wx) % F.wy; lz = r / (F.wx * F.wy); }
-                } else if (k == 1) {
-                    t = 0; lx = F.wx; ly = li % F.wy; lz = li / F.wy;
-                } else if (k == 2) {
-                    t = 1; ly = F.wy; lx = li % F.wx; lz = li / F.wx;
-                } else {
-                    t = 2; lz = F.wz; lx = li % F.wx; ly = li / F.wx;
-                }
-                const int X = 2 * lx + (t != 0), Y = 2 * ly + (t != 1), Z = 2 * lz + (t != 2);
-                int gi = F.ox + lx, gj = F.oy + ly, gk = F.oz + lz;
-                if (gi >= D.L[0]) gi -= D.L[0];
-                if (gj >= D.L[1]) gj -= D.L[1];
-                if (gk >= D.L[2]) gk -= D.L[2];
-                const uint64_t key = ((((uint64_t)gk * D.L[1] + gj) * D.L[0] + gi) * 3) + t;
-                const int slot = atomicAdd(W.cnt, 1);
-                if (slot < kMaxSlots) {
-                    W.raw_pos[slot] = (uint16_t)(F.lds[k] + li);
-                    W.raw_xyz[slot] = pack_xyz(X, Y, Z);
-                    W.raw_key[slot] = key;
-                }
-            }
+        for (int bb = 0; bb < 4; bb++) {
+            if (((wq >> (8 * bb)) & 0xff) != kSpV) continue;
+            const int li = 16 * chunk + 4 * q + bb - al;
+            if (li < 0 || li >= seg_len(G, k)) continue;
+            add_slot(G, D, W, k, li);
         }
     }
 }
 
-// Rate of event d of the vacancy at local doubled coordinates xyz (0 when
-// the edge is not owned by this tile or the target is a vacancy).  Also
-// returns the target's local doubled coordinates and LDS position.
-__device__ __forceinline__ double tile_rate(const Footprint& F, const WaveLds& W, const LatDesc& D,
-                                            uint32_t xyz, int d, int& tX, int& tY, int& tZ,
-                                            int& tpos)
+// Copy (kFromGlobal) or read in place the footprint's 16-byte chunks and
+// collect its vacancies (unsorted).  All loads of a lane are issued before
+// any of them is consumed.
+__device__ __forceinline__ void collect_slots(const TileGeo& G, const LatDesc& D, const WaveScratch& W,
+                                              const unsigned char* src, int lane, bool from_global)
+{
+    const int al0 = (int)(G.st0 & 15), al1 = (int)(G.st1 & 15), al2 = (int)(G.st2 & 15),
+              al3 = (int)(G.st3 & 15);
+    const int n0 = (al0 + G.len0 + 15) >> 4, n1 = (al1 + G.len1 + 15) >> 4,
+              n2 = (al2 + G.len2 + 15) >> 4, n3 = (al3 + G.len3 + 15) >> 4;
+    const int total = n0 + n1 + n2 + n3;
+    for (int base = 0; base < total; base += 256) {
+        uint4 v0, v1, v2, v3;
+        int k0, k1, k2, k3, c0, c1, c2, c3;
+        // locate chunk j: segment k, chunk index c within it
+        auto locate = [&](int j, int& k, int& c) {
+            k = -1;
+            c = j;
+            if (j >= total) return;
+            if (c < n0) { k = 0; return; }
+            c -= n0;
+            if (c < n1) { k = 1; return; }
+            c -= n1;
+            if (c < n2) { k = 2; return; }
+            c -= n2;
+            k = 3;
+        };
+        auto fetch = [&](int k, int c) -> uint4 {
+            const int64_t st = seg_st(G, k);
+            const int a = (int)(st & 15);
+            return *((const uint4*)(src + (st - a)) + c);
+        };
+        locate(base + lane, k0, c0);
+        locate(base + lane + 64, k1, c1);
+        locate(base + lane + 128, k2, c2);
+        locate(base + lane + 192, k3, c3);
+        if (k0 >= 0) v0 = fetch(k0, c0);
+        if (k1 >= 0) v1 = fetch(k1, c1);
+        if (k2 >= 0) v2 = fetch(k2, c2);
+        if (k3 >= 0) v3 = fetch(k3, c3);
+        auto take = [&](int k, int c, uint4 v) {
+            if (k < 0) return;
+            const int a = (int)(seg_st(G, k) & 15);
+            if (from_global) *((uint4*)(W.occ + seg_lds(G, k) - a) + c) = v;
+            scan_chunk(G, D, W, k, c, a, v);
+        };
+        take(k0, c0, v0);
+        take(k1, c1, v1);
+        take(k2, c2, v2);
+        take(k3, c3, v3);
+    }
+    (void)al1;
+    (void)al2;
+    (void)al3;
+}
+
+// Order the slots by canonical site index (keys are distinct).
+__device__ __forceinline__ void sort_slots(const WaveScratch& W, int n, int lane)
+{
+    for (int l = lane; l < n; l += 64) {
+        const uint64_t key = W.raw_key[l];
+        int rank = 0;
+        for (int j = 0; j < n; j++) rank += W.raw_key[j] < key;
+        W.xyz[rank] = W.raw_xyz[l];
+    }
+}
+
+// Rate of event d of the vacancy at packed local doubled coordinates xyz:
+// 0 when the hop edge's midpoint is outside the sub-block or the target
+// holds a vacancy; else the table entry for (ion species, z step, boundary).
+__device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned char* occl,
+                                            const double* k12, const LatDesc& D, uint32_t xyz, int d)
 {
     const int X = xyz & 1023, Y = (xyz >> 10) & 1023, Z = xyz >> 20;
     const int t = site_type(X, Y);
     int hx, hy, hz;
     hop_vec(t, d, hx, hy, hz);
     const int ox = (2 * X + hx) >> 2, oy = (2 * Y + hy) >> 2, oz = (2 * Z + hz) >> 2;
-    if (ox < 0 || ox >= F.wx || oy < 0 || oy >= F.wy || oz < 0 || oz >= F.wz) return 0.0;
-    tX = X + hx;
-    tY = Y + hy;
-    tZ = Z + hz;
+    if (ox < 0 || ox >= G.wx || oy < 0 || oy >= G.wy || oz < 0 || oz >= G.wz) return 0.0;
+    const int tX = X + hx, tY = Y + hy, tZ = Z + hz;
     const int tt = site_type(tX, tY);
     int li;
-    const int seg = fp_local(F, tX >> 1, tY >> 1, tZ >> 1, tt, li);
-    tpos = sel4(F.lds, seg) + li;
-    const int sp = W.occ[tpos];
+    const int seg = fp_local(G, tX >> 1, tY >> 1, tZ >> 1, tt, li);
+    const int sp = occl[seg_lds(G, seg) + li];
     if (sp == kSpV) return 0.0;
-    // grain-boundary flag of either end: type-a sites on planes normal to a
-    const int cs = t == 0 ? (F.ox + (X >> 1)) : (t == 1 ? (F.oy + (Y >> 1)) : (F.oz + (Z >> 1)));
-    const int ct = tt == 0 ? (F.ox + (tX >> 1)) : (tt == 1 ? (F.oy + (tY >> 1)) : (F.oz + (tZ >> 1)));
-    const int Lt = D.L[t], Ltt = D.L[tt];
-    const int g = is_gb(D, t, cs >= Lt ? cs - Lt : cs) | is_gb(D, tt, ct >= Ltt ? ct - Ltt : ct);
-    return W.k12[(sp * 3 + hz + 1) * 2 + g];
+    int g = 0;
+    if (D.gb_period > 0) {
+        int cs = t == 0 ? G.ox + (X >> 1) : (t == 1 ? G.oy + (Y >> 1) : G.oz + (Z >> 1));
+        int ct = tt == 0 ? G.ox + (tX >> 1) : (tt == 1 ? G.oy + (tY >> 1) : G.oz + (tZ >> 1));
+        if (cs >= D.L[t]) cs -= D.L[t];
+        if (ct >= D.L[tt]) ct -= D.L[tt];
+        g = is_gb(D, t, cs) | is_gb(D, tt, ct);
+    }
+    return k12[(sp * 3 + hz + 1) * 2 + g];
 }
 
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_phase(DevPtrs P, int colour, int lds_per_wave)
+__device__ __forceinline__ bool nn_site(uint32_t a, uint32_t b)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int tile = blockIdx.x * WAVES + wv;
-    if (tile >= P.n_tiles) return;
-    const int lat = P.tile2lat[tile];
-    const LatDesc& D = P.desc[lat];
-    LatState* S = P.state + lat;
-    if (S->done) return;
-    const uint64_t cycle = S->cycles;
-    const double t_sync = P.call[lat].t_sync;
-    const WaveLds W = wave_lds(smem + wv * lds_per_wave);
+    const int dx = (int)(a & 1023) - (int)(b & 1023);
+    const int dy = (int)((a >> 10) & 1023) - (int)((b >> 10) & 1023);
+    const int dz = (int)(a >> 20) - (int)(b >> 20);
+    return dx * dx + dy * dy + dz * dz == 2;
+}
 
-    // tile -> fragment -> sub-block of this colour
-    const int f = tile - D.tile0;
-    const int nfx = D.nsb[0] >> 1, nfy = D.nsb[1] >> 1;
-    const int fx = f % nfx, fy = (f / nfx) % nfy, fz = f / (nfx * nfy);
-    const int bi = 2 * fx + (colour & 1), bj = 2 * fy + ((colour >> 1) & 1),
-              bk = 2 * fz + ((colour >> 2) & 1);
-    const Brick B = brick_of(D, P.bounds, bi, bj, bk);
-    const int bin = bi + 1 == D.nsb[0] ? 0 : bi + 1;
-    const int bjn = bj + 1 == D.nsb[1] ? 0 : bj + 1;
-    const int bkn = bk + 1 == D.nsb[2] ? 0 : bk + 1;
-    const Brick BX = brick_of(D, P.bounds, bin, bj, bk);
-    const Brick BY = brick_of(D, P.bounds, bi, bjn, bk);
-    const Brick BZ = brick_of(D, P.bounds, bi, bj, bkn);
+// Packed local doubled coordinates of the target of event d from xyz.
+__device__ __forceinline__ uint32_t hop_target_xyz(uint32_t xyz, int d, int& hx, int& hy, int& hz)
+{
+    const int X = xyz & 1023, Y = (xyz >> 10) & 1023, Z = xyz >> 20;
+    hop_vec(site_type(X, Y), d, hx, hy, hz);
+    return pack_xyz(X + hx, Y + hy, Z + hz);
+}
 
-    Footprint F;
-    F.wx = B.wx; F.wy = B.wy; F.wz = B.wz;
-    F.ox = B.x0; F.oy = B.y0; F.oz = B.z0;
-    F.g[0] = D.occ_off + B.base;                                  F.len[0] = 3 * B.wx * B.wy * B.wz;
-    F.g[1] = D.occ_off + BX.base;                                 F.len[1] = B.wy * B.wz;
-    F.g[2] = D.occ_off + BY.base + (int64_t)BY.wx * BY.wy * BY.wz; F.len[2] = B.wz * B.wx;
-    F.g[3] = D.occ_off + BZ.base + 2 * (int64_t)BZ.wx * BZ.wy * BZ.wz; F.len[3] = B.wy * B.wx;
-    {
-        int off = 0;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const int al = (int)(F.g[k] & 15);
-            F.lds[k] = off + al;
-            off += (al + F.len[k] + 15) & ~15;
+// BKL on one tile (Eqs. TransitionProb, eventSelection, TimeStep) until the
+// next event would land after t_sync or no event is possible.  n sorted
+// slots in W.xyz; event e = slot*8 + direction, in that order.
+//  - n <= 8: lane e holds event e and its rate;
+//  - n <= 64: lane l holds slot l and the rates of its 8 events;
+//  - else: rates are recomputed from LDS at every step.
+// The cumulative rates are a wavefront prefix sum; after a hop only the
+// events whose vacancy moved or whose target changed are recomputed.
+// Displacement changes are kept per moved particle in lane registers
+// (origin, current site, accumulated hop) and written to HBM in two
+// wave-wide passes (all reads, then all writes) when the 64 records fill up
+// and at the end.
+__device__ __forceinline__ void tile_bkl(const TileGeo& G, const WaveScratch& W, unsigned char* occl,
+                                         const LatDesc& D, int8_t* occ_lat, int4* disp_lat,
+                                         uint32_t f, uint32_t cycle, uint32_t colour, double t_sync,
+                                         int n, int lane, uint32_t& hops_o, uint32_t& hops_h,
+                                         bool write_occ)
+{
+    bool rv = false;
+    uint32_t r_orig = 0, r_cur = 0;
+    int ax = 0, ay = 0, az = 0;
+    int nrec = 0;
+    auto flush = [&]() {
+        int4 old = make_int4(0, 0, 0, 0);
+        int lo;
+        int64_t so = 0, sf = 0;
+        if (rv) {
+            xyz_where(G, r_orig, lo, so);
+            xyz_where(G, r_cur, lo, sf);
+            old = disp_lat[so];
         }
-    }
-    if (lane == 0) *W.cnt = 0;
-    if (lane < 12) W.k12[lane] = D.k12[lane];
-    wave_lds_fence();
-#pragma unroll
-    for (int k = 0; k < 4; k++) load_segment(F, k, P.occ, W, D, lane);
-    wave_lds_fence();
-    const int n = *W.cnt;
-    if (n == 0) return;
-    if (n > kMaxSlots) {
-        if (lane == 0) atomicOr(&S->err, 1u);
-        return;
-    }
-    // order the slots by canonical site index (keys are distinct)
-    for (int l = lane; l < n; l += 64) {
-        const uint64_t key = W.raw_key[l];
-        int rank = 0;
-        for (int j = 0; j < n; j++) rank += W.raw_key[j] < key;
-        W.pos[rank] = W.raw_pos[l];
-        W.xyz[rank] = W.raw_xyz[l];
-    }
-    wave_lds_fence();
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every lane's read is done
+        __builtin_amdgcn_wave_barrier();
+        if (rv) disp_lat[sf] = make_int4(old.x + ax, old.y + ay, old.z + az, 0);
+        rv = false;
+        ax = ay = az = 0;
+        nrec = 0;
+    };
 
+    // mode 0: lane per event, 1: lane per slot (cached), 2: recompute
+    const int mode = n <= 8 ? 0 : (n <= 64 ? 1 : 2);
     const int m = (n + 63) >> 6;
     const int s0 = lane * m < n ? lane * m : n;
     const int s1 = s0 + m < n ? s0 + m : n;
-    const int64_t lat_disp = D.disp_off - D.occ_off;  // occ byte offset -> disp element
+    // mode 0 state
+    const int my_d = lane & 7;
+    const bool ev_valid = mode == 0 && (lane >> 3) < n;
+    uint32_t my_xyz = 0;
+    if (mode == 0 && ev_valid) my_xyz = W.xyz[lane >> 3];
+    if (mode == 1 && lane < n) my_xyz = W.xyz[lane];
+    double kk[8];
+#pragma unroll
+    for (int d = 0; d < 8; d++) kk[d] = 0.0;
+    double ls = 0.0;
+    auto refresh_slot = [&]() {
+        ls = 0.0;
+#pragma unroll
+        for (int d = 0; d < 8; d++) {
+            kk[d] = tile_rate(G, occl, W.k12, D, my_xyz, d);
+            ls += kk[d];
+        }
+    };
+    if (mode == 0 && ev_valid) ls = tile_rate(G, occl, W.k12, D, my_xyz, my_d);
+    if (mode == 1 && lane < n) refresh_slot();
+
     double tau = 0.0;
     uint32_t step = 0;
-    uint32_t hops_o = 0, hops_h = 0;
     for (;;) {
-        double ls = 0.0;
-        for (int s = s0; s < s1; s++) {
-            const uint32_t xyz = W.xyz[s];
-#pragma unroll
-            for (int d = 0; d < 8; d++) {
-                int a, b, c, p;
-                ls += tile_rate(F, W, D, xyz, d, a, b, c, p);
+        if (mode == 2) {
+            ls = 0.0;
+            for (int s = s0; s < s1; s++) {
+                const uint32_t xyz = W.xyz[s];
+                for (int d = 0; d < 8; d++) ls += tile_rate(G, occl, W.k12, D, xyz, d);
             }
         }
-        const double incl = wave_incl_scan(ls, lane);
-        const double R = __shfl(incl, 63, 64);
+        const double incl = wave_scan_dpp(ls);
+        const double R = lane_value(incl, 63);
         if (R == 0.0) break;
-        uint32_t x[4];
-        philox10(step, (uint32_t)f, (uint32_t)cycle, ((uint32_t)colour << 8) | 2u, D.seed,
-                 D.lattice_id, x);
-        const double u_sel = u53_lo(x[0], x[1]);
-        const double u_t = u53_hi(x[2], x[3]);
+        uint32_t x0, x1, x2, x3;
+        philox10(step, f, cycle, (colour << 8) | 2u, D.seed, D.lattice_id, x0, x1, x2, x3);
+        const double u_sel = u53_lo(x0, x1);
+        const double u_t = u53_hi(x2, x3);
         const double dt = -clock_ln(u_t) / R;
         const double tn = tau + dt;
         if (tn > t_sync) break;
@@ -431,65 +614,237 @@ __global__ __launch_bounds__(64 * WAVES) void k_phase(DevPtrs P, int colour, int
         if (mk) {
             sel = __ffsll((unsigned long long)mk) - 1;
         } else {
-            const uint64_t nz = __ballot(ls > 0.0);
-            sel = 63 - __clzll((long long)nz);
+            sel = 63 - __clzll((long long)__ballot(ls > 0.0));
             fallback = true;
         }
-        int ev = -1;
-        if (lane == sel) {
+        // pick = packed vacancy coordinates | direction << 29; slot index
+        int pick = 0, pslot = 0;
+        if (mode == 0) {
+            pick = (int)(my_xyz | ((uint32_t)my_d << 29));
+            pslot = lane >> 3;
+        } else if (lane == sel) {
             double C = incl - ls;
-            int last = -1;
-            for (int s = s0; s < s1 && ev < 0; s++) {
-                const uint32_t xyz = W.xyz[s];
+            int found = -1, last = -1;
+            if (mode == 1) {
+#pragma unroll
                 for (int d = 0; d < 8; d++) {
-                    int a, b, c, p;
-                    const double k = tile_rate(F, W, D, xyz, d, a, b, c, p);
-                    if (k > 0.0) last = s * 8 + d;
-                    C += k;
-                    if (!fallback && C > y) { ev = s * 8 + d; break; }
+                    if (kk[d] > 0.0) last = d;
+                    C += kk[d];
+                    if (!fallback && found < 0 && C > y) found = d;
                 }
+                pick = (int)(my_xyz | ((uint32_t)(found >= 0 ? found : last) << 29));
+                pslot = lane;
+            } else {
+                uint32_t lx = 0;
+                for (int s = s0; s < s1 && found < 0; s++) {
+                    const uint32_t xyz = W.xyz[s];
+                    for (int d = 0; d < 8; d++) {
+                        const double k = tile_rate(G, occl, W.k12, D, xyz, d);
+                        if (k > 0.0) { last = s * 8 + d; lx = xyz; }
+                        C += k;
+                        if (!fallback && C > y) { found = s * 8 + d; lx = xyz; break; }
+                    }
+                }
+                const int e = found >= 0 ? found : last;
+                pick = (int)(lx | ((uint32_t)(e & 7) << 29));
+                pslot = e >> 3;
             }
-            if (ev < 0) ev = last;
-            // apply: swap vacancy and ion, move displacement entries
-            const int s = ev >> 3, d = ev & 7;
-            const uint32_t xyz = W.xyz[s];
-            int tX, tY, tZ, tpos;
-            tile_rate(F, W, D, xyz, d, tX, tY, tZ, tpos);
-            const int X = xyz & 1023, Y = (xyz >> 10) & 1023, Z = xyz >> 20;
-            const int t = site_type(X, Y);
-            int hx, hy, hz;
-            hop_vec(t, d, hx, hy, hz);
-            int li_s, li_t;
-            const int seg_s = fp_local(F, X >> 1, Y >> 1, Z >> 1, t, li_s);
-            const int seg_t = fp_local(F, tX >> 1, tY >> 1, tZ >> 1, site_type(tX, tY), li_t);
-            const int spos = sel4(F.lds, seg_s) + li_s;
-            const int sp = W.occ[tpos];
-            W.occ[spos] = (unsigned char)sp;
-            W.occ[tpos] = (unsigned char)kSpV;
-            W.pos[s] = (uint16_t)tpos;
-            W.xyz[s] = pack_xyz(tX, tY, tZ);
-            const int64_t gs = sel4(F.g, seg_s) + li_s;
-            const int64_t gt = sel4(F.g, seg_t) + li_t;
-            P.occ[gs] = (int8_t)sp;
-            P.occ[gt] = (int8_t)kSpV;
-            int4* ds = P.disp + (gs + lat_disp);
-            int4* dtp = P.disp + (gt + lat_disp);
-            const int4 dv = *ds;
-            const int4 di = *dtp;
-            *dtp = make_int4(dv.x + hx, dv.y + hy, dv.z + hz, 0);
-            *ds = make_int4(di.x - hx, di.y - hy, di.z - hz, 0);
-            ev = (ev & 0xffff) | (sp << 16);
         }
-        ev = __shfl(ev, sel, 64);
-        if ((ev >> 16) == kSpO) hops_o++;
-        else hops_h++;
+        pick = __builtin_amdgcn_readlane(pick, sel);
+        pslot = __builtin_amdgcn_readlane(pslot, sel);
+        const uint32_t sx = (uint32_t)pick & 0x1FFFFFFFu;
+        const int d = (int)((uint32_t)pick >> 29);
+        int hx, hy, hz;
+        const uint32_t tx = hop_target_xyz(sx, d, hx, hy, hz);
+        int spos, tpos;
+        int64_t sst, tst;
+        xyz_where(G, sx, spos, sst);
+        xyz_where(G, tx, tpos, tst);
+        const int sp = occl[tpos];
         wave_lds_fence();
+        if (lane == 0) {
+            occl[spos] = (unsigned char)sp;
+            occl[tpos] = (unsigned char)kSpV;
+            W.xyz[pslot] = tx;
+            if (write_occ) {
+                occ_lat[sst] = (int8_t)sp;
+                occ_lat[tst] = (int8_t)kSpV;
+            }
+        }
+        // particle records: the vacancy moves sx -> tx, the ion tx -> sx
+        uint64_t mv = __ballot(rv && r_cur == sx);
+        uint64_t mi = __ballot(rv && r_cur == tx);
+        if (nrec + (mv == 0) + (mi == 0) > 64) {
+            flush();
+            mv = 0;
+            mi = 0;
+        }
+        int lv, lion;
+        if (mv) {
+            lv = __ffsll((unsigned long long)mv) - 1;
+        } else {
+            lv = nrec++;
+            if (lane == lv) { rv = true; r_orig = sx; r_cur = sx; }
+        }
+        if (mi) {
+            lion = __ffsll((unsigned long long)mi) - 1;
+        } else {
+            lion = nrec++;
+            if (lane == lion) { rv = true; r_orig = tx; r_cur = tx; }
+        }
+        if (lane == lv) { r_cur = tx; ax += hx; ay += hy; az += hz; }
+        if (lane == lion) { r_cur = sx; ax -= hx; ay -= hy; az -= hz; }
+        if (sp == kSpO) hops_o++;
+        else hops_h++;
         step++;
+        wave_lds_fence();
+        if (mode == 0) {
+            if (ev_valid) {
+                if ((lane >> 3) == pslot) my_xyz = tx;
+                int a, b, c;
+                const uint32_t tg = hop_target_xyz(my_xyz, my_d, a, b, c);
+                if ((lane >> 3) == pslot || tg == sx || tg == tx)
+                    ls = tile_rate(G, occl, W.k12, D, my_xyz, my_d);
+            }
+        } else if (mode == 1) {
+            if (lane == pslot) my_xyz = tx;
+            if (lane < n && (lane == pslot || nn_site(my_xyz, sx) || nn_site(my_xyz, tx)))
+                refresh_slot();
+        }
     }
-    if (lane == 0 && (hops_o | hops_h)) {
+    flush();
+}
+
+// ----------------------------------------------------------------------------
+// Lockstep phase kernel: one wave per tile of colour `colour`, every
+// fragment lattice of the set, footprint staged HBM -> LDS.
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_phase(DevPtrs P, int colour)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int tile = blockIdx.x * WAVES + wv;
+    if (tile >= P.n_tiles) return;
+    const int lat = P.n_lat == 1 ? 0 : P.tile2lat[tile];
+    const LatDesc& D = P.desc[lat];
+    LatState* S = P.state + lat;
+    if (S->done) return;
+    const uint32_t cycle = (uint32_t)S->cycles;
+    const double t_sync = P.call[lat].t_sync;
+    const WaveScratch W = wave_scratch(smem + wv * P.lds_wave_bytes);
+    const int f = tile - D.tile0;
+    TileGeo G = tile_geo(D, f, colour);
+    tile_lds_private(G);
+    if (lane == 0) *W.cnt = 0;
+    if (lane < 12) W.k12[lane] = D.k12[lane];
+    wave_lds_fence();
+    collect_slots(G, D, W, (const unsigned char*)(P.occ + D.occ_off), lane, true);
+    wave_lds_fence();
+    const int n = *W.cnt;
+    if (n == 0) return;
+    if (n > kMaxSlots) {
+        if (lane == 0) atomicOr(&S->err, 1u);
+        return;
+    }
+    sort_slots(W, n, lane);
+    wave_lds_fence();
+    uint32_t ho = 0, hh = 0;
+    tile_bkl(G, W, W.occ, D, P.occ + D.occ_off, P.disp + D.disp_off, (uint32_t)f, cycle,
+             (uint32_t)colour, t_sync, n, lane, ho, hh, true);
+    if (lane == 0 && (ho | hh)) {
         unsigned long long* b = P.buckets + ((size_t)lat * kHopBuckets + (f & (kHopBuckets - 1))) * 2;
-        if (hops_o) atomicAdd(b, (unsigned long long)hops_o);
-        if (hops_h) atomicAdd(b + 1, (unsigned long long)hops_h);
+        if (ho) atomicAdd(b, (unsigned long long)ho);
+        if (hh) atomicAdd(b + 1, (unsigned long long)hh);
+    }
+}
+
+// Persistent batched kernel: one workgroup per lattice runs the whole call
+// (cycles of 8 phases, workgroup barrier between phases), so every lattice
+// advances at its own pace.  A lattice that fits is kept in LDS for the
+// whole call; otherwise each wave stages its tile's footprint from HBM.
+__global__ __launch_bounds__(512) void k_batch(DevPtrs P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ unsigned long long hop_tot[2];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
+    const int lat = P.batch_ids[blockIdx.x];
+    const LatDesc& D = P.desc[lat];
+    LatState* S = P.state + lat;
+    const LatCall* C = P.call + lat;
+    const bool resident = D.resident != 0;
+    unsigned char* slab = smem;
+    const WaveScratch W = wave_scratch(smem + P.lds_resident_bytes + wv * P.lds_wave_bytes);
+    int8_t* occ_lat = P.occ + D.occ_off;
+    int4* disp_lat = P.disp + D.disp_off;
+    const int64_t nbytes = D.n_sites;
+    if (resident) {
+        const int nch = (int)((nbytes + 15) >> 4);
+        for (int j = threadIdx.x; j < nch; j += blockDim.x)
+            ((uint4*)slab)[j] = ((const uint4*)occ_lat)[j];
+    }
+    if (threadIdx.x < 2) hop_tot[threadIdx.x] = 0;
+    if (lane < 12) W.k12[lane] = D.k12[lane];
+    __syncthreads();
+    const double t_sync = C->t_sync;
+    const uint64_t max_cycles = C->max_cycles, min_hops = C->min_hops;
+    const uint64_t cycle0 = S->cycles;
+    const int ntiles = D.nf[0] * D.nf[1] * D.nf[2];
+    uint64_t ncyc = 0;
+    bool err = false;
+    while (ncyc < max_cycles) {
+        const uint32_t cycle = (uint32_t)(cycle0 + ncyc);
+        for (int colour = 0; colour < 8; colour++) {
+            uint32_t ho = 0, hh = 0;
+            for (int f = wv; f < ntiles; f += nw) {
+                TileGeo G = tile_geo(D, f, colour);
+                if (lane == 0) *W.cnt = 0;
+                wave_lds_fence();
+                if (resident) tile_lds_resident(G);
+                else tile_lds_private(G);
+                unsigned char* occl = resident ? slab : W.occ;
+                collect_slots(G, D, W, resident ? slab : (const unsigned char*)occ_lat, lane, !resident);
+                wave_lds_fence();
+                const int n = *W.cnt;
+                if (n == 0) continue;
+                if (n > kMaxSlots) {
+                    err = true;
+                    continue;
+                }
+                sort_slots(W, n, lane);
+                wave_lds_fence();
+                tile_bkl(G, W, occl, D, occ_lat, disp_lat, (uint32_t)f, cycle, (uint32_t)colour,
+                         t_sync, n, lane, ho, hh, !resident);
+            }
+            if (lane == 0 && (ho | hh)) {
+                atomicAdd(&hop_tot[0], (unsigned long long)ho);
+                atomicAdd(&hop_tot[1], (unsigned long long)hh);
+            }
+            __syncthreads();
+        }
+        ncyc++;
+        const unsigned long long tot = hop_tot[0] + hop_tot[1];
+        __syncthreads();
+        if (min_hops > 0 && tot >= min_hops) break;
+    }
+    if (resident) {
+        const int nch = (int)(nbytes >> 4);
+        for (int j = threadIdx.x; j < nch; j += blockDim.x)
+            ((uint4*)occ_lat)[j] = ((const uint4*)slab)[j];
+        for (int64_t b = (int64_t)nch * 16 + threadIdx.x; b < nbytes; b += blockDim.x)
+            occ_lat[b] = (int8_t)slab[b];
+    }
+    if (err && lane == 0) atomicOr(&S->err, 1u);
+    if (threadIdx.x == 0) {
+        S->busy_ticks = __builtin_amdgcn_s_memrealtime() - t_begin;
+        S->cycles = cycle0 + ncyc;
+        S->done = 1u;
+        unsigned long long* b = P.buckets + (size_t)lat * kHopBuckets * 2;
+        b[0] += hop_tot[0];
+        b[1] += hop_tot[1];
     }
 }
 
@@ -644,11 +999,12 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
         }
         incl += before;
         if (R == 0.0) break;
-        uint32_t x[4];
-        philox10((uint32_t)draws, (uint32_t)(draws >> 32), 0xFFFFFFFFu, 3u, D.seed, D.lattice_id, x);
+        uint32_t x0, x1, x2, x3;
+        philox10((uint32_t)draws, (uint32_t)(draws >> 32), 0xFFFFFFFFu, 3u, D.seed, D.lattice_id,
+                 x0, x1, x2, x3);
         draws++;
-        const double u_sel = u53_lo(x[0], x[1]);
-        const double u_t = u53_hi(x[2], x[3]);
+        const double u_sel = u53_lo(x0, x1);
+        const double u_t = u53_hi(x2, x3);
         const double dt = -clock_ln(u_t) / R;
         const double tn = t + dt;
         if (horizon > 0.0 && tn > t_end) {
@@ -744,10 +1100,10 @@ __global__ void k_init(DevPtrs P, const uint64_t* counts, int n_lat)
     for (uint64_t i = 0; i < nv + nh; i++) {
         const int8_t sp = i < nv ? (int8_t)kSpV : (int8_t)kSpH;
         for (;;) {
-            uint32_t x[4];
-            philox10((uint32_t)d, (uint32_t)(d >> 32), 0u, 1u, D.seed, D.lattice_id, x);
+            uint32_t x0, x1, x2, x3;
+            philox10((uint32_t)d, (uint32_t)(d >> 32), 0u, 1u, D.seed, D.lattice_id, x0, x1, x2, x3);
             d++;
-            const uint64_t w = ((uint64_t)x[0] << 32) | x[1];
+            const uint64_t w = ((uint64_t)x0 << 32) | x1;
             const uint64_t lo = w * N;
             const uint64_t j = __umul64hi(w, N);
             if (lo < thresh) continue;
@@ -854,11 +1210,22 @@ int launch_phase(const DevPtrs& P, int colour, int lds_per_wave, void* stream)
     if (4 * lds_per_wave <= kMaxLdsPerBlock) {
         const int blocks = (P.n_tiles + 3) / 4;
         hipLaunchKernelGGL(k_phase<4>, dim3(blocks), dim3(256), (size_t)lds_per_wave * 4,
-                           (hipStream_t)stream, P, colour, lds_per_wave);
+                           (hipStream_t)stream, P, colour);
     } else {
         hipLaunchKernelGGL(k_phase<1>, dim3(P.n_tiles), dim3(64), (size_t)lds_per_wave,
-                           (hipStream_t)stream, P, colour, lds_per_wave);
+                           (hipStream_t)stream, P, colour);
     }
+    return (int)hipGetLastError();
+}
+
+int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream)
+{
+    if (n_batch == 0) return 0;
+    const size_t lds = (size_t)P.lds_resident_bytes + (size_t)waves * P.lds_wave_bytes;
+    hipError_t e = hipFuncSetAttribute((const void*)k_batch,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k_batch, dim3(n_batch), dim3(64 * waves), lds, (hipStream_t)stream, P);
     return (int)hipGetLastError();
 }
 
@@ -912,7 +1279,7 @@ int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_o
 int phase_lds_per_wave(int max_footprint_bytes)
 {
     // footprint segments each padded to 16 bytes, plus alignment slack
-    return slot_area_bytes() + ((max_footprint_bytes + 4 * 32 + 15) & ~15);
+    return scratch_bytes() + ((max_footprint_bytes + 4 * 32 + 15) & ~15);
 }
 
 }  // namespace fkmc

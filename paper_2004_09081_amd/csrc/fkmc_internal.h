@@ -33,7 +33,10 @@ constexpr int kStatFields = 10;     // count, r(3), rr(6)
 struct LatDesc {
     int32_t L[3];
     int32_t nsb[3];       // sub-blocks per axis (2 per fragment; 1 in plain mode)
+    int32_t F[3];         // fragment edge (cells); last fragment takes the remainder
+    int32_t nf[3];        // fragments per axis
     int32_t plain;
+    int32_t resident;     // persistent kernel keeps the whole lattice in LDS
     uint32_t seed;
     uint32_t lattice_id;
     int32_t gb_period;
@@ -64,7 +67,8 @@ struct LatState {
     double t;             // plain-mode clock
     uint64_t draws;       // plain-mode draw counter
     uint64_t hops[2];     // plain-mode hop counters (O, H)
-    uint64_t pad[2];
+    uint64_t busy_ticks;  // persistent kernel: real-time ticks of the last call
+    uint64_t steps;       // persistent kernel: BKL draws of the last call
 };
 
 struct DevPtrs {
@@ -80,6 +84,9 @@ struct DevPtrs {
     long long* stat_acc;           // [n][3][kStatFields]
     int32_t n_lat;
     int32_t n_tiles;               // fragment-mode tiles per colour, all lattices
+    const int32_t* batch_ids;      // lattices run by the persistent kernel
+    int32_t lds_resident_bytes;    // LDS slab for a resident lattice (persistent kernel)
+    int32_t lds_wave_bytes;        // per-wave LDS scratch (footprint + slots)
 };
 
 // Kernel launchers (fkmc_device.hip).  All return a hipError_t value.
@@ -93,7 +100,9 @@ int launch_gather(const DevPtrs& P, int lat, int64_t n_sites, int8_t* d_occ_cano
                   int32_t* d_disp_canon, void* stream);
 int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_occ_canon,
                    void* stream);
-// LDS bytes one wave of the phase kernel needs for a footprint of the given size.
+int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream);
+// LDS bytes one wave needs: slot scratch, plus a footprint copy when the
+// lattice is not resident.
 int phase_lds_per_wave(int max_footprint_bytes);
 
 }  // namespace fkmc

@@ -68,7 +68,8 @@ class Stats(C.Structure):
                 ("hops", C.c_uint64 * 2), ("count", C.c_uint64 * 3),
                 ("sum_r", (C.c_int64 * 3) * 3), ("sum_rr", (C.c_int64 * 6) * 3),
                 ("msd", C.c_double * 3), ("D", C.c_double * 3),
-                ("drift", (C.c_double * 3) * 3), ("Dtensor", (C.c_double * 6) * 3)]
+                ("drift", (C.c_double * 3) * 3), ("Dtensor", (C.c_double * 6) * 3),
+                ("busy_ms", C.c_double)]
 
     def to_dict(self) -> dict:
         return {
@@ -80,6 +81,7 @@ class Stats(C.Structure):
             "msd": np.array(self.msd[:]), "D": np.array(self.D[:]),
             "drift": np.array([r[:] for r in self.drift]),
             "Dtensor": np.array([r[:] for r in self.Dtensor]),
+            "busy_ms": self.busy_ms,
         }
 
 
@@ -104,6 +106,7 @@ _SIGS = {
     "fkmc_read_state": [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t],
     "fkmc_read_stats": [C.c_void_p, _P(Stats)],
     "fkmc_set_timing": [C.c_void_p, C.c_int32],
+    "fkmc_set_schedule": [C.c_void_p, C.c_int32, C.c_int32],
     "fkmc_phase_timing": [C.c_void_p, _P(C.c_double), _P(C.c_uint64)],
     "fkmc_quantisation": [C.c_void_p, C.c_uint32, _P(C.c_double), _P(C.c_double)],
     "fkmc_last_error": [],
@@ -239,6 +242,11 @@ class LatticeSet:
 
     def sync(self):
         _check(lib().fkmc_sync(self._h))
+
+    SCHEDULES = {"auto": 0, "lockstep": 1, "persistent": 2}
+
+    def set_schedule(self, schedule: str = "auto", waves: int = 0):
+        _check(lib().fkmc_set_schedule(self._h, self.SCHEDULES[schedule], int(waves)))
 
     def set_timing(self, on: bool):
         _check(lib().fkmc_set_timing(self._h, 1 if on else 0))

@@ -35,6 +35,8 @@ FRAG_CASES = {
     "gb_all_axes": Case((12, 12, 12), (4, 4, 4), seed=6, nv=30, nh=30, T=600.0, Ea_O=0.55,
                         Ea_H=0.5, gb_period=3, gb_mask=7, gb_dE=0.05),
     "dense_vac": Case((8, 8, 8), (8, 8, 8), seed=7, nv=120, nh=40, T=600.0, Ea_H=0.5),
+    # about 80 vacancies per footprint: the slot-recompute path
+    "very_dense": Case((8, 8, 8), (8, 8, 8), seed=8, nv=500, nh=100, T=600.0, Ea_H=0.5),
 }
 
 
@@ -216,3 +218,57 @@ def test_no_vacancy_and_errors():
     assert e.value.code == -2
     with pytest.raises(F.FkmcError):
         g.set_occupancy(0, np.full(g.geoms[0].n_sites, 3, np.int8))
+
+
+SCHED_CASES = [
+    Case((30, 30, 28), (6, 6, 7), seed=21, lattice_id=0, nv=150, nh=600, T=700.0, Ea_O=0.6,
+         Ea_H=0.45),                                    # 75,600 sites: not LDS-resident
+    Case((10, 10, 10), (4, 4, 4), seed=21, lattice_id=1, nv=20, nh=30, T=650.0, Ea_O=0.55,
+         Ea_H=0.5, E_z=2e8),                            # resident, ragged fragments
+    Case((16, 16, 16), (8, 8, 8), seed=21, lattice_id=2, nv=40, nh=0, T=600.0, Ea_O=0.6,
+         gb_period=4, gb_dE=0.1),                       # resident, boundary planes
+    Case((6, 7, 5), (2, 3, 5), seed=21, lattice_id=3, nv=90, nh=20, T=600.0, Ea_H=0.5),  # > 64 slots possible
+]
+
+
+@pytest.mark.parametrize("schedule,waves", [("lockstep", 0), ("persistent", 1),
+                                            ("persistent", 4), ("persistent", 8)])
+def test_schedules_match_oracle(schedule, waves):
+    """Lockstep launches and the persistent one-workgroup-per-lattice kernel
+    (any wave count, LDS-resident or HBM-staged lattices) give the oracle's
+    trajectories bit for bit."""
+    say("schedule parity", schedule, waves)
+    lats = [c.oracle() for c in SCHED_CASES]
+    ts = [1.5 / (8.0 * l.k12[0]) for l in lats]
+    for lat, t in zip(lats, ts):
+        lat.advance(t, max_cycles=3)
+    g = gpu_set(SCHED_CASES)
+    g.set_schedule(schedule, waves)
+    g.advance(ts, max_cycles=3)
+    stats = g.read_stats()
+    for i, lat in enumerate(lats):
+        assert stats[i]["cycles"] == lat.cycles and stats[i]["t"] == lat.t
+        assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops]
+        assert_same_state(g, i, lat, "%s/%d member %d" % (schedule, waves, i))
+
+
+def test_schedule_rejects_oversized_workgroup():
+    from paper_2004_09081_amd import fkmc as F
+    g = gpu_set(SCHED_CASES[1:3])
+    with pytest.raises(F.FkmcError):
+        g.set_schedule("persistent", 16)
+
+
+def test_persistent_min_hops_rule():
+    say("persistent min_hops")
+    lats = [c.oracle() for c in SCHED_CASES[1:3]]
+    ts = [1.0 / (8.0 * l.k12[0]) for l in lats]
+    for lat, t in zip(lats, ts):
+        lat.advance(t, max_cycles=500, min_hops=300)
+    g = gpu_set(SCHED_CASES[1:3])
+    g.set_schedule("persistent", 4)
+    g.advance(ts, max_cycles=500, min_hops=300)
+    stats = g.read_stats()
+    for i, lat in enumerate(lats):
+        assert stats[i]["cycles"] == lat.cycles
+        assert_same_state(g, i, lat, "member %d" % i)
