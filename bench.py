@@ -125,7 +125,22 @@ def main():
     ap.add_argument("--frag", default="auto",
                     help="cfg4 fragment edge: cells, 'half' (ceil(L/2)) or 'auto' (autotuned per lattice)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup of the persistent kernel")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-train", type=int, default=4096)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this many MiB (reference for the "
+                         "HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib << 20
+        x = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes": n}))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -255,6 +270,14 @@ def main():
                                          "sample": "%d of %d lattices, run one at a time" % (len(idx), len(specs)),
                                          "batched_over_plain": value / plain_rate}
         log("one-lattice-per-launch: %.4g hops/s (batched/plain = %.1f)" % (plain_rate, value / plain_rate))
+
+    if args.workload == "cfg4" and not args.no_surrogate:
+        from paper_2004_09081_amd import surrogate
+        rep = surrogate.run_cfg5(n_train=args.surrogate_train, n_test=512, log=log)
+        out["surrogate"] = rep
+        log("surrogate: MAE %.4f decades on served points, served %.2f, kMC-only %.2f s vs "
+            "surrogate+fallback %.2f s" % (rep["mae_log10D"], rep["served_fraction"],
+                                           rep["time_kmc_only_s"], rep["time_surrogate_with_fallback_s"]))
 
     if not args.no_cpu_baseline:
         hops_c, tc, nl, partial = cpu_baseline(specs, args.cpu_budget, hop_target or 10**18)

@@ -155,7 +155,9 @@ fkmc_status fkmc_init_random(fkmc_lattice* lat, const uint64_t* n_vac, const uin
 fkmc_status fkmc_set_occupancy(fkmc_lattice* lat, uint32_t i, const int8_t* host, size_t n);
 
 /* Build and quantise the 12-entry rate table of every lattice from params[i]
- * (entry (X*3 + dz+1)*2 + g).  The quantum is q = 2^e with
+ * (entry (X*3 + dz+1)*2 + g).  Entries of an ion species absent from the
+ * lattice are set to zero first (hops conserve the species counts).  The
+ * quantum is q = 2^e with
  * e = ceil(log2 kmax) - 53 + ceil(log2 n_ev), n_ev = 8 min(N_V, S), S the
  * largest number of sites in one BKL domain.  FKMC_E_RANGE when a nonzero
  * rate would keep fewer than 10 significant bits. */
@@ -236,6 +238,51 @@ fkmc_status fkmc_phase_timing(const fkmc_lattice* lat, double* avg_ms, uint64_t*
 fkmc_status fkmc_quantisation(const fkmc_lattice* lat, uint32_t i, double* q, double* max_rel);
 
 const char* fkmc_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Learned surrogate: an ensemble of `members` MLPs 4 -> 128 -> 128 -> 2
+ * (SiLU) mapping (1000/T, x_H, log10 x_V, E_z / 1e7 V/m) to
+ * (log10 D_O, log10 D_H), trained on diffusion coefficients measured by the
+ * kMC engine.  Weights are used in BF16 with FP32 accumulation (MFMA on the
+ * 128x128 layer), Adam (0.9, 0.999, 1e-8) on FP32 master weights, loss =
+ * sum over outputs of the masked mean square error of standardised targets
+ * (inputs and valid targets standardised by their mean and population
+ * standard deviation over the data set).  Parameter vector of one member:
+ * W1[4][128], b1[128], W2[128][128] (input-major), b2[128], W3[128][2],
+ * b3[2]; 17410 floats.  All data pointers below are DEVICE pointers unless
+ * named host; the work buffer is caller-owned device memory (256-byte
+ * aligned).  Initialisation: He-normal weights from Philox (key seed),
+ * zero biases. */
+typedef struct fkmc_mlp fkmc_mlp;
+uint32_t fkmc_mlp_param_count(void);
+fkmc_status fkmc_mlp_query_sizes(uint32_t members, uint32_t max_samples, size_t* bytes);
+fkmc_status fkmc_mlp_create(uint32_t members, uint32_t seed, uint32_t max_samples, void* work,
+                            size_t bytes, void* hip_stream, fkmc_mlp** out);
+fkmc_status fkmc_mlp_destroy(fkmc_mlp* h);
+/* Training data: X[n][4], Y[n][2] targets, mask[n][2] (1 = valid label,
+ * 0 = ignored); computes the standardisation.  The arrays must stay valid
+ * while the handle trains on them. */
+fkmc_status fkmc_mlp_set_data(fkmc_mlp* h, const float* X, const float* Y, const float* mask,
+                              uint32_t n);
+/* `steps` Adam steps with learning rate lr; each step uses `batch` samples
+ * drawn uniformly with replacement from Philox (independent streams per
+ * member: a bootstrap per step), or the whole set in order when batch = 0.
+ * batch <= 1024.  loss_host (may be NULL) receives each member's loss of
+ * the last step. */
+fkmc_status fkmc_mlp_train(fkmc_mlp* h, uint32_t steps, uint32_t batch, float lr, float* loss_host);
+/* Loss and gradient over the whole data set at the current parameters, no
+ * update: grads_host[members][17410], loss_host[members] (may be NULL). */
+fkmc_status fkmc_mlp_grad(fkmc_mlp* h, float* grads_host, float* loss_host);
+/* Ensemble prediction for X[n][4]: mean[n][2] and population standard
+ * deviation std[n][2] across members, in de-standardised units; each
+ * (may be NULL) receives every member's output [members][n][2]. */
+fkmc_status fkmc_mlp_predict(fkmc_mlp* h, const float* X, uint32_t n, float* mean, float* stdev,
+                             float* each);
+fkmc_status fkmc_mlp_get_params(fkmc_mlp* h, float* host, size_t n);
+/* Replace all members' parameters (n = members * 17410) and reset Adam. */
+fkmc_status fkmc_mlp_set_params(fkmc_mlp* h, const float* host, size_t n);
+/* Standardisation: x mean[4], x std[4], y mean[2], y std[2]. */
+fkmc_status fkmc_mlp_get_norm(fkmc_mlp* h, float* host12);
 
 #ifdef __cplusplus
 }

@@ -136,6 +136,16 @@ def rate_raw(p: RateParams, a_angstrom: float) -> np.ndarray:
     return o
 
 
+def absent_species_zeroed(raw: np.ndarray, occ: np.ndarray) -> np.ndarray:
+    """Copy of the 12-entry table with the entries of ion species that do
+    not occur in occ set to zero (index (X*3 + dz+1)*2 + g, X = 0 O, 1 H)."""
+    out = np.array(raw, dtype=np.float64)
+    for X in (SP_O, SP_H):
+        if not (occ == X).any():
+            out[X * 6:(X + 1) * 6] = 0.0
+    return out
+
+
 def quantise(raw: np.ndarray, n_ev: int):
     raw = np.ascontiguousarray(raw, dtype=np.float64)
     o = np.zeros(12)
@@ -236,7 +246,11 @@ class Lattice:
         return d.value
 
     def set_rates(self, p: RateParams):
+        """Rate table of Eq. RateCnst1 (field and boundary terms included),
+        quantised for exact sums.  Species absent from the lattice (hops
+        conserve the counts) get zero rates, so they do not set the quantum."""
         raw = rate_raw(p, self.g.a_angstrom)
+        raw = absent_species_zeroed(raw, self.occ)
         nv = int((self.occ == SP_V).sum())
         n_ev = 8 * min(max(nv, 1), max_domain_sites(self.g))
         self.k12, self.q, self.max_rel = quantise(raw, n_ev)

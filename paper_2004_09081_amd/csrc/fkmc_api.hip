@@ -249,6 +249,7 @@ struct fkmc_lattice {
     int batch_wave_bytes = 0;
     int batch_slab_bytes = 0;
     std::vector<uint64_t> n_vac;
+    std::vector<uint64_t> n_o, n_h;       // ion counts (conserved by hops)
     std::vector<char> rates_ok;
     std::vector<double> t_frag;           // fragment-mode clock
     std::vector<uint64_t> cycles_host;    // cycles at the end of the last call
@@ -371,6 +372,9 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
     L->Y = Y;
     L->lds_per_wave = lpw;
     L->n_vac.assign(n, 0);
+    L->n_o.assign(n, 0);
+    L->n_h.assign(n, 0);
+    for (uint32_t i = 0; i < n; i++) L->n_o[i] = 3ull * geoms[i].L[0] * geoms[i].L[1] * geoms[i].L[2];
     L->rates_ok.assign(n, 0);
     L->t_frag.assign(n, 0.0);
     L->cycles_host.assign(n, 0);
@@ -507,6 +511,8 @@ fkmc_status fkmc_init_random(fkmc_lattice* L, const uint64_t* n_vac, const uint6
     HIP_OK(hipStreamSynchronize(L->stream));
     for (uint32_t i = 0; i < L->n; i++) {
         L->n_vac[i] = n_vac[i];
+        L->n_h[i] = n_h[i];
+        L->n_o[i] = (uint64_t)L->desc[i].n_sites - n_vac[i] - n_h[i];
         L->rates_ok[i] = 0;
     }
     return FKMC_OK;
@@ -518,10 +524,11 @@ fkmc_status fkmc_set_occupancy(fkmc_lattice* L, uint32_t i, const int8_t* host, 
     if (i >= L->n) return fail(FKMC_E_INVALID, "lattice index %u out of range", i);
     const size_t N = (size_t)L->desc[i].n_sites;
     if (n != N) return fail(FKMC_E_INVALID, "occupancy has %zu entries, lattice has %zu sites", n, N);
-    uint64_t nv = 0;
+    uint64_t nv = 0, nh = 0;
     for (size_t k = 0; k < N; k++) {
         if (host[k] < 0 || host[k] > 2) return fail(FKMC_E_INVALID, "species code %d at %zu", host[k], k);
         nv += host[k] == kSpV;
+        nh += host[k] == kSpH;
     }
     int8_t* tmp = nullptr;
     HIP_OK(hipMalloc((void**)&tmp, N));
@@ -535,12 +542,22 @@ fkmc_status fkmc_set_occupancy(fkmc_lattice* L, uint32_t i, const int8_t* host, 
     if (s) return s;
     HIP_OK(hipStreamSynchronize(L->stream));
     L->n_vac[i] = nv;
+    L->n_h[i] = nh;
+    L->n_o[i] = N - nv - nh;
     L->rates_ok[i] = 0;
     return FKMC_OK;
 }
 
-static fkmc_status set_table(fkmc_lattice* L, uint32_t i, const double raw[12])
+// Rates of ion species absent from the lattice are zeroed (hops conserve
+// the species counts), so they never set the quantum.
+static fkmc_status set_table(fkmc_lattice* L, uint32_t i, const double raw_in[12])
 {
+    double raw[12];
+    for (int e = 0; e < 12; e++) raw[e] = raw_in[e];
+    if (L->n_o[i] == 0)
+        for (int e = 0; e < 6; e++) raw[e] = 0.0;
+    if (L->n_h[i] == 0)
+        for (int e = 6; e < 12; e++) raw[e] = 0.0;
     const uint64_t nev = 8ull * std::min<uint64_t>(std::max<uint64_t>(L->n_vac[i], 1), domain_sites(L->geo[i]));
     double k[12], q, rel;
     fkmc_status s = quantise(raw, nev, k, &q, &rel);

@@ -723,7 +723,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_phase(DevPtrs P, int colour)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int tile = blockIdx.x * WAVES + wv;
     if (tile >= P.n_tiles) return;
     const int lat = P.n_lat == 1 ? 0 : P.tile2lat[tile];
@@ -768,7 +768,7 @@ __global__ __launch_bounds__(512) void k_batch(DevPtrs P)
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long hop_tot[2];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int nw = blockDim.x >> 6;
     const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
     const int lat = P.batch_ids[blockIdx.x];

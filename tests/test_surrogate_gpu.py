@@ -1,0 +1,104 @@
+"""Surrogate kernels (MFMA BF16 forward/backward, Adam) against the float64
+reference with the same BF16 rounding points."""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as R
+from tests.common import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_09081_amd import surrogate
+    return surrogate
+
+
+def _problem(seed, n):
+    rng = np.random.default_rng(seed)
+    X = np.stack([rng.uniform(1.1, 3.3, n), rng.uniform(0, 0.3, n), rng.uniform(-3, -2, n),
+                  rng.uniform(0, 1, n)], 1)
+    Y = np.stack([-14 - 3 * X[:, 0] + 0.5 * X[:, 1], -9 - 1.2 * X[:, 0] - 2 * X[:, 1] ** 2], 1)
+    M = np.ones((n, 2))
+    M[rng.random(n) < 0.3, 0] = 0.0
+    P = R.he_init(rng, 3)
+    return X, Y, M, P
+
+
+def _std(X, Y, M):
+    xm, xs, ym, ys = R.standardise(X, Y, M)
+    return (X - xm) / xs, np.where(M > 0, (Y - ym) / ys, 0.0), (xm, xs, ym, ys)
+
+
+def test_norm_and_forward_match_reference(S):
+    say("surrogate forward")
+    X, Y, M, P = _problem(0, 200)
+    ens = S.Ensemble(members=3, seed=1)
+    ens.set_params(P)
+    ens.set_data(X, Y, M)
+    norm = ens.get_norm()
+    Xs, Ts, (xm, xs, ym, ys) = _std(X, Y, M)
+    np.testing.assert_allclose(norm, np.concatenate([xm, xs, ym, ys]), rtol=1e-5, atol=1e-6)
+    mean, std, each = ens.predict(X, each=True)
+    refs = []
+    for m in range(3):
+        y, _ = R.forward(P[m].astype(np.float32).astype(np.float64), Xs)
+        refs.append(y * ys + ym)
+        err = np.abs(each[m] - refs[-1]) / ys
+        assert err.max() < 2e-2, err.max()
+    refs = np.stack(refs)
+    np.testing.assert_allclose(mean, refs.mean(0), atol=2e-2 * ys.max())
+    np.testing.assert_allclose(std, refs.std(0), atol=2e-2 * ys.max())
+
+
+def test_gradient_matches_reference(S):
+    say("surrogate gradient")
+    X, Y, M, P = _problem(1, 200)   # 6 full tiles of 32 and a ragged one
+    ens = S.Ensemble(members=3, seed=2)
+    ens.set_params(P)
+    ens.set_data(X, Y, M)
+    g, loss = ens.grad()
+    Xs, Ts, _ = _std(X, Y, M)
+    for m in range(3):
+        l_ref, g_ref = R.loss_and_grad(P[m].astype(np.float32).astype(np.float64), Xs, Ts, M)
+        assert abs(loss[m] - l_ref) <= 1e-3 * l_ref
+        o = 0
+        for name, shape in R.SIZES:
+            k = int(np.prod(shape))
+            a, b = g[m, o:o + k].astype(np.float64), g_ref[o:o + k]
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300)
+            assert rel < 1e-2 and cos > 0.9999, (m, name, rel, cos)
+            o += k
+
+
+def test_adam_step_matches_reference(S):
+    say("surrogate Adam step")
+    X, Y, M, P = _problem(2, 96)
+    ens = S.Ensemble(members=3, seed=3)
+    ens.set_params(P)
+    ens.set_data(X, Y, M)
+    g, _ = ens.grad()
+    ens.train(1, batch=0, lr=1e-3)
+    Q = ens.get_params()
+    for m in range(3):
+        exp, _, _ = R.adam(P[m].astype(np.float32).astype(np.float64), 0, 0, g[m].astype(np.float64), 1, 1e-3)
+        np.testing.assert_allclose(Q[m], exp, atol=2e-6)
+
+
+def test_training_fits_smooth_map(S):
+    say("surrogate training")
+    X, Y, M, _ = _problem(3, 2048)
+    ens = S.Ensemble(members=5, seed=4)
+    ens.set_data(X, Y, M)
+    loss0 = ens.train(1, batch=256, lr=1e-3)
+    loss = ens.train(3000, batch=256, lr=1e-3)
+    assert (loss < 0.02).all() and (loss < loss0).all(), (loss0, loss)
+    Xt, Yt, Mt, _ = _problem(4, 256)
+    mean, std = ens.predict(Xt)
+    err = np.abs(mean - Yt)[Mt > 0]
+    assert err.mean() < 0.05, err.mean()
