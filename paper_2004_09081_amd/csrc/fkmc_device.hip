@@ -533,7 +533,7 @@ __device__ __forceinline__ uint32_t hop_target_xyz(uint32_t xyz, int d, int& hx,
 // (origin, current site, accumulated hop) and written to HBM in two
 // wave-wide passes (all reads, then all writes) when the 64 records fill up
 // and at the end.
-__device__ __forceinline__ void tile_bkl(const TileGeo& G, const WaveScratch& W, unsigned char* occl,
+__device__ __forceinline__ void tile_bkl(const TileGeo& G_, const WaveScratch& W, unsigned char* occl,
                                          const LatDesc& D, int8_t* occ_lat, int4* disp_lat,
                                          uint32_t f, uint32_t cycle, uint32_t colour, double t_sync,
                                          int n, int lane, uint32_t& hops_o, uint32_t& hops_h,
@@ -548,8 +548,8 @@ __device__ __forceinline__ void tile_bkl(const TileGeo& G, const WaveScratch& W,
         int lo;
         int64_t so = 0, sf = 0;
         if (rv) {
-            xyz_where(G, r_orig, lo, so);
-            xyz_where(G, r_cur, lo, sf);
+            xyz_where(G_, r_orig, lo, so);
+            xyz_where(G_, r_cur, lo, sf);
             old = disp_lat[so];
         }
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every lane's read is done
@@ -560,31 +560,33 @@ __device__ __forceinline__ void tile_bkl(const TileGeo& G, const WaveScratch& W,
         nrec = 0;
     };
 
-    // mode 0: lane per event, 1: lane per slot (cached), 2: recompute
-    const int mode = n <= 8 ? 0 : (n <= 64 ? 1 : 2);
+    // mode 1: G lanes per slot (G = 8, 4, 2, 1 for n <= 8, 16, 32, 64), each
+    // caching the rates of 8/G consecutive events; mode 2: recompute.
+    const int mode = n <= 64 ? 1 : 2;
+    const int G = n <= 8 ? 8 : (n <= 16 ? 4 : (n <= 32 ? 2 : 1));
+    const int epl = 8 / G;
+    const int my_slot = lane / G;
+    const int my_d0 = (lane % G) * epl;
+    const bool ev_valid = mode == 1 && my_slot < n;
     const int m = (n + 63) >> 6;
     const int s0 = lane * m < n ? lane * m : n;
     const int s1 = s0 + m < n ? s0 + m : n;
-    // mode 0 state
-    const int my_d = lane & 7;
-    const bool ev_valid = mode == 0 && (lane >> 3) < n;
-    uint32_t my_xyz = 0;
-    if (mode == 0 && ev_valid) my_xyz = W.xyz[lane >> 3];
-    if (mode == 1 && lane < n) my_xyz = W.xyz[lane];
+    uint32_t my_xyz = ev_valid ? W.xyz[my_slot] : 0u;
     double kk[8];
 #pragma unroll
     for (int d = 0; d < 8; d++) kk[d] = 0.0;
     double ls = 0.0;
-    auto refresh_slot = [&]() {
+    auto refresh = [&]() {
         ls = 0.0;
 #pragma unroll
-        for (int d = 0; d < 8; d++) {
-            kk[d] = tile_rate(G, occl, W.k12, D, my_xyz, d);
-            ls += kk[d];
+        for (int j = 0; j < 8; j++) {
+            if (j < epl) {
+                kk[j] = tile_rate(G_, occl, W.k12, D, my_xyz, my_d0 + j);
+                ls += kk[j];
+            }
         }
     };
-    if (mode == 0 && ev_valid) ls = tile_rate(G, occl, W.k12, D, my_xyz, my_d);
-    if (mode == 1 && lane < n) refresh_slot();
+    if (ev_valid) refresh();
 
     double tau = 0.0;
     uint32_t step = 0;
@@ -593,7 +595,7 @@ __device__ __forceinline__ void tile_bkl(const TileGeo& G, const WaveScratch& W,
             ls = 0.0;
             for (int s = s0; s < s1; s++) {
                 const uint32_t xyz = W.xyz[s];
-                for (int d = 0; d < 8; d++) ls += tile_rate(G, occl, W.k12, D, xyz, d);
+                for (int d = 0; d < 8; d++) ls += tile_rate(G_, occl, W.k12, D, xyz, d);
             }
         }
         const double incl = wave_scan_dpp(ls);
@@ -619,27 +621,26 @@ __device__ __forceinline__ void tile_bkl(const TileGeo& G, const WaveScratch& W,
         }
         // pick = packed vacancy coordinates | direction << 29; slot index
         int pick = 0, pslot = 0;
-        if (mode == 0) {
-            pick = (int)(my_xyz | ((uint32_t)my_d << 29));
-            pslot = lane >> 3;
-        } else if (lane == sel) {
+        if (lane == sel) {
             double C = incl - ls;
             int found = -1, last = -1;
             if (mode == 1) {
 #pragma unroll
-                for (int d = 0; d < 8; d++) {
-                    if (kk[d] > 0.0) last = d;
-                    C += kk[d];
-                    if (!fallback && found < 0 && C > y) found = d;
+                for (int j = 0; j < 8; j++) {
+                    if (j < epl) {
+                        if (kk[j] > 0.0) last = j;
+                        C += kk[j];
+                        if (!fallback && found < 0 && C > y) found = j;
+                    }
                 }
-                pick = (int)(my_xyz | ((uint32_t)(found >= 0 ? found : last) << 29));
-                pslot = lane;
+                pick = (int)(my_xyz | ((uint32_t)(my_d0 + (found >= 0 ? found : last)) << 29));
+                pslot = my_slot;
             } else {
                 uint32_t lx = 0;
                 for (int s = s0; s < s1 && found < 0; s++) {
                     const uint32_t xyz = W.xyz[s];
                     for (int d = 0; d < 8; d++) {
-                        const double k = tile_rate(G, occl, W.k12, D, xyz, d);
+                        const double k = tile_rate(G_, occl, W.k12, D, xyz, d);
                         if (k > 0.0) { last = s * 8 + d; lx = xyz; }
                         C += k;
                         if (!fallback && C > y) { found = s * 8 + d; lx = xyz; break; }
@@ -658,8 +659,8 @@ __device__ __forceinline__ void tile_bkl(const TileGeo& G, const WaveScratch& W,
         const uint32_t tx = hop_target_xyz(sx, d, hx, hy, hz);
         int spos, tpos;
         int64_t sst, tst;
-        xyz_where(G, sx, spos, sst);
-        xyz_where(G, tx, tpos, tst);
+        xyz_where(G_, sx, spos, sst);
+        xyz_where(G_, tx, tpos, tst);
         const int sp = occl[tpos];
         wave_lds_fence();
         if (lane == 0) {
@@ -698,18 +699,9 @@ __device__ __forceinline__ void tile_bkl(const TileGeo& G, const WaveScratch& W,
         else hops_h++;
         step++;
         wave_lds_fence();
-        if (mode == 0) {
-            if (ev_valid) {
-                if ((lane >> 3) == pslot) my_xyz = tx;
-                int a, b, c;
-                const uint32_t tg = hop_target_xyz(my_xyz, my_d, a, b, c);
-                if ((lane >> 3) == pslot || tg == sx || tg == tx)
-                    ls = tile_rate(G, occl, W.k12, D, my_xyz, my_d);
-            }
-        } else if (mode == 1) {
-            if (lane == pslot) my_xyz = tx;
-            if (lane < n && (lane == pslot || nn_site(my_xyz, sx) || nn_site(my_xyz, tx)))
-                refresh_slot();
+        if (ev_valid) {
+            if (my_slot == pslot) my_xyz = tx;
+            if (my_slot == pslot || nn_site(my_xyz, sx) || nn_site(my_xyz, tx)) refresh();
         }
     }
     flush();
@@ -763,7 +755,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_phase(DevPtrs P, int colour)
 // (cycles of 8 phases, workgroup barrier between phases), so every lattice
 // advances at its own pace.  A lattice that fits is kept in LDS for the
 // whole call; otherwise each wave stages its tile's footprint from HBM.
-__global__ __launch_bounds__(512) void k_batch(DevPtrs P)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(DevPtrs P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long hop_tot[2];
