@@ -202,12 +202,19 @@ fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_c
  *  FKMC_SCHEDULE_PERSISTENT: one launch per fkmc_advance call, one
  *    workgroup of `waves` wavefronts per lattice running all its cycles,
  *    small lattices held entirely in LDS (best for ensembles);
- *  FKMC_SCHEDULE_AUTO (default): persistent when the set has more than one
- *    fragment lattice.  waves in 1..8; 0 keeps the current value (default 8). */
+ *  FKMC_SCHEDULE_AUTO (default): persistent for a set of at least 32
+ *    fragment lattices, or of several lattices of at most 49152 sites each;
+ *    lockstep otherwise.  waves in 1..8; 0 keeps the current value
+ *    (default 8). */
 #define FKMC_SCHEDULE_AUTO 0
 #define FKMC_SCHEDULE_LOCKSTEP 1
 #define FKMC_SCHEDULE_PERSISTENT 2
 fkmc_status fkmc_set_schedule(fkmc_lattice* lat, int32_t schedule, int32_t waves);
+
+/* Lockstep schedule: replay batches of 8 cycles from a prebuilt HIP graph
+ * (1, default) or enqueue every kernel separately (0).  Results are
+ * identical; event timing (fkmc_set_timing) always uses separate launches. */
+fkmc_status fkmc_set_graph(fkmc_lattice* lat, int32_t enable);
 
 /* Run exactly one phase (colour c of the current cycle) on every fragment
  * lattice, without completing the cycle: the lattice is left mid-cycle, and

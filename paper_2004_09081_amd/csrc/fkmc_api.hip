@@ -180,7 +180,7 @@ fkmc_status quantise(const double raw[12], uint64_t n_ev, double out[12], double
 struct Layout {
     size_t occ_bytes, disp_bytes, work_bytes;
     std::vector<int64_t> occ_off, disp_off;
-    size_t o_desc, o_call, o_state, o_buckets, o_stat, o_counts, o_plain, o_batch, o_tile2lat, o_bounds, o_c2s;
+    size_t o_desc, o_call, o_state, o_buckets, o_stat, o_counts, o_plain, o_batch, o_tile2lat, o_tiles, o_bounds, o_c2s;
     int32_t n_tiles;
     std::vector<std::vector<int32_t>> bounds[3];
 };
@@ -221,10 +221,57 @@ Layout plan(const fkmc_geometry* g, uint32_t n)
     Y.o_plain = take((size_t)n * sizeof(int32_t));
     Y.o_batch = take((size_t)n * sizeof(int32_t));
     Y.o_tile2lat = take((size_t)std::max(tiles, 1) * sizeof(int32_t));
+    Y.o_tiles = take((size_t)8 * std::max(tiles, 1) * sizeof(TileRec));
     Y.o_bounds = take((size_t)nb * sizeof(int32_t));
     Y.o_c2s = take((size_t)nc * sizeof(int32_t));
     Y.work_bytes = w;
     return Y;
+}
+
+// Host-built geometry of every tile of every colour, [colour][tile]: the
+// sub-block of colour c of fragment f (lower half ceil, upper half floor of
+// the fragment along each axis) and its footprint segments in the brick
+// layout.
+std::vector<TileRec> tile_records(const std::vector<LatDesc>& desc, const Layout& Y,
+                                  const std::vector<int32_t>& tile2lat)
+{
+    const size_t nt = tile2lat.size();
+    std::vector<TileRec> out(8 * nt);
+    for (size_t t = 0; t < nt; t++) {
+        const int lat = tile2lat[t];
+        const LatDesc& D = desc[lat];
+        const int f = (int)t - D.tile0;
+        const int nf0 = D.nsb[0] / 2, nf1 = D.nsb[1] / 2;
+        const int fi[3] = {f % nf0, (f / nf0) % nf1, f / (nf0 * nf1)};
+        const std::vector<int32_t>* b[3] = {&Y.bounds[0][lat], &Y.bounds[1][lat], &Y.bounds[2][lat]};
+        auto base = [&](int x0, int y0, int z0, int wy, int wz) {
+            return 3 * ((int64_t)z0 * D.L[1] * D.L[0] + (int64_t)wz * ((int64_t)y0 * D.L[0] + (int64_t)wy * x0));
+        };
+        for (int c = 0; c < 8; c++) {
+            int lo[3], w[3], lo1[3], w1[3];
+            for (int a = 0; a < 3; a++) {
+                const int sb = 2 * fi[a] + ((c >> a) & 1);
+                const int nx = sb + 1 == D.nsb[a] ? 0 : sb + 1;
+                lo[a] = (*b[a])[sb];
+                w[a] = (*b[a])[sb + 1] - lo[a];
+                lo1[a] = (*b[a])[nx];
+                w1[a] = (*b[a])[nx + 1] - lo1[a];
+            }
+            TileRec& R = out[(size_t)c * nt + t];
+            std::memset(&R, 0, sizeof R);
+            R.ox = (uint16_t)lo[0];
+            R.oy = (uint16_t)lo[1];
+            R.oz = (uint16_t)lo[2];
+            R.wx = (uint8_t)w[0];
+            R.wy = (uint8_t)w[1];
+            R.wz = (uint8_t)w[2];
+            R.st[0] = base(lo[0], lo[1], lo[2], w[1], w[2]);
+            R.st[1] = base(lo1[0], lo[1], lo[2], w[1], w[2]);
+            R.st[2] = base(lo[0], lo1[1], lo[2], w1[1], w[2]) + (int64_t)w[0] * w1[1] * w[2];
+            R.st[3] = base(lo[0], lo[1], lo1[2], w[1], w1[2]) + 2 * (int64_t)w[0] * w[1] * w1[2];
+        }
+    }
+    return out;
 }
 
 }  // namespace
@@ -260,7 +307,11 @@ struct fkmc_lattice {
     std::vector<hipEvent_t> ev;
     double last_avg_ms = 0.0;
     uint64_t last_launches = 0;
+    hipGraphExec_t graph = nullptr;       // kGraphCycles lockstep cycles
+    bool use_graph = true;
 };
+
+static constexpr int kGraphCycles = 8;
 
 namespace {
 
@@ -434,6 +485,7 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
     L->P.state = (LatState*)(w + Y.o_state);
     L->P.buckets = (unsigned long long*)(w + Y.o_buckets);
     L->P.tile2lat = (const int32_t*)(w + Y.o_tile2lat);
+    L->P.tiles = (const TileRec*)(w + Y.o_tiles);
     L->P.bounds = (const int32_t*)(w + Y.o_bounds);
     L->P.c2s = (const int32_t*)(w + Y.o_c2s);
     L->P.stat_acc = (long long*)(w + Y.o_stat);
@@ -466,8 +518,12 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
     if (!bounds.empty())
         CREATE_OK(hipMemcpyAsync(w + Y.o_bounds, bounds.data(), bounds.size() * 4, hipMemcpyHostToDevice, L->stream));
     CREATE_OK(hipMemcpyAsync(w + Y.o_c2s, c2s.data(), c2s.size() * 4, hipMemcpyHostToDevice, L->stream));
-    if (!tile2lat.empty())
+    std::vector<TileRec> recs;
+    if (!tile2lat.empty()) {
         CREATE_OK(hipMemcpyAsync(w + Y.o_tile2lat, tile2lat.data(), tile2lat.size() * 4, hipMemcpyHostToDevice, L->stream));
+        recs = tile_records(L->desc, Y, tile2lat);
+        CREATE_OK(hipMemcpyAsync(w + Y.o_tiles, recs.data(), recs.size() * sizeof(TileRec), hipMemcpyHostToDevice, L->stream));
+    }
     if (!L->plain_ids.empty())
         CREATE_OK(hipMemcpyAsync(L->d_plain_ids, L->plain_ids.data(), L->plain_ids.size() * 4, hipMemcpyHostToDevice, L->stream));
     if (!L->batch_ids.empty())
@@ -483,6 +539,7 @@ fkmc_status fkmc_destroy(fkmc_lattice* L)
     if (!L) return FKMC_OK;
     (void)hipStreamSynchronize(L->stream);
     for (auto e : L->ev) (void)hipEventDestroy(e);
+    if (L->graph) (void)hipGraphExecDestroy(L->graph);
     if (L->h_state) (void)hipHostFree(L->h_state);
     delete L;
     return FKMC_OK;
@@ -653,38 +710,75 @@ static fkmc_status prepare_call(fkmc_lattice* L, const double* t_sync, uint64_t 
 }
 
 // Persistent-kernel plan: which lattices stay in LDS, and the LDS sizes.
+// One workgroup needs slab + waves * wave_bytes, where the slab holds the
+// largest resident lattice and wave_bytes the slot scratch plus a private
+// footprint copy sized for the largest non-resident footprint.  Lattices are
+// moved out of LDS, largest first, until that fits the per-workgroup budget
+// (two workgroups per CU), so that every lattice's workgroup is resident at
+// once.
 static fkmc_status plan_batch(fkmc_lattice* L)
 {
     const int waves = L->batch_waves;
-    int fp_max = 0, slab = 0;
     const int scratch = phase_lds_per_wave(0) - ((0 + 4 * 32 + 15) & ~15);
-    for (int32_t i : L->batch_ids) {
-        const int64_t bytes = L->desc[i].n_sites;
-        const int need_res = (int)(((bytes + 15) & ~15) + 32);
-        if (need_res + waves * scratch <= L->lds_budget && bytes < 65536 - 64) {
-            L->desc[i].resident = 1;
-            slab = std::max(slab, need_res);
-        } else {
-            L->desc[i].resident = 0;
-            fp_max = std::max<int>(fp_max, (int)max_footprint(L->geo[i]));
+    std::vector<int32_t> ids = L->batch_ids;
+    std::sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
+        return L->desc[a].n_sites < L->desc[b].n_sites;
+    });
+    for (int32_t i : ids) L->desc[i].resident = 0;
+    // resident: the k smallest lattices, k as large as fits
+    int best_k = 0, best_slab = 0, best_wave = 0;
+    for (size_t k = 0; k <= ids.size(); k++) {
+        int slab = 0, fp_max = 0;
+        bool fits = true;
+        for (size_t r = 0; r < ids.size(); r++) {
+            const int32_t i = ids[r];
+            if (r < k) {
+                const int64_t need = ((L->desc[i].n_sites + 15) & ~15) + 32 +
+                                     ((4 * (int64_t)L->n_vac[i] + 15) & ~15);
+                if (need > 65536) { fits = false; break; }
+                slab = std::max<int>(slab, (int)need);
+            } else {
+                fp_max = std::max<int>(fp_max, (int)max_footprint(L->geo[i]));
+            }
         }
+        if (!fits) break;
+        const int wave_bytes = fp_max ? phase_lds_per_wave(fp_max) : scratch;
+        if (slab + waves * wave_bytes > L->lds_budget) {
+            if (k == 0) {  // even with nothing resident: allow one workgroup per CU
+                if (waves * wave_bytes > 163840)
+                    return fail(FKMC_E_UNSUPPORTED, "persistent kernel needs %d bytes of LDS",
+                                waves * wave_bytes);
+                best_k = 0;
+                best_slab = 0;
+                best_wave = wave_bytes;
+            }
+            break;
+        }
+        best_k = (int)k;
+        best_slab = slab;
+        best_wave = wave_bytes;
     }
-    const int wave_bytes = fp_max ? phase_lds_per_wave(fp_max) : scratch;
-    if (slab + waves * wave_bytes > 163840)
-        return fail(FKMC_E_UNSUPPORTED,
-                    "persistent kernel needs %d bytes of LDS (resident slab %d, %d waves x %d; budget %d)",
-                    slab + waves * wave_bytes, slab, waves, wave_bytes, L->lds_budget);
-    L->batch_slab_bytes = slab;
-    L->batch_wave_bytes = wave_bytes;
+    for (int r = 0; r < best_k; r++) L->desc[ids[r]].resident = 1;
+    for (int32_t i : ids) L->desc[i].n_vac = (int32_t)L->n_vac[i];
+    L->batch_slab_bytes = best_slab;
+    L->batch_wave_bytes = best_wave;
     return upload_desc(L);
 }
 
+// AUTO: the persistent kernel gives every lattice one workgroup, which pays
+// off for an ensemble (at least 32 lattices, or lattices small enough to sit
+// in LDS); a few large lattices are better served by lockstep launches that
+// spread every lattice's tiles over the whole GPU.
 static bool use_persistent(const fkmc_lattice* L)
 {
     if (L->batch_ids.empty()) return false;
     if (L->schedule == FKMC_SCHEDULE_LOCKSTEP) return false;
     if (L->schedule == FKMC_SCHEDULE_PERSISTENT) return true;
-    return L->batch_ids.size() > 1;
+    if (L->batch_ids.size() < 2) return false;
+    if (L->batch_ids.size() >= 32) return true;
+    for (int32_t i : L->batch_ids)
+        if (L->desc[i].n_sites > 49152) return false;
+    return true;
 }
 
 fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cycles, uint64_t min_hops)
@@ -714,16 +808,30 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         }
     } else if (any_frag && max_cycles > 0) {
         LAUNCH_OK(launch_cycle_begin(L->P, L->stream));
+        // Cycles are enqueued in batches; the device marks a lattice done once
+        // it reaches its target, after which its kernels return at once, so
+        // cycles enqueued beyond the target change nothing.  Without event
+        // timing, whole batches of cycles are replayed from a prebuilt graph.
+        const bool graph = L->use_graph && !L->timing;
+        if (graph && !L->graph) {
+            L->P.lds_wave_bytes = L->lds_per_wave;
+            LAUNCH_OK(build_cycle_graph(L->P, L->lds_per_wave, kGraphCycles, &L->graph));
+        }
         uint64_t batch = min_hops > 0 ? 1 : max_cycles;
         uint64_t cyc = 0;
         while (cyc < max_cycles) {
-            const uint64_t nb = std::min(batch, max_cycles - cyc);
-            for (uint64_t b = 0; b < nb; b++) {
-                for (int c = 0; c < 8; c++) {
-                    s = record_phase(L, c, ev_used);
-                    if (s) return s;
+            uint64_t nb = std::min(batch, max_cycles - cyc);
+            if (graph) {
+                nb = (nb + kGraphCycles - 1) / kGraphCycles * kGraphCycles;
+                for (uint64_t b = 0; b < nb; b += kGraphCycles) HIP_OK(hipGraphLaunch(L->graph, L->stream));
+            } else {
+                for (uint64_t b = 0; b < nb; b++) {
+                    for (int c = 0; c < 8; c++) {
+                        s = record_phase(L, c, ev_used);
+                        if (s) return s;
+                    }
+                    LAUNCH_OK(launch_cycle_end(L->P, L->stream));
                 }
-                LAUNCH_OK(launch_cycle_end(L->P, L->stream));
             }
             cyc += nb;
             if (cyc >= max_cycles) break;
@@ -756,6 +864,13 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         L->last_launches = ev_used / 2;
         L->last_avg_ms = tot / (double)(ev_used / 2);
     }
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_set_graph(fkmc_lattice* L, int32_t enable)
+{
+    if (!L) return fail(FKMC_E_INVALID, "null handle");
+    L->use_graph = enable != 0;
     return FKMC_OK;
 }
 

@@ -238,44 +238,19 @@ __device__ __forceinline__ int seg_len(const TileGeo& G, int k)
     return k == 0 ? G.len0 : (k == 1 ? G.len1 : (k == 2 ? G.len2 : G.len3));
 }
 
-// Sub-block b (2 per fragment) along one axis: start and width.
-__device__ __forceinline__ void axis_sub(int L, int F, int nf, int b, int& lo, int& w)
+__device__ __forceinline__ TileGeo tile_geo_rec(const TileRec& R)
 {
-    const int fr = b >> 1;
-    const int flo = fr * F;
-    const int fhi = fr == nf - 1 ? L : flo + F;
-    const int mid = flo + ((fhi - flo + 1) >> 1);
-    if (b & 1) {
-        lo = mid;
-        w = fhi - mid;
-    } else {
-        lo = flo;
-        w = mid - flo;
-    }
-}
-
-__device__ __forceinline__ int64_t brick_base(const LatDesc& D, int x0, int y0, int z0, int wy, int wz)
-{
-    return 3 * ((int64_t)z0 * D.L[1] * D.L[0] + (int64_t)wz * ((int64_t)y0 * D.L[0] + (int64_t)wy * x0));
-}
-
-__device__ __forceinline__ TileGeo tile_geo(const LatDesc& D, int f, int colour)
-{
-    const int fx = f % D.nf[0], fy = (f / D.nf[0]) % D.nf[1], fz = f / (D.nf[0] * D.nf[1]);
-    const int bi = 2 * fx + (colour & 1), bj = 2 * fy + ((colour >> 1) & 1),
-              bk = 2 * fz + ((colour >> 2) & 1);
     TileGeo G;
-    axis_sub(D.L[0], D.F[0], D.nf[0], bi, G.ox, G.wx);
-    axis_sub(D.L[1], D.F[1], D.nf[1], bj, G.oy, G.wy);
-    axis_sub(D.L[2], D.F[2], D.nf[2], bk, G.oz, G.wz);
-    int x1, wx1, y1, wy1, z1, wz1;
-    axis_sub(D.L[0], D.F[0], D.nf[0], bi + 1 == D.nsb[0] ? 0 : bi + 1, x1, wx1);
-    axis_sub(D.L[1], D.F[1], D.nf[1], bj + 1 == D.nsb[1] ? 0 : bj + 1, y1, wy1);
-    axis_sub(D.L[2], D.F[2], D.nf[2], bk + 1 == D.nsb[2] ? 0 : bk + 1, z1, wz1);
-    G.st0 = brick_base(D, G.ox, G.oy, G.oz, G.wy, G.wz);
-    G.st1 = brick_base(D, x1, G.oy, G.oz, G.wy, G.wz);
-    G.st2 = brick_base(D, G.ox, y1, G.oz, wy1, G.wz) + (int64_t)G.wx * wy1 * G.wz;
-    G.st3 = brick_base(D, G.ox, G.oy, z1, G.wy, wz1) + 2 * (int64_t)G.wx * G.wy * wz1;
+    G.wx = R.wx;
+    G.wy = R.wy;
+    G.wz = R.wz;
+    G.ox = R.ox;
+    G.oy = R.oy;
+    G.oz = R.oz;
+    G.st0 = R.st[0];
+    G.st1 = R.st[1];
+    G.st2 = R.st[2];
+    G.st3 = R.st[3];
     G.len0 = 3 * G.wx * G.wy * G.wz;
     G.len1 = G.wy * G.wz;
     G.len2 = G.wz * G.wx;
@@ -342,10 +317,12 @@ struct WaveScratch {
     uint64_t* raw_key;
     uint32_t* raw_xyz;
     uint32_t* xyz;
+    uint16_t* raw_idx;  // resident lattices: vacancy-list entry of each slot
+    uint16_t* idx;
     unsigned char* occ;
 };
 
-__host__ __device__ constexpr int scratch_bytes() { return 112 + kMaxSlots * 16; }
+__host__ __device__ constexpr int scratch_bytes() { return 112 + kMaxSlots * 20; }
 
 __device__ __forceinline__ WaveScratch wave_scratch(unsigned char* base)
 {
@@ -355,6 +332,8 @@ __device__ __forceinline__ WaveScratch wave_scratch(unsigned char* base)
     w.raw_key = (uint64_t*)(base + 112);
     w.raw_xyz = (uint32_t*)(base + 112 + 8 * kMaxSlots);
     w.xyz = (uint32_t*)(base + 112 + 12 * kMaxSlots);
+    w.raw_idx = (uint16_t*)(base + 112 + 16 * kMaxSlots);
+    w.idx = (uint16_t*)(base + 112 + 18 * kMaxSlots);
     w.occ = base + scratch_bytes();
     return w;
 }
@@ -473,6 +452,50 @@ __device__ __forceinline__ void sort_slots(const WaveScratch& W, int n, int lane
         int rank = 0;
         for (int j = 0; j < n; j++) rank += W.raw_key[j] < key;
         W.xyz[rank] = W.raw_xyz[l];
+        W.idx[rank] = W.raw_idx[l];
+    }
+}
+
+// Resident lattices keep the global position of every vacancy in an LDS
+// list (i | j << 10 | k << 20 | type << 30).  The slots of a tile are the
+// list entries inside its footprint.
+__device__ __forceinline__ void collect_from_list(const TileGeo& G, const LatDesc& D,
+                                                  const WaveScratch& W, const uint32_t* vlist,
+                                                  int nv, int lane)
+{
+    for (int v = lane; v < nv; v += 64) {
+        const uint32_t g = vlist[v];
+        const int i = g & 1023, j = (g >> 10) & 1023, k = (g >> 20) & 1023, t = g >> 30;
+        int lx = i - G.ox, ly = j - G.oy, lz = k - G.oz;
+        if (lx < 0) lx += D.L[0];
+        if (ly < 0) ly += D.L[1];
+        if (lz < 0) lz += D.L[2];
+        const bool inx = lx < G.wx, iny = ly < G.wy, inz = lz < G.wz;
+        const bool in = (inx && iny && inz) || (t == 0 && lx == G.wx && iny && inz) ||
+                        (t == 1 && ly == G.wy && inx && inz) || (t == 2 && lz == G.wz && inx && iny);
+        if (!in) continue;
+        const int slot = atomicAdd(W.cnt, 1);
+        if (slot < kMaxSlots) {
+            W.raw_key[slot] = ((((uint64_t)k * D.L[1] + j) * D.L[0] + i) * 3) + t;
+            W.raw_xyz[slot] = pack_xyz(2 * lx + (t != 0), 2 * ly + (t != 1), 2 * lz + (t != 2));
+            W.raw_idx[slot] = (uint16_t)v;
+        }
+    }
+}
+
+// Write the final positions of a tile's vacancies back to the list.
+__device__ __forceinline__ void update_list(const TileGeo& G, const LatDesc& D, const WaveScratch& W,
+                                            uint32_t* vlist, int n, int lane)
+{
+    for (int l = lane; l < n; l += 64) {
+        const uint32_t xyz = W.xyz[l];
+        const int X = xyz & 1023, Y = (xyz >> 10) & 1023, Z = xyz >> 20;
+        const int t = site_type(X, Y);
+        int i = G.ox + (X >> 1), j = G.oy + (Y >> 1), k = G.oz + (Z >> 1);
+        if (i >= D.L[0]) i -= D.L[0];
+        if (j >= D.L[1]) j -= D.L[1];
+        if (k >= D.L[2]) k -= D.L[2];
+        vlist[W.idx[l]] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20) | ((uint32_t)t << 30);
     }
 }
 
@@ -537,27 +560,33 @@ __device__ __forceinline__ void tile_bkl(const TileGeo& G_, const WaveScratch& W
                                          const LatDesc& D, int8_t* occ_lat, int4* disp_lat,
                                          uint32_t f, uint32_t cycle, uint32_t colour, double t_sync,
                                          int n, int lane, uint32_t& hops_o, uint32_t& hops_h,
-                                         bool write_occ)
+                                         bool write_occ, bool& stores_pending)
 {
     bool rv = false;
     uint32_t r_orig = 0, r_cur = 0;
     int ax = 0, ay = 0, az = 0;
+    int4 r_old = make_int4(0, 0, 0, 0);  // origin's displacement, loaded when the record opens
     int nrec = 0;
     auto flush = [&]() {
-        int4 old = make_int4(0, 0, 0, 0);
         int lo;
-        int64_t so = 0, sf = 0;
-        if (rv) {
-            xyz_where(G_, r_orig, lo, so);
-            xyz_where(G_, r_cur, lo, sf);
-            old = disp_lat[so];
-        }
+        int64_t sf = 0;
+        if (rv) xyz_where(G_, r_cur, lo, sf);
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every lane's read is done
         __builtin_amdgcn_wave_barrier();
-        if (rv) disp_lat[sf] = make_int4(old.x + ax, old.y + ay, old.z + az, 0);
+        if (rv) disp_lat[sf] = make_int4(r_old.x + ax, r_old.y + ay, r_old.z + az, 0);
+        stores_pending = true;  // waited for before the next displacement read
         rv = false;
         ax = ay = az = 0;
         nrec = 0;
+    };
+    auto open_record = [&](uint32_t xyz) {
+        int lo;
+        int64_t so;
+        rv = true;
+        r_orig = xyz;
+        r_cur = xyz;
+        xyz_where(G_, xyz, lo, so);
+        r_old = disp_lat[so];  // (pending writes of this wave were waited for above)
     };
 
     // mode 1: G lanes per slot (G = 8, 4, 2, 1 for n <= 8, 16, 32, 64), each
@@ -681,17 +710,22 @@ __device__ __forceinline__ void tile_bkl(const TileGeo& G_, const WaveScratch& W
             mi = 0;
         }
         int lv, lion;
+        if (stores_pending && (mv == 0 || mi == 0)) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            __builtin_amdgcn_wave_barrier();
+            stores_pending = false;
+        }
         if (mv) {
             lv = __ffsll((unsigned long long)mv) - 1;
         } else {
             lv = nrec++;
-            if (lane == lv) { rv = true; r_orig = sx; r_cur = sx; }
+            if (lane == lv) open_record(sx);
         }
         if (mi) {
             lion = __ffsll((unsigned long long)mi) - 1;
         } else {
             lion = nrec++;
-            if (lane == lion) { rv = true; r_orig = tx; r_cur = tx; }
+            if (lane == lion) open_record(tx);
         }
         if (lane == lv) { r_cur = tx; ax += hx; ay += hy; az += hz; }
         if (lane == lion) { r_cur = sx; ax -= hx; ay -= hy; az -= hz; }
@@ -726,7 +760,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_phase(DevPtrs P, int colour)
     const double t_sync = P.call[lat].t_sync;
     const WaveScratch W = wave_scratch(smem + wv * P.lds_wave_bytes);
     const int f = tile - D.tile0;
-    TileGeo G = tile_geo(D, f, colour);
+    TileGeo G = tile_geo_rec(P.tiles[(size_t)colour * P.n_tiles + tile]);
     tile_lds_private(G);
     if (lane == 0) *W.cnt = 0;
     if (lane < 12) W.k12[lane] = D.k12[lane];
@@ -742,8 +776,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_phase(DevPtrs P, int colour)
     sort_slots(W, n, lane);
     wave_lds_fence();
     uint32_t ho = 0, hh = 0;
+    bool pending = false;
     tile_bkl(G, W, W.occ, D, P.occ + D.occ_off, P.disp + D.disp_off, (uint32_t)f, cycle,
-             (uint32_t)colour, t_sync, n, lane, ho, hh, true);
+             (uint32_t)colour, t_sync, n, lane, ho, hh, true, pending);
     if (lane == 0 && (ho | hh)) {
         unsigned long long* b = P.buckets + ((size_t)lat * kHopBuckets + (f & (kHopBuckets - 1))) * 2;
         if (ho) atomicAdd(b, (unsigned long long)ho);
@@ -773,55 +808,94 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     int8_t* occ_lat = P.occ + D.occ_off;
     int4* disp_lat = P.disp + D.disp_off;
     const int64_t nbytes = D.n_sites;
+    __shared__ int vlist_n;
+    uint32_t* vlist = (uint32_t*)(slab + (((nbytes + 15) & ~(int64_t)15) + 32));
+    if (threadIdx.x == 0) vlist_n = 0;
     if (resident) {
         const int nch = (int)((nbytes + 15) >> 4);
         for (int j = threadIdx.x; j < nch; j += blockDim.x)
             ((uint4*)slab)[j] = ((const uint4*)occ_lat)[j];
     }
+    __syncthreads();
+    if (resident) {
+        // vacancy list, scanned in canonical order
+        for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
+            const int t = (int)(c % 3);
+            const int64_t cell = c / 3;
+            const int i = (int)(cell % D.L[0]);
+            const int j = (int)((cell / D.L[0]) % D.L[1]);
+            const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
+            if (slab[store_index(D, P.bounds, P.c2s, i, j, k, t)] != kSpV) continue;
+            const int v = atomicAdd(&vlist_n, 1);
+            if (v < D.n_vac)
+                vlist[v] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20) | ((uint32_t)t << 30);
+        }
+    }
     if (threadIdx.x < 2) hop_tot[threadIdx.x] = 0;
     if (lane < 12) W.k12[lane] = D.k12[lane];
     __syncthreads();
+    const int nv_list = vlist_n < D.n_vac ? vlist_n : D.n_vac;
+    bool err = resident && vlist_n > D.n_vac;
     const double t_sync = C->t_sync;
     const uint64_t max_cycles = C->max_cycles, min_hops = C->min_hops;
     const uint64_t cycle0 = S->cycles;
     const int ntiles = D.nf[0] * D.nf[1] * D.nf[2];
+    // A lattice with one tile per colour is run by wave 0 alone, without
+    // workgroup barriers; otherwise every phase ends with one.
+    const bool solo = ntiles == 1;
+    bool pending = false;
     uint64_t ncyc = 0;
-    bool err = false;
-    while (ncyc < max_cycles) {
-        const uint32_t cycle = (uint32_t)(cycle0 + ncyc);
-        for (int colour = 0; colour < 8; colour++) {
-            uint32_t ho = 0, hh = 0;
-            for (int f = wv; f < ntiles; f += nw) {
-                TileGeo G = tile_geo(D, f, colour);
-                if (lane == 0) *W.cnt = 0;
-                wave_lds_fence();
-                if (resident) tile_lds_resident(G);
-                else tile_lds_private(G);
-                unsigned char* occl = resident ? slab : W.occ;
-                collect_slots(G, D, W, resident ? slab : (const unsigned char*)occ_lat, lane, !resident);
-                wave_lds_fence();
-                const int n = *W.cnt;
-                if (n == 0) continue;
-                if (n > kMaxSlots) {
-                    err = true;
-                    continue;
+    if (!solo || wv == 0) {
+        while (ncyc < max_cycles) {
+            const uint32_t cycle = (uint32_t)(cycle0 + ncyc);
+            for (int colour = 0; colour < 8; colour++) {
+                uint32_t ho = 0, hh = 0;
+                for (int f = wv; f < ntiles; f += nw) {
+                    TileGeo G = tile_geo_rec(P.tiles[(size_t)colour * P.n_tiles + D.tile0 + f]);
+                    if (lane == 0) *W.cnt = 0;
+                    wave_lds_fence();
+                    unsigned char* occl = resident ? slab : W.occ;
+                    if (resident) {
+                        tile_lds_resident(G);
+                        collect_from_list(G, D, W, vlist, nv_list, lane);
+                    } else {
+                        tile_lds_private(G);
+                        collect_slots(G, D, W, (const unsigned char*)occ_lat, lane, true);
+                    }
+                    wave_lds_fence();
+                    const int n = *W.cnt;
+                    if (n == 0) continue;
+                    if (n > kMaxSlots) {
+                        err = true;
+                        continue;
+                    }
+                    sort_slots(W, n, lane);
+                    wave_lds_fence();
+                    tile_bkl(G, W, occl, D, occ_lat, disp_lat, (uint32_t)f, cycle, (uint32_t)colour,
+                             t_sync, n, lane, ho, hh, !resident, pending);
+                    if (resident) {
+                        wave_lds_fence();
+                        update_list(G, D, W, vlist, n, lane);
+                    }
                 }
-                sort_slots(W, n, lane);
-                wave_lds_fence();
-                tile_bkl(G, W, occl, D, occ_lat, disp_lat, (uint32_t)f, cycle, (uint32_t)colour,
-                         t_sync, n, lane, ho, hh, !resident);
+                if (lane == 0 && (ho | hh)) {
+                    atomicAdd(&hop_tot[0], (unsigned long long)ho);
+                    atomicAdd(&hop_tot[1], (unsigned long long)hh);
+                }
+                if (solo) {
+                    wave_lds_fence();
+                } else {
+                    __syncthreads();
+                    pending = false;  // the barrier waited for every store
+                }
             }
-            if (lane == 0 && (ho | hh)) {
-                atomicAdd(&hop_tot[0], (unsigned long long)ho);
-                atomicAdd(&hop_tot[1], (unsigned long long)hh);
-            }
-            __syncthreads();
+            ncyc++;
+            const unsigned long long tot = hop_tot[0] + hop_tot[1];
+            if (!solo) __syncthreads();
+            if (min_hops > 0 && tot >= min_hops) break;
         }
-        ncyc++;
-        const unsigned long long tot = hop_tot[0] + hop_tot[1];
-        __syncthreads();
-        if (min_hops > 0 && tot >= min_hops) break;
     }
+    __syncthreads();
     if (resident) {
         const int nch = (int)(nbytes >> 4);
         for (int j = threadIdx.x; j < nch; j += blockDim.x)
@@ -1219,6 +1293,50 @@ int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream)
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(k_batch, dim3(n_batch), dim3(64 * waves), lds, (hipStream_t)stream, P);
     return (int)hipGetLastError();
+}
+
+// A graph of `cycles` consecutive lockstep cycles (8 phase kernels and the
+// cycle-end kernel each, chained), built from kernel nodes so that it can be
+// launched on any stream.  Holds no memset or copy nodes.
+int build_cycle_graph(const DevPtrs& P, int lds_per_wave, int cycles, hipGraphExec_t* out)
+{
+    hipGraph_t g;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return (int)e;
+    DevPtrs args_p = P;  // argument values are copied into each node
+    hipGraphNode_t prev = nullptr;
+    const bool four = 4 * lds_per_wave <= kMaxLdsPerBlock;
+    int colours[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+    int begin0 = 0;
+    for (int c = 0; c < cycles && e == hipSuccess; c++) {
+        for (int col = 0; col < 9 && e == hipSuccess; col++) {
+            hipKernelNodeParams kp = {};
+            void* argv[3];
+            if (col < 8) {
+                argv[0] = &args_p;
+                argv[1] = &colours[col];
+                kp.func = four ? (void*)k_phase<4> : (void*)k_phase<1>;
+                kp.gridDim = four ? dim3((P.n_tiles + 3) / 4) : dim3(P.n_tiles);
+                kp.blockDim = four ? dim3(256) : dim3(64);
+                kp.sharedMemBytes = (unsigned)(lds_per_wave * (four ? 4 : 1));
+            } else {
+                argv[0] = &args_p;
+                argv[1] = &begin0;
+                kp.func = (void*)k_cycle;
+                kp.gridDim = dim3(P.n_lat);
+                kp.blockDim = dim3(64);
+                kp.sharedMemBytes = 0;
+            }
+            kp.kernelParams = argv;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+            prev = node;
+        }
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return (int)e;
 }
 
 int launch_cycle_end(const DevPtrs& P, void* stream)

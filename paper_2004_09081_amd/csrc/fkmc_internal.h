@@ -37,6 +37,8 @@ struct LatDesc {
     int32_t nf[3];        // fragments per axis
     int32_t plain;
     int32_t resident;     // persistent kernel keeps the whole lattice in LDS
+    int32_t n_vac;        // vacancies (conserved), sizes the resident vacancy list
+    int32_t pad0;
     uint32_t seed;
     uint32_t lattice_id;
     int32_t gb_period;
@@ -71,6 +73,16 @@ struct LatState {
     uint64_t steps;       // persistent kernel: BKL draws of the last call
 };
 
+// Geometry of one tile (sub-block of one colour of one fragment), built on
+// the host: origin and width per axis, and the storage offsets of the four
+// footprint segments (brick, +x face, +y face, +z face).
+struct TileRec {
+    int64_t st[4];
+    uint16_t ox, oy, oz;
+    uint8_t wx, wy, wz, pad;
+    uint32_t pad2;
+};
+
 struct DevPtrs {
     int8_t* occ;
     int4* disp;
@@ -79,6 +91,7 @@ struct DevPtrs {
     LatState* state;
     unsigned long long* buckets;   // [n][kHopBuckets][2]
     const int32_t* tile2lat;       // [n_tiles]
+    const TileRec* tiles;          // [8][n_tiles]
     const int32_t* bounds;
     const int32_t* c2s;
     long long* stat_acc;           // [n][3][kStatFields]
@@ -101,6 +114,7 @@ int launch_gather(const DevPtrs& P, int lat, int64_t n_sites, int8_t* d_occ_cano
 int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_occ_canon,
                    void* stream);
 int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream);
+int build_cycle_graph(const DevPtrs& P, int lds_per_wave, int cycles, hipGraphExec_t* out);
 // LDS bytes one wave needs: slot scratch, plus a footprint copy when the
 // lattice is not resident.
 int phase_lds_per_wave(int max_footprint_bytes);

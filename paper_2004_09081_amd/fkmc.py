@@ -107,6 +107,7 @@ _SIGS = {
     "fkmc_read_stats": [C.c_void_p, _P(Stats)],
     "fkmc_set_timing": [C.c_void_p, C.c_int32],
     "fkmc_set_schedule": [C.c_void_p, C.c_int32, C.c_int32],
+    "fkmc_set_graph": [C.c_void_p, C.c_int32],
     "fkmc_phase_timing": [C.c_void_p, _P(C.c_double), _P(C.c_uint64)],
     "fkmc_quantisation": [C.c_void_p, C.c_uint32, _P(C.c_double), _P(C.c_double)],
     "fkmc_last_error": [],
@@ -247,6 +248,9 @@ class LatticeSet:
 
     def set_schedule(self, schedule: str = "auto", waves: int = 0):
         _check(lib().fkmc_set_schedule(self._h, self.SCHEDULES[schedule], int(waves)))
+
+    def set_graph(self, on: bool):
+        _check(lib().fkmc_set_graph(self._h, 1 if on else 0))
 
     def set_timing(self, on: bool):
         _check(lib().fkmc_set_timing(self._h, 1 if on else 0))

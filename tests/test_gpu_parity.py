@@ -272,3 +272,26 @@ def test_persistent_min_hops_rule():
     for i, lat in enumerate(lats):
         assert stats[i]["cycles"] == lat.cycles
         assert_same_state(g, i, lat, "member %d" % i)
+
+
+def test_graph_replays_match_eager_and_oracle():
+    """Lockstep cycles replayed from the HIP graph, several calls in a row
+    with reads and eager work between them, equal the separately launched
+    path and the oracle at every call (including max_cycles that is not a
+    multiple of the graph's 8 cycles, and a hop target)."""
+    say("graph replays")
+    c = FRAG_CASES["ragged"]
+    lat = c.oracle()
+    t_sync = 1.5 / (8.0 * lat.k12[0])
+    g = gpu_set([c])
+    e = gpu_set([c])
+    e.set_graph(False)
+    for rep, (mc, mh) in enumerate([(3, 0), (11, 0), (1000, 400), (5, 0)]):
+        lat.advance(t_sync, max_cycles=mc, min_hops=mh)
+        g.advance([t_sync], max_cycles=mc, min_hops=mh)
+        e.advance([t_sync], max_cycles=mc, min_hops=mh)
+        sg, se = g.read_stats()[0], e.read_stats()[0]
+        assert sg["cycles"] == se["cycles"] == lat.cycles, (rep, sg["cycles"], se["cycles"], lat.cycles)
+        assert sg["t"] == lat.t and sg["hops"].tolist() == [int(x) for x in lat.hops]
+        assert_same_state(g, 0, lat, "graph call %d" % rep)
+        assert_same_state(e, 0, lat, "eager call %d" % rep)
