@@ -232,6 +232,16 @@ fkmc_status fkmc_read_state(fkmc_lattice* lat, uint32_t i, int8_t* occ, int32_t*
 /* Statistics of every lattice (out[n]); synchronises. */
 fkmc_status fkmc_read_stats(fkmc_lattice* lat, fkmc_stats* out);
 
+/* Checkpoint of lattice i into a host buffer of fkmc_checkpoint_size()
+ * bytes: geometry and key, canonical occupancy and displacements, clock,
+ * cycle and draw counters, hop counters and the quantised rate table.
+ * Synchronises.  fkmc_restore() puts it back into lattice i of a handle with
+ * the same geometry and key; the run then continues exactly as the original
+ * would (the random numbers are indexed by the counters, not by a state). */
+fkmc_status fkmc_checkpoint_size(const fkmc_lattice* lat, uint32_t i, size_t* bytes);
+fkmc_status fkmc_checkpoint(fkmc_lattice* lat, uint32_t i, void* host, size_t bytes);
+fkmc_status fkmc_restore(fkmc_lattice* lat, uint32_t i, const void* host, size_t bytes);
+
 /* Enable (1) or disable (0) HIP-event timing of each phase launch of the
  * following fkmc_advance calls (at most 2048 launches per call are timed). */
 fkmc_status fkmc_set_timing(fkmc_lattice* lat, int32_t enable);

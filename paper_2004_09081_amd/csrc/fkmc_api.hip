@@ -867,6 +867,120 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
     return FKMC_OK;
 }
 
+// Checkpoint layout (all little-endian, host byte order): header, then the
+// canonical occupancy (N int8) and displacements (3N int32).
+struct CkptHeader {
+    char magic[8];       // "FKMCCKP1"
+    int32_t L[3], frag[3];
+    double a_angstrom;
+    uint32_t seed, lattice_id;
+    int64_t n_sites;
+    uint64_t cycles, draws, hops[2], n_vac, n_h;
+    double t;
+    double k12[12];
+    int32_t gb_period, gb_mask;
+    int32_t rates_ok, pad;
+};
+
+fkmc_status fkmc_checkpoint_size(const fkmc_lattice* L, uint32_t i, size_t* bytes)
+{
+    if (!L || !bytes || i >= L->n) return fail(FKMC_E_INVALID, "bad argument");
+    *bytes = sizeof(CkptHeader) + (size_t)L->desc[i].n_sites * 13;
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_checkpoint(fkmc_lattice* L, uint32_t i, void* host, size_t bytes)
+{
+    size_t need = 0;
+    fkmc_status s = fkmc_checkpoint_size(L, i, &need);
+    if (s) return s;
+    if (!host || bytes < need) return fail(FKMC_E_INVALID, "checkpoint buffer too small (%zu < %zu)", bytes, need);
+    std::vector<fkmc_stats> st(L->n);
+    s = fkmc_read_stats(L, st.data());
+    if (s) return s;
+    CkptHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, "FKMCCKP1", 8);
+    for (int a = 0; a < 3; a++) {
+        h.L[a] = L->geo[i].L[a];
+        h.frag[a] = L->geo[i].frag[a];
+    }
+    h.a_angstrom = L->geo[i].a_angstrom;
+    h.seed = L->geo[i].seed;
+    h.lattice_id = L->geo[i].lattice_id;
+    h.n_sites = L->desc[i].n_sites;
+    h.cycles = st[i].cycles;
+    h.draws = st[i].draws;
+    h.hops[0] = st[i].hops[0];
+    h.hops[1] = st[i].hops[1];
+    h.n_vac = L->n_vac[i];
+    h.n_h = L->n_h[i];
+    h.t = st[i].t;
+    std::memcpy(h.k12, L->desc[i].k12, sizeof h.k12);
+    h.gb_period = L->desc[i].gb_period;
+    h.gb_mask = L->desc[i].gb_mask;
+    h.rates_ok = L->rates_ok[i];
+    char* out = (char*)host;
+    std::memcpy(out, &h, sizeof h);
+    const size_t N = (size_t)h.n_sites;
+    return fkmc_read_state(L, i, (int8_t*)(out + sizeof h), (int32_t*)(out + sizeof h + N), N);
+}
+
+// Restore lattice i (same geometry) from a checkpoint: state, clock,
+// counters and rate table; the continuation is identical to the original run.
+fkmc_status fkmc_restore(fkmc_lattice* L, uint32_t i, const void* host, size_t bytes)
+{
+    if (!L || !host || i >= L->n) return fail(FKMC_E_INVALID, "bad argument");
+    if (bytes < sizeof(CkptHeader)) return fail(FKMC_E_INVALID, "checkpoint too short");
+    CkptHeader h;
+    std::memcpy(&h, host, sizeof h);
+    if (std::memcmp(h.magic, "FKMCCKP1", 8) != 0) return fail(FKMC_E_INVALID, "not a checkpoint");
+    const fkmc_geometry& g = L->geo[i];
+    for (int a = 0; a < 3; a++)
+        if (h.L[a] != g.L[a] || h.frag[a] != g.frag[a]) return fail(FKMC_E_INVALID, "geometry differs");
+    if (h.seed != g.seed || h.lattice_id != g.lattice_id || h.a_angstrom != g.a_angstrom)
+        return fail(FKMC_E_INVALID, "key or lattice constant differs");
+    const size_t N = (size_t)L->desc[i].n_sites;
+    if (bytes < sizeof h + N * 13) return fail(FKMC_E_INVALID, "checkpoint too short");
+    const char* in = (const char*)host;
+    const int8_t* occ = (const int8_t*)(in + sizeof h);
+    std::vector<int32_t> disp((size_t)N * 3);
+    std::memcpy(disp.data(), in + sizeof h + N, N * 12);
+    fkmc_status s = fkmc_set_occupancy(L, i, occ, N);
+    if (s) return s;
+    // displacements: canonical int32x3 -> storage int4 via a device gather of the copy
+    int32_t* d_disp = nullptr;
+    HIP_OK(hipMalloc((void**)&d_disp, N * 12));
+    hipError_t e1 = hipMemcpyAsync(d_disp, disp.data(), N * 12, hipMemcpyHostToDevice, L->stream);
+    int le = e1 == hipSuccess ? launch_scatter_disp(L->P, (int)i, (int64_t)N, d_disp, L->stream) : 0;
+    hipError_t e2 = hipStreamSynchronize(L->stream);
+    (void)hipFree(d_disp);
+    if (e1 != hipSuccess || le != 0 || e2 != hipSuccess) return fail(FKMC_E_DEVICE, "restore copy failed");
+    // clock and counters
+    LatState st;
+    std::memset(&st, 0, sizeof st);
+    st.cycles = h.cycles;
+    st.draws = h.draws;
+    st.t = L->desc[i].plain ? h.t : 0.0;
+    st.hops[0] = h.hops[0];
+    st.hops[1] = h.hops[1];
+    HIP_OK(hipMemcpyAsync((char*)L->buf.work + L->Y.o_state + i * sizeof(LatState), &st, sizeof st,
+                          hipMemcpyHostToDevice, L->stream));
+    unsigned long long b[2] = {h.hops[0], h.hops[1]};
+    HIP_OK(hipMemcpyAsync((char*)L->buf.work + L->Y.o_buckets + (size_t)i * kHopBuckets * 2 * 8, b, 16,
+                          hipMemcpyHostToDevice, L->stream));
+    HIP_OK(hipStreamSynchronize(L->stream));
+    L->t_frag[i] = L->desc[i].plain ? 0.0 : h.t;
+    L->cycles_host[i] = h.cycles;
+    std::memcpy(L->desc[i].k12, h.k12, sizeof h.k12);
+    L->desc[i].gb_period = h.gb_period;
+    L->desc[i].gb_mask = h.gb_mask;
+    s = upload_desc(L);
+    if (s) return s;
+    L->rates_ok[i] = h.rates_ok;
+    return FKMC_OK;
+}
+
 fkmc_status fkmc_set_graph(fkmc_lattice* L, int32_t enable)
 {
     if (!L) return fail(FKMC_E_INVALID, "null handle");

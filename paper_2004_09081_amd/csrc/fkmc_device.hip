@@ -1377,6 +1377,29 @@ int launch_gather(const DevPtrs& P, int lat, int64_t n_sites, int8_t* d_occ_cano
     return (int)hipGetLastError();
 }
 
+__global__ void k_scatter_disp(DevPtrs P, int lat, const int32_t* disp_c)
+{
+    const LatDesc& D = P.desc[lat];
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= D.n_sites) return;
+    const int t = (int)(n % 3);
+    const int64_t cell = n / 3;
+    const int i = (int)(cell % D.L[0]);
+    const int j = (int)((cell / D.L[0]) % D.L[1]);
+    const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
+    const int64_t s = store_index(D, P.bounds, P.c2s, i, j, k, t);
+    P.disp[D.disp_off + s] = make_int4(disp_c[3 * n], disp_c[3 * n + 1], disp_c[3 * n + 2], 0);
+}
+
+int launch_scatter_disp(const DevPtrs& P, int lat, int64_t n_sites, const int32_t* d_disp_canon,
+                        void* stream)
+{
+    const int64_t blocks = (n_sites + 255) / 256;
+    hipLaunchKernelGGL(k_scatter_disp, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, P,
+                       lat, d_disp_canon);
+    return (int)hipGetLastError();
+}
+
 int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_occ_canon,
                    void* stream)
 {

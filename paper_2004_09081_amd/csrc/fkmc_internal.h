@@ -115,6 +115,8 @@ int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_o
                    void* stream);
 int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream);
 int build_cycle_graph(const DevPtrs& P, int lds_per_wave, int cycles, hipGraphExec_t* out);
+int launch_scatter_disp(const DevPtrs& P, int lat, int64_t n_sites, const int32_t* d_disp_canon,
+                        void* stream);
 // LDS bytes one wave needs: slot scratch, plus a footprint copy when the
 // lattice is not resident.
 int phase_lds_per_wave(int max_footprint_bytes);

@@ -108,6 +108,9 @@ _SIGS = {
     "fkmc_set_timing": [C.c_void_p, C.c_int32],
     "fkmc_set_schedule": [C.c_void_p, C.c_int32, C.c_int32],
     "fkmc_set_graph": [C.c_void_p, C.c_int32],
+    "fkmc_checkpoint_size": [C.c_void_p, C.c_uint32, _P(C.c_size_t)],
+    "fkmc_checkpoint": [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t],
+    "fkmc_restore": [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t],
     "fkmc_phase_timing": [C.c_void_p, _P(C.c_double), _P(C.c_uint64)],
     "fkmc_quantisation": [C.c_void_p, C.c_uint32, _P(C.c_double), _P(C.c_double)],
     "fkmc_last_error": [],
@@ -248,6 +251,17 @@ class LatticeSet:
 
     def set_schedule(self, schedule: str = "auto", waves: int = 0):
         _check(lib().fkmc_set_schedule(self._h, self.SCHEDULES[schedule], int(waves)))
+
+    def checkpoint(self, i: int) -> bytes:
+        n = C.c_size_t()
+        _check(lib().fkmc_checkpoint_size(self._h, i, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().fkmc_checkpoint(self._h, i, buf, n.value))
+        return buf.raw
+
+    def restore(self, i: int, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        _check(lib().fkmc_restore(self._h, i, buf, len(data)))
 
     def set_graph(self, on: bool):
         _check(lib().fkmc_set_graph(self._h, 1 if on else 0))

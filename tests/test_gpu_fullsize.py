@@ -1,0 +1,74 @@
+"""Parity at the full size of the biased 600^3 workload (6.48e8 sites,
+16^3-cell fragments, boundary planes, field): the whole initial occupancy
+against the oracle, then one phase of colour 0 on the GPU against the oracle
+run on a sample of fragments (their footprints are touched by no other tile
+of that phase), plus invariants over the whole lattice."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests.common import say
+
+pytestmark = pytest.mark.gpu
+
+
+def footprint_index(L, lo, hi):
+    """Canonical indices of the footprint of sub-block [lo, hi): its cells'
+    sites plus the type-a sites of the next cell layer along +a."""
+    Lx, Ly, Lz = L
+    xs, ys, zs = [np.arange(lo[a], hi[a]) for a in range(3)]
+    def idx(i, j, k, t):
+        return ((k * Ly + j) * Lx + i) * 3 + t
+    I, J, K = np.meshgrid(xs, ys, zs, indexing="ij")
+    own = np.concatenate([idx(I, J, K, t).ravel() for t in range(3)])
+    J2, K2 = np.meshgrid(ys, zs, indexing="ij")
+    fx = idx(hi[0] % Lx, J2, K2, 0).ravel()
+    I2, K2 = np.meshgrid(xs, zs, indexing="ij")
+    fy = idx(I2, hi[1] % Ly, K2, 1).ravel()
+    I2, J2 = np.meshgrid(xs, ys, indexing="ij")
+    fz = idx(I2, J2, hi[2] % Lz, 2).ravel()
+    return np.concatenate([own, fx, fy, fz]).astype(np.int64)
+
+
+def test_full_size_biased_lattice_init_and_phase():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_09081_amd import fkmc as F
+    from paper_2004_09081_amd import workloads as W
+    sp = W.cfg3()
+    say("full size: init", sp.L, sp.n_vac)
+    geoms, rates = W.to_gpu([sp], F)
+    g = F.LatticeSet(geoms)
+    g.init_random([sp.n_vac], [sp.n_h])
+    g.set_rates(rates)
+    og = O.Geometry(L=sp.L, frag=sp.frag, a_angstrom=sp.a, seed=sp.seed, lattice_id=sp.lattice_id,
+                    gb_period_cells=sp.gb_period, gb_axes_mask=sp.gb_mask)
+    lat = O.Lattice(og)
+    lat.init_random(sp.n_vac, sp.n_h)
+    occ0, _ = g.read_state(0, with_disp=False)
+    assert np.array_equal(occ0, lat.occ), "initial occupancy differs"
+    lat.set_rates(O.RateParams(T=sp.T, Ea_O=sp.Ea_O, Ea_H=sp.Ea_H, E_z=sp.E_z, q=sp.q,
+                               gb_period_cells=sp.gb_period, gb_axes_mask=sp.gb_mask,
+                               gb_dE=sp.gb_dE))
+    assert g.get_rate_table(0).tobytes() == lat.k12.tobytes()
+    say("full size: phase 0")
+    g.run_phase([sp.t_sync], 0)
+    occ1, disp1 = g.read_state(0)
+    nf = lat.n_fragments
+    rng = np.random.default_rng(11)
+    sample = np.concatenate([[0, nf - 1], rng.choice(nf, 62, replace=False)])
+    moved = 0
+    for f in sample:
+        lat.phase(sp.t_sync, 0, 0, int(f))
+        lo, hi = O.sub_block(og, int(f), 0)
+        fp = footprint_index(sp.L, lo, hi)
+        assert np.array_equal(occ1[fp], lat.occ[fp]), "fragment %d occupancy" % f
+        assert np.array_equal(disp1[fp], lat.disp[fp]), "fragment %d displacement" % f
+        moved += int((lat.disp[fp] != 0).any(axis=1).sum())
+    assert moved > 0
+    # whole-lattice invariants: species conserved, displacements sum to zero
+    assert np.bincount(occ1, minlength=3).tolist() == np.bincount(occ0, minlength=3).tolist()
+    assert disp1.astype(np.int64).sum(axis=0).tolist() == [0, 0, 0]
+    st = g.read_stats()[0]
+    assert int(st["hops"].sum()) > 0 and st["count"][2] == sp.n_vac

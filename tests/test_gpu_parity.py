@@ -295,3 +295,41 @@ def test_graph_replays_match_eager_and_oracle():
         assert sg["t"] == lat.t and sg["hops"].tolist() == [int(x) for x in lat.hops]
         assert_same_state(g, 0, lat, "graph call %d" % rep)
         assert_same_state(e, 0, lat, "eager call %d" % rep)
+
+
+@pytest.mark.parametrize("name", ["field_gb", "plain"])
+def test_checkpoint_resume_is_bit_exact(name):
+    """Checkpoint after some cycles, restore into a fresh handle, continue:
+    identical to the uninterrupted run and to the oracle."""
+    say("checkpoint/resume", name)
+    c = FRAG_CASES["field_gb"] if name == "field_gb" else PLAIN_CASES["plain_H"]
+    lat = c.oracle()
+    t_sync = 2.0 / (8.0 * lat.k12[0])
+    a = gpu_set([c])
+    def step(s):
+        if lat.g.plain:
+            s.advance([0.0], 0, 700)
+        else:
+            s.advance([t_sync], max_cycles=3)
+    step(a)
+    blob = a.checkpoint(0)
+    step(a)
+    b = gpu_set([c])
+    b.init_random([0], [0])          # wipe, then restore
+    b.restore(0, blob)
+    step(b)
+    sa, sb = a.read_stats()[0], b.read_stats()[0]
+    for k in ("t", "cycles", "draws"):
+        assert sa[k] == sb[k], k
+    assert sa["hops"].tolist() == sb["hops"].tolist()
+    oa, da = a.read_state(0)
+    ob, db = b.read_state(0)
+    assert np.array_equal(oa, ob) and np.array_equal(da, db)
+    if lat.g.plain:
+        lat.advance_plain(700)
+        lat.advance_plain(700)
+    else:
+        lat.advance(t_sync, max_cycles=3)
+        lat.advance(t_sync, max_cycles=3)
+    assert_same_state(b, 0, lat, "resumed " + name)
+    assert sb["t"] == lat.t

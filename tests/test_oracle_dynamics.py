@@ -191,3 +191,56 @@ def test_displacements_conserved_and_observables():
     assert st.D[2] == pytest.approx(st.msd[2] / 12.0)
     assert st.drift[2, 0] == pytest.approx(2.0 * 2 / (2 * 2.0))
     assert st.Dtensor[2, 0, 0] == pytest.approx(4.0 * ((4 + 0) / 2 - 1.0) / 4.0)
+
+
+def test_drift_with_boundary_planes_matches_projected_chain():
+    """One vacancy under a field along z with boundary planes normal to z:
+    rates depend only on the layer Z (doubled coordinate), and layers of one
+    parity are alike, so Z alone is a Markov chain on a ring of 2 Lz layers.
+    Starting from its stationary law, E[z(t)] = v t with v from that chain."""
+    from scipy.linalg import null_space
+    T, Ea, E, q, gbdE, P = 600.0, 0.6, 3e8, 2.0, 0.08, 3
+    Lxy, Lz = 3, 6
+    p = O.RateParams(nu=1e13, T=T, Ea_O=Ea, E_z=E, q=q, gb_period_cells=P, gb_axes_mask=4, gb_dE=gbdE)
+    k = lambda dz, g: brute.arrhenius(1e13, Ea, T, E, q, dz / 2.0, A, gb=g * gbdE)
+    nz = 2 * Lz
+    Q = np.zeros((nz, nz))
+    gb_layer = lambda Z: Z % 2 == 0 and (Z // 2) % P == 0
+    for Z in range(nz):
+        up, dn = (Z + 1) % nz, (Z - 1) % nz
+        if Z % 2:   # types 0/1: two up and two down hops, the other end is even
+            Q[Z, up] += 2 * k(+1, gb_layer(up))
+            Q[Z, dn] += 2 * k(-1, gb_layer(dn))
+        else:       # type 2: four up and four down hops
+            Q[Z, up] += 4 * k(+1, gb_layer(Z))
+            Q[Z, dn] += 4 * k(-1, gb_layer(Z))
+    Q -= np.diag(Q.sum(1))
+    pi = null_space(Q.T)[:, 0]
+    pi = pi / pi.sum()
+    v_ref = sum(pi[Z] * (Q[Z, (Z + 1) % nz] - Q[Z, (Z - 1) % nz]) for Z in range(nz)) * A / 2
+    # sites of each layer, and the stationary start
+    g = O.Geometry(L=(Lxy, Lxy, Lz), gb_period_cells=P, gb_axes_mask=4)
+    N = g.n_sites
+    layer_sites = {Z: [] for Z in range(nz)}
+    for s in range(N):
+        t = s % 3
+        kc = s // 3 // (Lxy * Lxy)
+        layer_sites[2 * kc + (t != 2)].append(s)
+    rng = np.random.default_rng(5)
+    R = 3000
+    tend = 150.0 / (8 * k(0, 0))
+    z = np.zeros(R)
+    for r in range(R):
+        Z = rng.choice(nz, p=pi)
+        s0 = rng.choice(layer_sites[Z])
+        lat = O.Lattice(O.Geometry(L=(Lxy, Lxy, Lz), seed=13, lattice_id=r, gb_period_cells=P,
+                                   gb_axes_mask=4))
+        lat.occ[s0] = 2
+        lat.set_rates(p)
+        lat.advance_plain(10**9, t_horizon=tend)
+        v = np.nonzero(lat.occ == 2)[0][0]
+        z[r] = lat.disp[v, 2] * A / 2
+    v_est = z.mean() / tend
+    se = z.std(ddof=1) / math.sqrt(R) / tend
+    assert abs(v_est - v_ref) < 4 * se, (v_est, v_ref, se)
+    assert se / abs(v_ref) < 0.1
