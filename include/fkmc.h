@@ -126,6 +126,9 @@ typedef struct {
     double Dtensor[3][6];  /* (<r_a r_b> - <r_a><r_b>)/(2t), A^2/s */
     double busy_ms;        /* persistent schedule: device time this lattice's
                               workgroup took in the last fkmc_advance (ms) */
+    uint32_t lds_resident; /* 1 if the last fkmc_advance ran the persistent
+                              schedule with this lattice held in LDS */
+    uint32_t reserved;
 } fkmc_stats;
 
 /* Required byte sizes of the occ, disp and work buffers for n lattices. */

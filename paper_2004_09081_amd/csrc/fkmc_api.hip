@@ -309,6 +309,7 @@ struct fkmc_lattice {
     uint64_t last_launches = 0;
     hipGraphExec_t graph = nullptr;       // kGraphCycles lockstep cycles
     bool use_graph = true;
+    bool last_persistent = false;  // the last fkmc_advance ran the persistent kernel
 };
 
 static constexpr int kGraphCycles = 8;
@@ -794,7 +795,9 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         L->ev.resize(2 * 2048);
         for (auto& e : L->ev) HIP_OK(hipEventCreate(&e));
     }
+    L->last_persistent = false;
     if (any_frag && max_cycles > 0 && use_persistent(L)) {
+        L->last_persistent = true;
         s = plan_batch(L);
         if (s) return s;
         DevPtrs P = L->P;
@@ -1068,6 +1071,7 @@ fkmc_status fkmc_read_stats(fkmc_lattice* L, fkmc_stats* out)
             o.t = L->t_frag[i];
             o.cycles = S.cycles;
             o.busy_ms = (double)S.busy_ticks / 100000.0;  // 100 MHz real-time counter
+            o.lds_resident = L->last_persistent && L->desc[i].resident ? 1u : 0u;
             for (int b = 0; b < kHopBuckets; b++) {
                 o.hops[0] += bk[((size_t)i * kHopBuckets + b) * 2];
                 o.hops[1] += bk[((size_t)i * kHopBuckets + b) * 2 + 1];
