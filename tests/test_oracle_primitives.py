@@ -49,6 +49,20 @@ def _ulp_err(x, ref):
     return abs(x - ref) / math.ulp(ref) if ref != 0 else abs(x)
 
 
+def test_philox_known_answer_vectors():
+    """Published Philox4x32-10 test vectors (tests/golden/philox4x32_10_kat.txt)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    n = 0
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x, 16) for x in line.split()]
+        got = O.philox(tuple(v[0:4]), tuple(v[4:6]))
+        assert [int(x) for x in got] == v[6:10], line
+        n += 1
+    assert n == 3
+
+
 def test_ln_constants_match_mpmath():
     assert O.ln_constants() == gen_ln_constants.constants()
 
