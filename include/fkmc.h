@@ -208,11 +208,20 @@ fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_c
  *  FKMC_SCHEDULE_AUTO (default): persistent for a set of at least 32
  *    fragment lattices, or of several lattices of at most 49152 sites each;
  *    lockstep otherwise.  waves in 1..8; 0 keeps the current value
- *    (default 8). */
+ *    (default 4). */
 #define FKMC_SCHEDULE_AUTO 0
 #define FKMC_SCHEDULE_LOCKSTEP 1
 #define FKMC_SCHEDULE_PERSISTENT 2
 fkmc_status fkmc_set_schedule(fkmc_lattice* lat, int32_t schedule, int32_t waves);
+
+/* Tile groups: a wavefront runs `group` tiles of a phase at once, each on
+ * 64/group lanes with that many vacancy slots; a tile with more vacancies
+ * runs afterwards on the whole wavefront.  group = 0 (default) chooses per
+ * lattice from the mean vacancy count of a footprint; otherwise the
+ * lockstep schedule uses group (1, 2, 4 or 8) and the persistent schedule
+ * uses 8 when group is 8 and 1 (whole wavefront per tile) for any other
+ * value.  Results are identical for every group size. */
+fkmc_status fkmc_set_group(fkmc_lattice* lat, int32_t group);
 
 /* Lockstep schedule: replay batches of 8 cycles from a prebuilt HIP graph
  * (1, default) or enqueue every kernel separately (0).  Results are

@@ -180,7 +180,7 @@ fkmc_status quantise(const double raw[12], uint64_t n_ev, double out[12], double
 struct Layout {
     size_t occ_bytes, disp_bytes, work_bytes;
     std::vector<int64_t> occ_off, disp_off;
-    size_t o_desc, o_call, o_state, o_buckets, o_stat, o_counts, o_plain, o_batch, o_tile2lat, o_tiles, o_bounds, o_c2s;
+    size_t o_desc, o_call, o_state, o_buckets, o_stat, o_counts, o_plain, o_batch, o_tile2lat, o_tiles, o_bounds, o_c2s, o_groups;
     int32_t n_tiles;
     std::vector<std::vector<int32_t>> bounds[3];
 };
@@ -224,6 +224,7 @@ Layout plan(const fkmc_geometry* g, uint32_t n)
     Y.o_tiles = take((size_t)8 * std::max(tiles, 1) * sizeof(TileRec));
     Y.o_bounds = take((size_t)nb * sizeof(int32_t));
     Y.o_c2s = take((size_t)nc * sizeof(int32_t));
+    Y.o_groups = take((size_t)std::max(tiles, 1) * sizeof(int2));
     Y.work_bytes = w;
     return Y;
 }
@@ -289,12 +290,14 @@ struct fkmc_lattice {
     int32_t* d_batch_ids = nullptr;
     std::vector<int32_t> batch_ids;       // fragment lattices
     uint64_t* d_counts = nullptr;
-    int lds_per_wave = 0;                 // lockstep kernel
+    int fp_stride = 0;                    // LDS bytes of the largest staged footprint
+    int phase_group = 0;                  // lockstep kernel: tiles per wave (0: not chosen yet)
+    int group_override = 0;               // fkmc_set_group (0: automatic)
+    int2* d_groups = nullptr;
     int schedule = FKMC_SCHEDULE_AUTO;
-    int batch_waves = 8;
+    int batch_waves = 4;
     int lds_budget = 65536;               // persistent kernel, per workgroup
-    int batch_wave_bytes = 0;
-    int batch_slab_bytes = 0;
+    int batch_region_bytes = 0;
     std::vector<uint64_t> n_vac;
     std::vector<uint64_t> n_o, n_h;       // ion counts (conserved by hops)
     std::vector<char> rates_ok;
@@ -412,8 +415,8 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
         if (wm > kMaxWidth) return fail(FKMC_E_UNSUPPORTED, "lattice %u: sub-block edge %d > %d", i, wm, kMaxWidth);
         maxfp = std::max<int>(maxfp, (int)fp);
     }
-    const int lpw = maxfp ? phase_lds_per_wave(maxfp) : 0;
-    if (lpw > kMaxLdsPerBlock)
+    const int fps = maxfp ? footprint_stride(maxfp) : 0;
+    if (kWaveScratch + fps > kMaxLdsPerBlock)
         return fail(FKMC_E_UNSUPPORTED, "sub-block footprint of %d sites exceeds the LDS budget", maxfp);
 
     fkmc_lattice* L = new fkmc_lattice();
@@ -422,7 +425,7 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
     L->stream = (hipStream_t)hip_stream;
     L->buf = *buf;
     L->Y = Y;
-    L->lds_per_wave = lpw;
+    L->fp_stride = fps;
     L->n_vac.assign(n, 0);
     L->n_o.assign(n, 0);
     L->n_h.assign(n, 0);
@@ -495,7 +498,9 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
     L->d_plain_ids = (int32_t*)(w + Y.o_plain);
     L->d_batch_ids = (int32_t*)(w + Y.o_batch);
     L->P.batch_ids = L->d_batch_ids;
-    L->P.lds_wave_bytes = lpw;
+    L->P.fp_stride = fps;
+    L->d_groups = (int2*)(w + Y.o_groups);
+    L->P.groups = L->d_groups;
     {
         int dev = 0, smem = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -570,6 +575,7 @@ fkmc_status fkmc_init_random(fkmc_lattice* L, const uint64_t* n_vac, const uint6
     for (uint32_t i = 0; i < L->n; i++) {
         L->n_vac[i] = n_vac[i];
         L->n_h[i] = n_h[i];
+        L->phase_group = 0;
         L->n_o[i] = (uint64_t)L->desc[i].n_sites - n_vac[i] - n_h[i];
         L->rates_ok[i] = 0;
     }
@@ -601,6 +607,7 @@ fkmc_status fkmc_set_occupancy(fkmc_lattice* L, uint32_t i, const int8_t* host, 
     HIP_OK(hipStreamSynchronize(L->stream));
     L->n_vac[i] = nv;
     L->n_h[i] = nh;
+    L->phase_group = 0;
     L->n_o[i] = N - nv - nh;
     L->rates_ok[i] = 0;
     return FKMC_OK;
@@ -678,16 +685,73 @@ fkmc_status fkmc_get_rate_table(const fkmc_lattice* L, uint32_t i, double* k12, 
     return FKMC_OK;
 }
 
+// Tiles one wave runs at once for a lattice whose footprints hold lam
+// vacancies on average: the largest group (each tile then has 64/group
+// lanes and slots) for which at most 2 % of the tiles overflow their slots
+// (Poisson tail), within `lds` bytes of staged footprints per wave; groups
+// of 8 or 1 only unless `all`.
+static int pick_group(double lam, int fp_stride, int lds, bool all)
+{
+    auto fits = [&](int slots) {
+        double p = std::exp(-lam), c = p;
+        for (int k = 1; k <= slots; k++) {
+            p *= lam / k;
+            c += p;
+        }
+        return 1.0 - c <= 0.02;
+    };
+    for (int g = 8; g > 1; g /= 2) {
+        if (g != 8 && !all) continue;
+        if (fits(64 / g) && (int64_t)g * fp_stride <= lds) return g;
+    }
+    return 1;
+}
+
+static double mean_footprint_vacancies(const fkmc_lattice* L, uint32_t i)
+{
+    return (double)L->n_vac[i] * (double)max_footprint(L->geo[i]) / (double)L->desc[i].n_sites;
+}
+
+// Lockstep schedule: choose the group size for the set (the smallest over
+// its fragment lattices) and lay out one (lattice, first fragment) entry
+// per wave; groups never span two lattices.
+static fkmc_status prepare_lockstep(fkmc_lattice* L)
+{
+    if (L->phase_group) return FKMC_OK;
+    int g = 8;
+    for (int32_t i : L->batch_ids)
+        g = std::min(g, pick_group(mean_footprint_vacancies(L, i), L->fp_stride, 32768 - kWaveScratch, true));
+    if (L->group_override) g = L->group_override;
+    while (g > 1 && kWaveScratch + g * L->fp_stride > 65536) g /= 2;
+    std::vector<int2> groups;
+    for (int32_t i : L->batch_ids) {
+        const LatDesc& D = L->desc[i];
+        const int nt = D.nf[0] * D.nf[1] * D.nf[2];
+        for (int f0 = 0; f0 < nt; f0 += g) groups.push_back(make_int2(i, f0));
+    }
+    if (!groups.empty())
+        HIP_OK(hipMemcpyAsync(L->d_groups, groups.data(), groups.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, L->stream));
+    HIP_OK(hipStreamSynchronize(L->stream));
+    L->P.n_groups = (int32_t)groups.size();
+    L->P.lds_wave_bytes = kWaveScratch + g * L->fp_stride;
+    if (L->graph) {
+        (void)hipGraphExecDestroy(L->graph);
+        L->graph = nullptr;
+    }
+    L->phase_group = g;
+    return FKMC_OK;
+}
+
 static fkmc_status record_phase(fkmc_lattice* L, int colour, size_t& ev_used)
 {
-    L->P.lds_wave_bytes = L->lds_per_wave;
     if (L->timing && ev_used + 2 <= L->ev.size()) {
         HIP_OK(hipEventRecord(L->ev[ev_used], L->stream));
-        LAUNCH_OK(launch_phase(L->P, colour, L->lds_per_wave, L->stream));
+        LAUNCH_OK(launch_phase(L->P, colour, L->phase_group, L->stream));
         HIP_OK(hipEventRecord(L->ev[ev_used + 1], L->stream));
         ev_used += 2;
     } else {
-        LAUNCH_OK(launch_phase(L->P, colour, L->lds_per_wave, L->stream));
+        LAUNCH_OK(launch_phase(L->P, colour, L->phase_group, L->stream));
     }
     return FKMC_OK;
 }
@@ -710,59 +774,49 @@ static fkmc_status prepare_call(fkmc_lattice* L, const double* t_sync, uint64_t 
     return FKMC_OK;
 }
 
-// Persistent-kernel plan: which lattices stay in LDS, and the LDS sizes.
-// One workgroup needs slab + waves * wave_bytes, where the slab holds the
-// largest resident lattice and wave_bytes the slot scratch plus a private
-// footprint copy sized for the largest non-resident footprint.  Lattices are
-// moved out of LDS, largest first, until that fits the per-workgroup budget
-// (two workgroups per CU), so that every lattice's workgroup is resident at
-// once.
+// Persistent-kernel plan.  A workgroup's dynamic LDS is one region plus
+// the waves' scratch; the region holds either the whole lattice (occupancy,
+// vacancy list, cell -> sub-block maps) or every wave's staged footprints,
+// so a lattice stays in LDS whenever its slab fits the region's bound (two
+// workgroups per CU).  Each lattice also gets its group size (8, 4 or 1).
 static fkmc_status plan_batch(fkmc_lattice* L)
 {
     const int waves = L->batch_waves;
-    const int scratch = phase_lds_per_wave(0) - ((0 + 4 * 32 + 15) & ~15);
-    std::vector<int32_t> ids = L->batch_ids;
-    std::sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
-        return L->desc[a].n_sites < L->desc[b].n_sites;
-    });
-    for (int32_t i : ids) L->desc[i].resident = 0;
-    // resident: the k smallest lattices, k as large as fits
-    int best_k = 0, best_slab = 0, best_wave = 0;
-    for (size_t k = 0; k <= ids.size(); k++) {
-        int slab = 0, fp_max = 0;
-        bool fits = true;
-        for (size_t r = 0; r < ids.size(); r++) {
-            const int32_t i = ids[r];
-            if (r < k) {
-                const int64_t need = ((L->desc[i].n_sites + 15) & ~15) + 32 +
-                                     ((4 * (int64_t)L->n_vac[i] + 15) & ~15);
-                if (need > 65536) { fits = false; break; }
-                slab = std::max<int>(slab, (int)need);
-            } else {
-                fp_max = std::max<int>(fp_max, (int)max_footprint(L->geo[i]));
-            }
+    const int bound = L->lds_budget - waves * kWaveScratch - 64;
+    int region = 0;
+    for (int32_t i : L->batch_ids) {
+        LatDesc& D = L->desc[i];
+        const fkmc_geometry& g = L->geo[i];
+        const double lam = mean_footprint_vacancies(L, i);
+        const int64_t slab = ((D.n_sites + 15) & ~(int64_t)15) + 4 * (((int64_t)L->n_vac[i] + 3) & ~3) +
+                             g.L[0] + g.L[1] + g.L[2];
+        bool small = slab <= std::min(bound, 65536);
+        for (int a = 0; a < 3; a++) small = small && D.nsb[a] <= 255 && g.L[a] <= 1023;
+        D.n_vac = (int32_t)L->n_vac[i];
+        D.resident = small ? 1 : 0;
+        const int fps = footprint_stride((int)max_footprint(g));
+        D.fp_stride = fps;
+        if (L->group_override) {
+            D.group = L->group_override == 8 ? 8 : 1;
+            if (!small && (int64_t)waves * D.group * fps > std::min(bound, 65536)) D.group = 1;
+            region = std::max<int>(region, small ? (int)slab : waves * D.group * fps);
+            if (!small && (int64_t)waves * fps > std::min(bound, 65536))
+                return fail(FKMC_E_UNSUPPORTED, "lattice %d: %d waves need %lld bytes of LDS", (int)i,
+                            waves, (long long)waves * fps + waves * kWaveScratch);
+        } else if (small) {
+            D.group = pick_group(lam, 0, 0, false);
+            region = std::max<int>(region, (int)slab);
+        } else {
+            // staged footprints keep LDS addresses below 2^16
+            const int area = std::min(bound, 65536);
+            D.group = pick_group(lam, fps, area / waves, false);
+            if ((int64_t)waves * D.group * fps > area)
+                return fail(FKMC_E_UNSUPPORTED, "lattice %d: %d waves need %lld bytes of LDS", (int)i,
+                            waves, (long long)waves * fps + waves * kWaveScratch);
+            region = std::max<int>(region, waves * D.group * fps);
         }
-        if (!fits) break;
-        const int wave_bytes = fp_max ? phase_lds_per_wave(fp_max) : scratch;
-        if (slab + waves * wave_bytes > L->lds_budget) {
-            if (k == 0) {  // even with nothing resident: allow one workgroup per CU
-                if (waves * wave_bytes > 163840)
-                    return fail(FKMC_E_UNSUPPORTED, "persistent kernel needs %d bytes of LDS",
-                                waves * wave_bytes);
-                best_k = 0;
-                best_slab = 0;
-                best_wave = wave_bytes;
-            }
-            break;
-        }
-        best_k = (int)k;
-        best_slab = slab;
-        best_wave = wave_bytes;
     }
-    for (int r = 0; r < best_k; r++) L->desc[ids[r]].resident = 1;
-    for (int32_t i : ids) L->desc[i].n_vac = (int32_t)L->n_vac[i];
-    L->batch_slab_bytes = best_slab;
-    L->batch_wave_bytes = best_wave;
+    L->batch_region_bytes = (region + 15) & ~15;
     return upload_desc(L);
 }
 
@@ -801,8 +855,7 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         s = plan_batch(L);
         if (s) return s;
         DevPtrs P = L->P;
-        P.lds_resident_bytes = L->batch_slab_bytes;
-        P.lds_wave_bytes = L->batch_wave_bytes;
+        P.lds_region_bytes = L->batch_region_bytes;
         if (L->timing) HIP_OK(hipEventRecord(L->ev[0], L->stream));
         LAUNCH_OK(launch_batch(P, (int)L->batch_ids.size(), L->batch_waves, L->stream));
         if (L->timing) {
@@ -810,6 +863,8 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
             ev_used = 2;
         }
     } else if (any_frag && max_cycles > 0) {
+        s = prepare_lockstep(L);
+        if (s) return s;
         LAUNCH_OK(launch_cycle_begin(L->P, L->stream));
         // Cycles are enqueued in batches; the device marks a lattice done once
         // it reaches its target, after which its kernels return at once, so
@@ -817,8 +872,7 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         // timing, whole batches of cycles are replayed from a prebuilt graph.
         const bool graph = L->use_graph && !L->timing;
         if (graph && !L->graph) {
-            L->P.lds_wave_bytes = L->lds_per_wave;
-            LAUNCH_OK(build_cycle_graph(L->P, L->lds_per_wave, kGraphCycles, &L->graph));
+            LAUNCH_OK(build_cycle_graph(L->P, L->phase_group, kGraphCycles, &L->graph));
         }
         uint64_t batch = min_hops > 0 ? 1 : max_cycles;
         uint64_t cyc = 0;
@@ -991,6 +1045,16 @@ fkmc_status fkmc_set_graph(fkmc_lattice* L, int32_t enable)
     return FKMC_OK;
 }
 
+fkmc_status fkmc_set_group(fkmc_lattice* L, int32_t group)
+{
+    if (!L) return fail(FKMC_E_INVALID, "null handle");
+    if (group != 0 && group != 1 && group != 2 && group != 4 && group != 8)
+        return fail(FKMC_E_INVALID, "group must be 0, 1, 2, 4 or 8");
+    L->group_override = group;
+    L->phase_group = 0;
+    return FKMC_OK;
+}
+
 fkmc_status fkmc_set_schedule(fkmc_lattice* L, int32_t schedule, int32_t waves)
 {
     if (!L) return fail(FKMC_E_INVALID, "null handle");
@@ -1010,7 +1074,9 @@ fkmc_status fkmc_run_phase(fkmc_lattice* L, const double* t_sync, int32_t colour
     fkmc_status s = prepare_call(L, t_sync, 1, 0, true);
     if (s) return s;
     LAUNCH_OK(launch_cycle_begin(L->P, L->stream));
-    LAUNCH_OK(launch_phase(L->P, colour, L->lds_per_wave, L->stream));
+    s = prepare_lockstep(L);
+    if (s) return s;
+    LAUNCH_OK(launch_phase(L->P, colour, L->phase_group, L->stream));
     return read_states(L);
 }
 

@@ -224,18 +224,37 @@ struct TileGeo {
     int len0, len1, len2, len3;
 };
 
+// One of three or four register values by a runtime index.  The empty asm
+// makes the operands plain registers, so that the selection is never
+// turned into an indexed load from a private copy of the struct.
+__device__ __forceinline__ int pick3(int k, int a, int b, int c)
+{
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
+    return k == 0 ? a : (k == 1 ? b : c);
+}
+__device__ __forceinline__ int pick4(int k, int a, int b, int c, int d)
+{
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+    return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
+}
+__device__ __forceinline__ int64_t pick4(int k, int64_t a, int64_t b, int64_t c, int64_t d)
+{
+    asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
+    return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
+}
+
 // Segment accessors (selects, never a runtime-indexed local array).
 __device__ __forceinline__ int64_t seg_st(const TileGeo& G, int k)
 {
-    return k == 0 ? G.st0 : (k == 1 ? G.st1 : (k == 2 ? G.st2 : G.st3));
+    return pick4(k, G.st0, G.st1, G.st2, G.st3);
 }
 __device__ __forceinline__ int seg_lds(const TileGeo& G, int k)
 {
-    return k == 0 ? G.lds0 : (k == 1 ? G.lds1 : (k == 2 ? G.lds2 : G.lds3));
+    return pick4(k, G.lds0, G.lds1, G.lds2, G.lds3);
 }
 __device__ __forceinline__ int seg_len(const TileGeo& G, int k)
 {
-    return k == 0 ? G.len0 : (k == 1 ? G.len1 : (k == 2 ? G.len2 : G.len3));
+    return pick4(k, G.len0, G.len1, G.len2, G.len3);
 }
 
 __device__ __forceinline__ TileGeo tile_geo_rec(const TileRec& R)
@@ -257,29 +276,6 @@ __device__ __forceinline__ TileGeo tile_geo_rec(const TileRec& R)
     G.len3 = G.wy * G.wx;
     G.lds0 = G.lds1 = G.lds2 = G.lds3 = 0;
     return G;
-}
-
-// LDS positions of the four segments in a wave's private footprint copy:
-// consecutive 16-byte-aligned runs keeping each segment's HBM alignment.
-__device__ __forceinline__ void tile_lds_private(TileGeo& G)
-{
-    int off = 0;
-    G.lds0 = off + (int)(G.st0 & 15);
-    off += ((int)(G.st0 & 15) + G.len0 + 15) & ~15;
-    G.lds1 = off + (int)(G.st1 & 15);
-    off += ((int)(G.st1 & 15) + G.len1 + 15) & ~15;
-    G.lds2 = off + (int)(G.st2 & 15);
-    off += ((int)(G.st2 & 15) + G.len2 + 15) & ~15;
-    G.lds3 = off + (int)(G.st3 & 15);
-}
-
-// LDS positions when the whole lattice sits in LDS at its storage offsets.
-__device__ __forceinline__ void tile_lds_resident(TileGeo& G)
-{
-    G.lds0 = (int)G.st0;
-    G.lds1 = (int)G.st1;
-    G.lds2 = (int)G.st2;
-    G.lds3 = (int)G.st3;
 }
 
 __device__ __forceinline__ int fp_local(const TileGeo& G, int lx, int ly, int lz, int t, int& li)
@@ -308,202 +304,38 @@ __device__ __forceinline__ void xyz_where(const TileGeo& G, uint32_t xyz, int& l
 }
 
 // ----------------------------------------------------------------------------
-// Per-wave LDS scratch: vacancy count, rate table, unsorted slots (canonical
-// key + packed coordinates), sorted slot coordinates; then, for a tile whose
-// lattice is not LDS-resident, the private footprint copy.
-struct WaveScratch {
-    int* cnt;
-    double* k12;
-    uint64_t* raw_key;
-    uint32_t* raw_xyz;
-    uint32_t* xyz;
-    uint16_t* raw_idx;  // resident lattices: vacancy-list entry of each slot
-    uint16_t* idx;
-    unsigned char* occ;
+// ----------------------------------------------------------------------------
+// Small quotient a / b for 0 <= a < 2^22, 1 <= b < 2^22: the float product
+// with a one-ulp reciprocal lands within one of the true quotient, and one
+// remainder test each way corrects it.
+__device__ __forceinline__ int udiv22(int a, int b)
+{
+    int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+    const int r = a - q * b;
+    q += r >= b ? 1 : 0;
+    q -= r < 0 ? 1 : 0;
+    return q;
+}
+
+// What a tile needs of its lattice's rates: sizes for the boundary-plane
+// test and the quantised table (an LDS copy).
+struct RateCtx {
+    int L0, L1, L2;
+    int gbp, gbm;
+    const double* k12;
 };
 
-__host__ __device__ constexpr int scratch_bytes() { return 112 + kMaxSlots * 20; }
-
-__device__ __forceinline__ WaveScratch wave_scratch(unsigned char* base)
+__device__ __forceinline__ int gb_flag(const RateCtx& C, int t, int cell)
 {
-    WaveScratch w;
-    w.cnt = (int*)base;
-    w.k12 = (double*)(base + 16);
-    w.raw_key = (uint64_t*)(base + 112);
-    w.raw_xyz = (uint32_t*)(base + 112 + 8 * kMaxSlots);
-    w.xyz = (uint32_t*)(base + 112 + 12 * kMaxSlots);
-    w.raw_idx = (uint16_t*)(base + 112 + 16 * kMaxSlots);
-    w.idx = (uint16_t*)(base + 112 + 18 * kMaxSlots);
-    w.occ = base + scratch_bytes();
-    return w;
-}
-
-// Record vacancy found at segment k, local index li.
-__device__ __forceinline__ void add_slot(const TileGeo& G, const LatDesc& D, const WaveScratch& W,
-                                         int k, int li)
-{
-    int lx, ly, lz, t;
-    if (k == 0) {
-        const int V = G.wx * G.wy * G.wz;
-        t = li / V;
-        const int r = li - t * V;
-        if (t == 0) { ly = r % G.wy; lz = (r / G.wy) % G.wz; lx = r / (G.wy * G.wz); }
-        else if (t == 1) { lx = r % G.wx; lz = (r / G.wx) % G.wz; ly = r / (G.wx * G.wz); }
-        else { lx = r % G.wx; ly = (r / G.wx) % G.wy; lz = r / (G.wx * G.wy); }
-    } else if (k == 1) {
-        t = 0; lx = G.wx; ly = li % G.wy; lz = li / G.wy;
-    } else if (k == 2) {
-        t = 1; ly = G.wy; lx = li % G.wx; lz = li / G.wx;
-    } else {
-        t = 2; lz = G.wz; lx = li % G.wx; ly = li / G.wx;
-    }
-    int gi = G.ox + lx, gj = G.oy + ly, gk = G.oz + lz;
-    if (gi >= D.L[0]) gi -= D.L[0];
-    if (gj >= D.L[1]) gj -= D.L[1];
-    if (gk >= D.L[2]) gk -= D.L[2];
-    const uint64_t key = ((((uint64_t)gk * D.L[1] + gj) * D.L[0] + gi) * 3) + t;
-    const int slot = atomicAdd(W.cnt, 1);
-    if (slot < kMaxSlots) {
-        W.raw_xyz[slot] = pack_xyz(2 * lx + (t != 0), 2 * ly + (t != 1), 2 * lz + (t != 2));
-        W.raw_key[slot] = key;
-    }
-}
-
-// Vacancy bytes (value 2) of one 16-byte chunk of segment k.
-__device__ __forceinline__ void scan_chunk(const TileGeo& G, const LatDesc& D, const WaveScratch& W,
-                                           int k, int chunk, int al, uint4 v)
-{
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const uint32_t wq = q == 0 ? v.x : (q == 1 ? v.y : (q == 2 ? v.z : v.w));
-        const uint32_t x = wq ^ 0x02020202u;
-        if (((x - 0x01010101u) & ~x & 0x80808080u) == 0) continue;
-#pragma unroll
-        for (int bb = 0; bb < 4; bb++) {
-            if (((wq >> (8 * bb)) & 0xff) != kSpV) continue;
-            const int li = 16 * chunk + 4 * q + bb - al;
-            if (li < 0 || li >= seg_len(G, k)) continue;
-            add_slot(G, D, W, k, li);
-        }
-    }
-}
-
-// Copy (kFromGlobal) or read in place the footprint's 16-byte chunks and
-// collect its vacancies (unsorted).  All loads of a lane are issued before
-// any of them is consumed.
-__device__ __forceinline__ void collect_slots(const TileGeo& G, const LatDesc& D, const WaveScratch& W,
-                                              const unsigned char* src, int lane, bool from_global)
-{
-    const int al0 = (int)(G.st0 & 15), al1 = (int)(G.st1 & 15), al2 = (int)(G.st2 & 15),
-              al3 = (int)(G.st3 & 15);
-    const int n0 = (al0 + G.len0 + 15) >> 4, n1 = (al1 + G.len1 + 15) >> 4,
-              n2 = (al2 + G.len2 + 15) >> 4, n3 = (al3 + G.len3 + 15) >> 4;
-    const int total = n0 + n1 + n2 + n3;
-    for (int base = 0; base < total; base += 256) {
-        uint4 v0, v1, v2, v3;
-        int k0, k1, k2, k3, c0, c1, c2, c3;
-        // locate chunk j: segment k, chunk index c within it
-        auto locate = [&](int j, int& k, int& c) {
-            k = -1;
-            c = j;
-            if (j >= total) return;
-            if (c < n0) { k = 0; return; }
-            c -= n0;
-            if (c < n1) { k = 1; return; }
-            c -= n1;
-            if (c < n2) { k = 2; return; }
-            c -= n2;
-            k = 3;
-        };
-        auto fetch = [&](int k, int c) -> uint4 {
-            const int64_t st = seg_st(G, k);
-            const int a = (int)(st & 15);
-            return *((const uint4*)(src + (st - a)) + c);
-        };
-        locate(base + lane, k0, c0);
-        locate(base + lane + 64, k1, c1);
-        locate(base + lane + 128, k2, c2);
-        locate(base + lane + 192, k3, c3);
-        if (k0 >= 0) v0 = fetch(k0, c0);
-        if (k1 >= 0) v1 = fetch(k1, c1);
-        if (k2 >= 0) v2 = fetch(k2, c2);
-        if (k3 >= 0) v3 = fetch(k3, c3);
-        auto take = [&](int k, int c, uint4 v) {
-            if (k < 0) return;
-            const int a = (int)(seg_st(G, k) & 15);
-            if (from_global) *((uint4*)(W.occ + seg_lds(G, k) - a) + c) = v;
-            scan_chunk(G, D, W, k, c, a, v);
-        };
-        take(k0, c0, v0);
-        take(k1, c1, v1);
-        take(k2, c2, v2);
-        take(k3, c3, v3);
-    }
-    (void)al1;
-    (void)al2;
-    (void)al3;
-}
-
-// Order the slots by canonical site index (keys are distinct).
-__device__ __forceinline__ void sort_slots(const WaveScratch& W, int n, int lane)
-{
-    for (int l = lane; l < n; l += 64) {
-        const uint64_t key = W.raw_key[l];
-        int rank = 0;
-        for (int j = 0; j < n; j++) rank += W.raw_key[j] < key;
-        W.xyz[rank] = W.raw_xyz[l];
-        W.idx[rank] = W.raw_idx[l];
-    }
-}
-
-// Resident lattices keep the global position of every vacancy in an LDS
-// list (i | j << 10 | k << 20 | type << 30).  The slots of a tile are the
-// list entries inside its footprint.
-__device__ __forceinline__ void collect_from_list(const TileGeo& G, const LatDesc& D,
-                                                  const WaveScratch& W, const uint32_t* vlist,
-                                                  int nv, int lane)
-{
-    for (int v = lane; v < nv; v += 64) {
-        const uint32_t g = vlist[v];
-        const int i = g & 1023, j = (g >> 10) & 1023, k = (g >> 20) & 1023, t = g >> 30;
-        int lx = i - G.ox, ly = j - G.oy, lz = k - G.oz;
-        if (lx < 0) lx += D.L[0];
-        if (ly < 0) ly += D.L[1];
-        if (lz < 0) lz += D.L[2];
-        const bool inx = lx < G.wx, iny = ly < G.wy, inz = lz < G.wz;
-        const bool in = (inx && iny && inz) || (t == 0 && lx == G.wx && iny && inz) ||
-                        (t == 1 && ly == G.wy && inx && inz) || (t == 2 && lz == G.wz && inx && iny);
-        if (!in) continue;
-        const int slot = atomicAdd(W.cnt, 1);
-        if (slot < kMaxSlots) {
-            W.raw_key[slot] = ((((uint64_t)k * D.L[1] + j) * D.L[0] + i) * 3) + t;
-            W.raw_xyz[slot] = pack_xyz(2 * lx + (t != 0), 2 * ly + (t != 1), 2 * lz + (t != 2));
-            W.raw_idx[slot] = (uint16_t)v;
-        }
-    }
-}
-
-// Write the final positions of a tile's vacancies back to the list.
-__device__ __forceinline__ void update_list(const TileGeo& G, const LatDesc& D, const WaveScratch& W,
-                                            uint32_t* vlist, int n, int lane)
-{
-    for (int l = lane; l < n; l += 64) {
-        const uint32_t xyz = W.xyz[l];
-        const int X = xyz & 1023, Y = (xyz >> 10) & 1023, Z = xyz >> 20;
-        const int t = site_type(X, Y);
-        int i = G.ox + (X >> 1), j = G.oy + (Y >> 1), k = G.oz + (Z >> 1);
-        if (i >= D.L[0]) i -= D.L[0];
-        if (j >= D.L[1]) j -= D.L[1];
-        if (k >= D.L[2]) k -= D.L[2];
-        vlist[W.idx[l]] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20) | ((uint32_t)t << 30);
-    }
+    if (C.gbp <= 0 || !((C.gbm >> t) & 1)) return 0;
+    return cell - udiv22(cell, C.gbp) * C.gbp == 0 ? 1 : 0;
 }
 
 // Rate of event d of the vacancy at packed local doubled coordinates xyz:
 // 0 when the hop edge's midpoint is outside the sub-block or the target
 // holds a vacancy; else the table entry for (ion species, z step, boundary).
 __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned char* occl,
-                                            const double* k12, const LatDesc& D, uint32_t xyz, int d)
+                                            const RateCtx& C, uint32_t xyz, int d)
 {
     const int X = xyz & 1023, Y = (xyz >> 10) & 1023, Z = xyz >> 20;
     const int t = site_type(X, Y);
@@ -518,14 +350,16 @@ __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned cha
     const int sp = occl[seg_lds(G, seg) + li];
     if (sp == kSpV) return 0.0;
     int g = 0;
-    if (D.gb_period > 0) {
-        int cs = t == 0 ? G.ox + (X >> 1) : (t == 1 ? G.oy + (Y >> 1) : G.oz + (Z >> 1));
-        int ct = tt == 0 ? G.ox + (tX >> 1) : (tt == 1 ? G.oy + (tY >> 1) : G.oz + (tZ >> 1));
-        if (cs >= D.L[t]) cs -= D.L[t];
-        if (ct >= D.L[tt]) ct -= D.L[tt];
-        g = is_gb(D, t, cs) | is_gb(D, tt, ct);
+    if (C.gbp > 0) {
+        int cs = pick3(t, G.ox + (X >> 1), G.oy + (Y >> 1), G.oz + (Z >> 1));
+        int ct = pick3(tt, G.ox + (tX >> 1), G.oy + (tY >> 1), G.oz + (tZ >> 1));
+        const int Ls = pick3(t, C.L0, C.L1, C.L2);
+        const int Lt = pick3(tt, C.L0, C.L1, C.L2);
+        if (cs >= Ls) cs -= Ls;
+        if (ct >= Lt) ct -= Lt;
+        g = gb_flag(C, t, cs) | gb_flag(C, tt, ct);
     }
-    return k12[(sp * 3 + hz + 1) * 2 + g];
+    return C.k12[(sp * 3 + hz + 1) * 2 + g];
 }
 
 __device__ __forceinline__ bool nn_site(uint32_t a, uint32_t b)
@@ -544,135 +378,508 @@ __device__ __forceinline__ uint32_t hop_target_xyz(uint32_t xyz, int d, int& hx,
     return pack_xyz(X + hx, Y + hy, Z + hz);
 }
 
-// BKL on one tile (Eqs. TransitionProb, eventSelection, TimeStep) until the
-// next event would land after t_sync or no event is possible.  n sorted
-// slots in W.xyz; event e = slot*8 + direction, in that order.
-//  - n <= 8: lane e holds event e and its rate;
-//  - n <= 64: lane l holds slot l and the rates of its 8 events;
-//  - else: rates are recomputed from LDS at every step.
-// The cumulative rates are a wavefront prefix sum; after a hop only the
-// events whose vacancy moved or whose target changed are recomputed.
-// Displacement changes are kept per moved particle in lane registers
-// (origin, current site, accumulated hop) and written to HBM in two
-// wave-wide passes (all reads, then all writes) when the 64 records fill up
-// and at the end.
-__device__ __forceinline__ void tile_bkl(const TileGeo& G_, const WaveScratch& W, unsigned char* occl,
-                                         const LatDesc& D, int8_t* occ_lat, int4* disp_lat,
-                                         uint32_t f, uint32_t cycle, uint32_t colour, double t_sync,
-                                         int n, int lane, uint32_t& hops_o, uint32_t& hops_h,
-                                         bool write_occ, bool& stores_pending)
-{
-    bool rv = false;
-    uint32_t r_orig = 0, r_cur = 0;
-    int ax = 0, ay = 0, az = 0;
-    int4 r_old = make_int4(0, 0, 0, 0);  // origin's displacement, loaded when the record opens
-    int nrec = 0;
-    auto flush = [&]() {
-        int lo;
-        int64_t sf = 0;
-        if (rv) xyz_where(G_, r_cur, lo, sf);
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every lane's read is done
-        __builtin_amdgcn_wave_barrier();
-        if (rv) disp_lat[sf] = make_int4(r_old.x + ax, r_old.y + ay, r_old.z + az, 0);
-        stores_pending = true;  // waited for before the next displacement read
-        rv = false;
-        ax = ay = az = 0;
-        nrec = 0;
-    };
-    auto open_record = [&](uint32_t xyz) {
-        int lo;
-        int64_t so;
-        rv = true;
-        r_orig = xyz;
-        r_cur = xyz;
-        xyz_where(G_, xyz, lo, so);
-        r_old = disp_lat[so];  // (pending writes of this wave were waited for above)
-    };
+// ----------------------------------------------------------------------------
+// Displacement records.  A particle that hops gets a record in one lane of
+// the wave: the displacement index of its current site, its displacement
+// when the record opened (read from HBM then) and the hops since.  Records
+// are keyed by displacement index, so they stay valid across tiles and
+// phases for as long as one wave alone moves the lattice's particles; a
+// flush writes every record's displacement to its particle's current site
+// (all reads completed before any write).
+struct Rec {
+    int64_t cur;  // < 0: free
+    int ax, ay, az;
+    int4 old;
+};
 
-    // mode 1: G lanes per slot (G = 8, 4, 2, 1 for n <= 8, 16, 32, 64), each
-    // caching the rates of 8/G consecutive events; mode 2: recompute.
-    const int mode = n <= 64 ? 1 : 2;
-    const int G = n <= 8 ? 8 : (n <= 16 ? 4 : (n <= 32 ? 2 : 1));
-    const int epl = 8 / G;
-    const int my_slot = lane / G;
-    const int my_d0 = (lane % G) * epl;
-    const bool ev_valid = mode == 1 && my_slot < n;
+struct RecCtl {
+    int n;         // records in use (wave-uniform)
+    bool pending;  // stores of the last flush may still be in flight
+};
+
+__device__ __forceinline__ void rec_init(Rec& r, RecCtl& c)
+{
+    r.cur = -1;
+    r.ax = r.ay = r.az = 0;
+    r.old = make_int4(0, 0, 0, 0);
+    c.n = 0;
+    c.pending = false;
+}
+
+__device__ __forceinline__ void rec_flush(Rec& r, RecCtl& c, int4* disp)
+{
+    if (c.n == 0) return;
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every record's read has returned
+    __builtin_amdgcn_wave_barrier();
+    if (r.cur >= 0) disp[r.cur] = make_int4(r.old.x + r.ax, r.old.y + r.ay, r.old.z + r.az, 0);
+    r.cur = -1;
+    r.ax = r.ay = r.az = 0;
+    c.n = 0;
+    c.pending = true;
+}
+
+// The vacancy at displacement index ks swaps with the ion at kt, the vacancy
+// moving by h.  ks, kt and h are wave-uniform.
+__device__ __forceinline__ void rec_hop(Rec& r, RecCtl& c, int4* disp, int lane, int64_t ks,
+                                        int64_t kt, int hx, int hy, int hz)
+{
+    uint64_t mv = __ballot(r.cur == ks);
+    uint64_t mi = __ballot(r.cur == kt);
+    if (c.n + (mv == 0) + (mi == 0) > 64) {
+        rec_flush(r, c, disp);
+        mv = 0;
+        mi = 0;
+    }
+    if (c.pending && (mv == 0 || mi == 0)) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // the flushed stores have landed
+        __builtin_amdgcn_wave_barrier();
+        c.pending = false;
+    }
+    int lv, li;
+    if (mv) {
+        lv = __ffsll((unsigned long long)mv) - 1;
+    } else {
+        lv = c.n++;
+        if (lane == lv) {
+            r.cur = ks;
+            r.old = disp[ks];
+        }
+    }
+    if (mi) {
+        li = __ffsll((unsigned long long)mi) - 1;
+    } else {
+        li = c.n++;
+        if (lane == li) {
+            r.cur = kt;
+            r.old = disp[kt];
+        }
+    }
+    if (lane == lv) {
+        r.cur = kt;
+        r.ax += hx;
+        r.ay += hy;
+        r.az += hz;
+    }
+    if (lane == li) {
+        r.cur = ks;
+        r.ax -= hx;
+        r.ay -= hy;
+        r.az -= hz;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Per-wave LDS scratch: slot counters (8 group tiles + 1 single tile), the
+// group's tile records, the rate table, and slot lists of 128 entries
+// (unsorted canonical key, packed coordinates, vacancy-list index; sorted
+// coordinates and list index).  In group mode tile k owns entries
+// [k*cap, k*cap + cap).
+struct WaveLds {
+    int* cnt;
+    TileRec* rec;
+    double* k12;
+    uint64_t* raw_key;
+    uint32_t* raw_xyz;
+    uint32_t* xyz;
+    uint16_t* raw_idx;
+    uint16_t* idx;
+};
+
+// Byte offsets of the parts of a wave's scratch.
+constexpr int kLdsRec = 64;                            // TileRec[8]
+constexpr int kLdsK12 = kLdsRec + 8 * (int)sizeof(TileRec);
+constexpr int kLdsRawKey = kLdsK12 + 96;               // uint64[128]
+constexpr int kLdsRawXyz = kLdsRawKey + 1024;          // uint32[128]
+constexpr int kLdsXyz = kLdsRawXyz + 512;              // uint32[128]
+constexpr int kLdsRawIdx = kLdsXyz + 512;              // uint16[128]
+constexpr int kLdsIdx = kLdsRawIdx + 256;              // uint16[128]
+constexpr int kLdsEnd = kLdsIdx + 256;
+static_assert(sizeof(TileRec) == 48, "tile record layout");
+static_assert(kLdsK12 % 8 == 0 && kLdsRawKey % 8 == 0, "scratch alignment");
+static_assert(kLdsEnd <= kWaveScratch && kWaveScratch % 16 == 0, "wave scratch size");
+
+__device__ __forceinline__ WaveLds wave_lds(unsigned char* b)
+{
+    WaveLds w;
+    w.cnt = (int*)b;
+    w.rec = (TileRec*)(b + kLdsRec);
+    w.k12 = (double*)(b + kLdsK12);
+    w.raw_key = (uint64_t*)(b + kLdsRawKey);
+    w.raw_xyz = (uint32_t*)(b + kLdsRawXyz);
+    w.xyz = (uint32_t*)(b + kLdsXyz);
+    w.raw_idx = (uint16_t*)(b + kLdsRawIdx);
+    w.idx = (uint16_t*)(b + kLdsIdx);
+    return w;
+}
+
+// LDS positions of a staged footprint: the four segments as consecutive
+// 16-byte-aligned runs from `base`, each keeping its HBM alignment.
+__device__ __forceinline__ void tile_lds_at(TileGeo& G, int base)
+{
+    int off = base;
+    G.lds0 = off + (int)(G.st0 & 15);
+    off += ((int)(G.st0 & 15) + G.len0 + 15) & ~15;
+    G.lds1 = off + (int)(G.st1 & 15);
+    off += ((int)(G.st1 & 15) + G.len1 + 15) & ~15;
+    G.lds2 = off + (int)(G.st2 & 15);
+    off += ((int)(G.st2 & 15) + G.len2 + 15) & ~15;
+    G.lds3 = off + (int)(G.st3 & 15);
+}
+
+// LDS positions when the whole lattice sits in LDS at its storage offsets.
+__device__ __forceinline__ void tile_lds_resident(TileGeo& G)
+{
+    G.lds0 = (int)G.st0;
+    G.lds1 = (int)G.st1;
+    G.lds2 = (int)G.st2;
+    G.lds3 = (int)G.st3;
+}
+
+// 16-byte chunk counts of the four staged segments.
+__device__ __forceinline__ void seg_chunks(const TileGeo& G, int& n0, int& n1, int& n2, int& n3)
+{
+    n0 = ((int)(G.st0 & 15) + G.len0 + 15) >> 4;
+    n1 = ((int)(G.st1 & 15) + G.len1 + 15) >> 4;
+    n2 = ((int)(G.st2 & 15) + G.len2 + 15) >> 4;
+    n3 = ((int)(G.st3 & 15) + G.len3 + 15) >> 4;
+}
+
+// Chunk c of the concatenated segments: segment k and chunk index within it.
+__device__ __forceinline__ int locate_chunk(int c, int n0, int n1, int n2, int& cj)
+{
+    if (c < n0) { cj = c; return 0; }
+    c -= n0;
+    if (c < n1) { cj = c; return 1; }
+    c -= n1;
+    if (c < n2) { cj = c; return 2; }
+    cj = c - n2;
+    return 3;
+}
+
+// Local cell and type of local index li of footprint segment k.
+__device__ __forceinline__ void seg_site(const TileGeo& G, int k, int li, int& lx, int& ly, int& lz,
+                                         int& t)
+{
+    if (k == 0) {
+        const int V = G.wx * G.wy * G.wz;
+        t = li >= 2 * V ? 2 : (li >= V ? 1 : 0);
+        const int r = li - t * V;
+        const int inner = pick3(t, G.wy, G.wx, G.wx);  // fastest axis of the plane
+        const int mid = pick3(t, G.wz, G.wz, G.wy);
+        const int q1 = udiv22(r, inner);
+        const int u = r - q1 * inner;
+        const int w = udiv22(q1, mid);
+        const int v = q1 - w * mid;
+        if (t == 0) { ly = u; lz = v; lx = w; }       // (x wz + z) wy + y
+        else if (t == 1) { lx = u; lz = v; ly = w; }  // (y wz + z) wx + x
+        else { lx = u; ly = v; lz = w; }              // (z wy + y) wx + x
+    } else if (k == 1) {
+        t = 0; lx = G.wx; lz = udiv22(li, G.wy); ly = li - lz * G.wy;
+    } else if (k == 2) {
+        t = 1; ly = G.wy; lz = udiv22(li, G.wx); lx = li - lz * G.wx;
+    } else {
+        t = 2; lz = G.wz; ly = udiv22(li, G.wx); lx = li - ly * G.wx;
+    }
+}
+
+// Append a vacancy at local cell (lx,ly,lz), type t of tile G to slot list
+// `list` (entries [list*cap, list*cap + cap), counter cnt[ci]).
+__device__ __forceinline__ void put_slot(const WaveLds& W, const TileGeo& G, int L0, int L1, int L2,
+                                         int ci, int first, int cap, int lx, int ly, int lz, int t,
+                                         int vidx)
+{
+    int gi = G.ox + lx, gj = G.oy + ly, gk = G.oz + lz;
+    if (gi >= L0) gi -= L0;
+    if (gj >= L1) gj -= L1;
+    if (gk >= L2) gk -= L2;
+    const uint64_t key = ((((uint64_t)gk * L1 + gj) * L0 + gi) * 3) + t;
+    const int s = atomicAdd(&W.cnt[ci], 1);
+    if (s < cap) {
+        W.raw_key[first + s] = key;
+        W.raw_xyz[first + s] = pack_xyz(2 * lx + (t != 0), 2 * ly + (t != 1), 2 * lz + (t != 2));
+        W.raw_idx[first + s] = (uint16_t)vidx;
+    }
+}
+
+// Vacancies of the footprint of tile G staged in LDS (positions G.lds*):
+// every lane reads 16-byte chunks, and the rare chunk holding a vacancy
+// byte (the only code with bit 1 set) is examined byte by byte.
+__device__ __forceinline__ void scan_staged(const WaveLds& W, const TileGeo& G, const unsigned char* occl,
+                                            int L0, int L1, int L2, int ci, int first, int cap,
+                                            int lane)
+{
+    int n0, n1, n2, n3;
+    seg_chunks(G, n0, n1, n2, n3);
+    const int total = n0 + n1 + n2 + n3;
+    const int base = G.lds0 - (int)(G.st0 & 15);
+    for (int c = lane; c < total; c += 64) {
+        const uint4 v = *(const uint4*)(occl + base + 16 * c);
+        if (((v.x | v.y | v.z | v.w) & 0x02020202u) == 0) continue;
+        int cj;
+        const int k = locate_chunk(c, n0, n1, n2, cj);
+        const int al = (int)(seg_st(G, k) & 15);
+        const int len = seg_len(G, k);
+#pragma nounroll
+        for (int b = 0; b < 16; b++) {
+            const uint32_t w = b < 4 ? v.x : (b < 8 ? v.y : (b < 12 ? v.z : v.w));
+            if (((w >> (8 * (b & 3))) & 0xff) != kSpV) continue;
+            const int li = 16 * cj + b - al;
+            if (li < 0 || li >= len) continue;
+            int lx, ly, lz, t;
+            seg_site(G, k, li, lx, ly, lz, t);
+            put_slot(W, G, L0, L1, L2, ci, first, cap, lx, ly, lz, t, 0);
+        }
+    }
+}
+
+// Issue the 16-byte HBM->LDS copies of a tile's footprint straight into LDS
+// (no registers): wave instruction i fills chunks [64 i, 64 i + 64).
+__device__ __forceinline__ void stage_footprint(const TileGeo& G, const int8_t* occ_lat,
+                                                unsigned char* occl, int lane)
+{
+    int n0, n1, n2, n3;
+    seg_chunks(G, n0, n1, n2, n3);
+    const int total = n0 + n1 + n2 + n3;
+    const int base = __builtin_amdgcn_readfirstlane(G.lds0 - (int)(G.st0 & 15));
+    for (int c0 = 0; c0 < total; c0 += 64) {
+        const int c = c0 + lane;
+        if (c < total) {
+            int cj;
+            const int k = locate_chunk(c, n0, n1, n2, cj);
+            const int64_t st = seg_st(G, k);
+            const int8_t* src = occ_lat + (st - (st & 15)) + 16 * cj;
+            __builtin_amdgcn_global_load_lds(
+                (const void*)src, (__attribute__((address_space(3))) void*)(occl + base + 16 * c0), 16,
+                0, 0);
+        }
+    }
+}
+
+// Owner tile (fragment index) in colour c of the vacancy at global cell
+// (i,j,k), type t, or -1; c2s holds the sub-block index of every cell
+// (x cells, then y, then z).
+__device__ __forceinline__ int owner_tile(const unsigned char* c2s, int L0, int L1, int L2, int nf0,
+                                          int nf1, int colour, int i, int j, int k, int t)
+{
+    int sb0 = c2s[i], sb1 = c2s[L0 + j], sb2 = c2s[L0 + L1 + k];
+    const int col = (sb0 & 1) | ((sb1 & 1) << 1) | ((sb2 & 1) << 2);
+    if (col != colour) {
+        if ((col ^ (1 << t)) != colour) return -1;
+        // on the +t face of the sub-block below along t?
+        const int ct = t == 0 ? i : (t == 1 ? j : k);
+        const int Lt = t == 0 ? L0 : (t == 1 ? L1 : L2);
+        const int off = t == 0 ? 0 : (t == 1 ? L0 : L0 + L1);
+        const int sbt = t == 0 ? sb0 : (t == 1 ? sb1 : sb2);
+        const int prev = c2s[off + (ct == 0 ? Lt - 1 : ct - 1)];
+        if (prev == sbt) return -1;
+        if (t == 0) sb0 = prev;
+        else if (t == 1) sb1 = prev;
+        else sb2 = prev;
+    }
+    return (sb0 >> 1) + nf0 * ((sb1 >> 1) + nf1 * (sb2 >> 1));
+}
+
+// Resident lattice: the slots of the group's tiles (or of tile `only`) from
+// the LDS vacancy list (i | j << 10 | k << 20 | type << 30).
+__device__ __forceinline__ void collect_list(const WaveLds& W, const LatDesc& D, const uint32_t* vlist,
+                                             int nv, const unsigned char* c2s, int colour, int f0,
+                                             int nt, int only, int cap, int lane)
+{
+    for (int v = lane; v < nv; v += 64) {
+        const uint32_t g = vlist[v];
+        const int i = g & 1023, j = (g >> 10) & 1023, k = (g >> 20) & 1023, t = g >> 30;
+        const int f = owner_tile(c2s, D.L[0], D.L[1], D.L[2], D.nf[0], D.nf[1], colour, i, j, k, t);
+        const int q = f - f0;
+        if (f < 0 || q < 0 || q >= nt || (only >= 0 && q != only)) continue;
+        const TileGeo G = tile_geo_rec(W.rec[q]);
+        int lx = i - G.ox, ly = j - G.oy, lz = k - G.oz;
+        if (lx < 0) lx += D.L[0];
+        if (ly < 0) ly += D.L[1];
+        if (lz < 0) lz += D.L[2];
+        const int list = only >= 0 ? 8 : q;
+        put_slot(W, G, D.L[0], D.L[1], D.L[2], list, only >= 0 ? 0 : q * cap, cap, lx, ly, lz, t, v);
+    }
+}
+
+// Order n slots of list [first, first+n) by canonical key (keys distinct).
+__device__ __forceinline__ void sort_list(const WaveLds& W, int first, int n, int l)
+{
+    const uint64_t key = W.raw_key[first + l];
+    int rank = 0;
+    for (int j = 0; j < n; j++) rank += W.raw_key[first + j] < key;
+    W.xyz[first + rank] = W.raw_xyz[first + l];
+    W.idx[first + rank] = W.raw_idx[first + l];
+}
+
+// Resident lattice: final position of slot l of list `first` back to the list.
+__device__ __forceinline__ void list_update(const WaveLds& W, const TileGeo& G, const LatDesc& D,
+                                            uint32_t* vlist, int first, int l)
+{
+    const uint32_t xyz = W.xyz[first + l];
+    const int X = xyz & 1023, Y = (xyz >> 10) & 1023, Z = xyz >> 20;
+    const int t = site_type(X, Y);
+    int i = G.ox + (X >> 1), j = G.oy + (Y >> 1), k = G.oz + (Z >> 1);
+    if (i >= D.L[0]) i -= D.L[0];
+    if (j >= D.L[1]) j -= D.L[1];
+    if (k >= D.L[2]) k -= D.L[2];
+    vlist[W.idx[first + l]] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20) | ((uint32_t)t << 30);
+}
+
+// ----------------------------------------------------------------------------
+// Segmented wavefront primitives over segments of S consecutive lanes.
+//
+// Inclusive prefix sum of a binary64 value: DPP row_shr 1,2,4,8 inside each
+// 16-lane row (segments of 8 mask the moves that cross their start), then
+// row_bcast:15 / row_bcast:31 across rows.  The summands are exact multiples
+// of one power of two, so every association gives the same sum.
+template <int S>
+__device__ __forceinline__ double seg_scan(double v, int sl)
+{
+    double o = dpp_shifted<0x111, 0xF>(v);
+    v += (S >= 16 || sl >= 1) ? o : 0.0;
+    o = dpp_shifted<0x112, 0xF>(v);
+    v += (S >= 16 || sl >= 2) ? o : 0.0;
+    o = dpp_shifted<0x114, 0xF>(v);
+    v += (S >= 16 || sl >= 4) ? o : 0.0;
+    if (S >= 16) v += dpp_shifted<0x118, 0xF>(v);
+    if (S >= 32) v += dpp_shifted<0x142, 0xA>(v);
+    if (S >= 64) v += dpp_shifted<0x143, 0xC>(v);
+    return v;
+}
+
+// Value of lane `src` (any lane of the wave) for every lane; all lanes active.
+__device__ __forceinline__ int lane_pull(int v, int src)
+{
+    return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+
+__device__ __forceinline__ double lane_pull(double v, int src)
+{
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Wave-uniform parameters of one group of tiles (all of one lattice).
+struct GroupCall {
+    int8_t* occ;       // the lattice's occupancy in HBM (write-through when staged)
+    int4* disp;        // displacement buffer
+    int64_t disp_off;  // the lattice's first displacement index
+    uint32_t seed, lid, cycle, ctag;
+    double t_sync;
+    bool write_occ;
+};
+
+// ----------------------------------------------------------------------------
+// BKL on K tiles at once (Eqs. TransitionProb, eventSelection, TimeStep),
+// each until its next event would land after t_sync or no event is possible.
+// Tile `seg` runs on lanes [seg*S, seg*S + S), S = 64/K, with its n sorted
+// slots at sxyz (packed local coordinates), fragment index f, its own Philox
+// stream (step, f, cycle, ctag) and clock; event e = slot*8 + direction, in
+// that order.  With n <= S, each slot has G lanes (G = 8, 4, 2, 1 as n
+// allows), each caching the rates of 8/G consecutive events; K = 1 with
+// n > 64 recomputes the rates from LDS at every step.  After a hop only the
+// events whose vacancy moved or whose target changed are recomputed.
+template <int K>
+__device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, unsigned char* occl,
+                                          uint32_t* sxyz, int n, uint32_t f, const GroupCall& X,
+                                          int lane, Rec& rec, RecCtl& rc, uint32_t& ho, uint32_t& hh)
+{
+    constexpr int S = 64 / K;
+    const int sl = lane & (S - 1);
+    const int sb = lane & ~(S - 1);
+    const uint64_t segmask = S == 64 ? ~0ull : (((1ull << (S & 63)) - 1ull) << sb);
+    const bool cached = n <= S;
+    int lg = 0;  // log2 lanes per slot
+    if (cached && n > 0) lg = n * 8 <= S ? 3 : (n * 4 <= S ? 2 : (n * 2 <= S ? 1 : 0));
+    const int epl = 8 >> lg;
+    const int my_slot = sl >> lg;
+    const int my_d0 = (sl & ((1 << lg) - 1)) * epl;
+    const bool ev_valid = cached && my_slot < n;
+    uint32_t my_xyz = ev_valid ? sxyz[my_slot] : 0u;
+    // recompute mode (K == 1, n > 64): lane l covers slots [s0, s1)
     const int m = (n + 63) >> 6;
     const int s0 = lane * m < n ? lane * m : n;
     const int s1 = s0 + m < n ? s0 + m : n;
-    uint32_t my_xyz = ev_valid ? W.xyz[my_slot] : 0u;
     double kk[8];
 #pragma unroll
     for (int d = 0; d < 8; d++) kk[d] = 0.0;
     double ls = 0.0;
     auto refresh = [&]() {
         ls = 0.0;
+#pragma nounroll
+        for (int j = 0; j < epl; j++) {
+            const double r = tile_rate(G, occl, C, my_xyz, my_d0 + j);
+            ls += r;
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
-            if (j < epl) {
-                kk[j] = tile_rate(G_, occl, W.k12, D, my_xyz, my_d0 + j);
-                ls += kk[j];
-            }
+            for (int q = 0; q < 8; q++) kk[q] = q == j ? r : kk[q];
         }
     };
     if (ev_valid) refresh();
 
     double tau = 0.0;
     uint32_t step = 0;
+    bool active = n > 0;
     for (;;) {
-        if (mode == 2) {
+        if (__ballot(active) == 0) break;
+        if (K == 1 && !cached) {
             ls = 0.0;
             for (int s = s0; s < s1; s++) {
-                const uint32_t xyz = W.xyz[s];
-                for (int d = 0; d < 8; d++) ls += tile_rate(G_, occl, W.k12, D, xyz, d);
+                const uint32_t xyz = sxyz[s];
+                for (int d = 0; d < 8; d++) ls += tile_rate(G, occl, C, xyz, d);
             }
         }
-        const double incl = wave_scan_dpp(ls);
-        const double R = lane_value(incl, 63);
-        if (R == 0.0) break;
+        const double lsv = active ? ls : 0.0;
+        const double incl = seg_scan<S>(lsv, sl);
+        const double R = S == 64 ? lane_value(incl, 63) : lane_pull(incl, lane | (S - 1));
         uint32_t x0, x1, x2, x3;
-        philox10(step, f, cycle, (colour << 8) | 2u, D.seed, D.lattice_id, x0, x1, x2, x3);
+        philox10(step, f, X.cycle, X.ctag, X.seed, X.lid, x0, x1, x2, x3);
         const double u_sel = u53_lo(x0, x1);
         const double u_t = u53_hi(x2, x3);
         const double dt = -clock_ln(u_t) / R;
         const double tn = tau + dt;
-        if (tn > t_sync) break;
-        tau = tn;
+        const bool go = active && R != 0.0 && tn <= X.t_sync;
+        active = go;
+        if (go) tau = tn;
         const double y = u_sel * R;
-        const uint64_t mk = __ballot(incl > y);
-        int sel;
-        bool fallback = false;
-        if (mk) {
-            sel = __ffsll((unsigned long long)mk) - 1;
-        } else {
-            sel = 63 - __clzll((long long)__ballot(ls > 0.0));
-            fallback = true;
-        }
-        // pick = packed vacancy coordinates | direction << 29; slot index
+        const uint64_t mk = __ballot(go && incl > y) & segmask;
+        const uint64_t nz = __ballot(go && lsv > 0.0) & segmask;
+        const bool fb = mk == 0;
+        int sel = lane;
+        if (mk) sel = __ffsll((unsigned long long)mk) - 1;
+        else if (nz) sel = 63 - __clzll((long long)nz);
+        // the selected lane of each segment picks the event
         int pick = 0, pslot = 0;
-        if (lane == sel) {
-            double C = incl - ls;
+        if (go && lane == sel) {
+            double Cc = incl - lsv;
             int found = -1, last = -1;
-            if (mode == 1) {
+            if (cached) {
 #pragma unroll
                 for (int j = 0; j < 8; j++) {
                     if (j < epl) {
                         if (kk[j] > 0.0) last = j;
-                        C += kk[j];
-                        if (!fallback && found < 0 && C > y) found = j;
+                        Cc += kk[j];
+                        if (!fb && found < 0 && Cc > y) found = j;
                     }
                 }
                 pick = (int)(my_xyz | ((uint32_t)(my_d0 + (found >= 0 ? found : last)) << 29));
                 pslot = my_slot;
-            } else {
+            } else if (K == 1) {
                 uint32_t lx = 0;
                 for (int s = s0; s < s1 && found < 0; s++) {
-                    const uint32_t xyz = W.xyz[s];
+                    const uint32_t xyz = sxyz[s];
                     for (int d = 0; d < 8; d++) {
-                        const double k = tile_rate(G_, occl, W.k12, D, xyz, d);
+                        const double k = tile_rate(G, occl, C, xyz, d);
                         if (k > 0.0) { last = s * 8 + d; lx = xyz; }
-                        C += k;
-                        if (!fallback && C > y) { found = s * 8 + d; lx = xyz; break; }
+                        Cc += k;
+                        if (!fb && Cc > y) { found = s * 8 + d; lx = xyz; break; }
                     }
                 }
                 const int e = found >= 0 ? found : last;
@@ -680,213 +887,300 @@ __device__ __forceinline__ void tile_bkl(const TileGeo& G_, const WaveScratch& W
                 pslot = e >> 3;
             }
         }
-        pick = __builtin_amdgcn_readlane(pick, sel);
-        pslot = __builtin_amdgcn_readlane(pslot, sel);
+        if (S == 64) {
+            pick = __builtin_amdgcn_readlane(pick, sel);
+            pslot = __builtin_amdgcn_readlane(pslot, sel);
+        } else {
+            pick = lane_pull(pick, sel);
+            pslot = lane_pull(pslot, sel);
+        }
         const uint32_t sx = (uint32_t)pick & 0x1FFFFFFFu;
         const int d = (int)((uint32_t)pick >> 29);
         int hx, hy, hz;
         const uint32_t tx = hop_target_xyz(sx, d, hx, hy, hz);
-        int spos, tpos;
-        int64_t sst, tst;
-        xyz_where(G_, sx, spos, sst);
-        xyz_where(G_, tx, tpos, tst);
-        const int sp = occl[tpos];
+        int spos = 0, tpos = 0;
+        int64_t sst = 0, tst = 0;
+        int sp = 0;
+        if (go) {
+            xyz_where(G, sx, spos, sst);
+            xyz_where(G, tx, tpos, tst);
+            sp = occl[tpos];
+        }
         wave_lds_fence();
-        if (lane == 0) {
+        if (go && sl == 0) {
             occl[spos] = (unsigned char)sp;
             occl[tpos] = (unsigned char)kSpV;
-            W.xyz[pslot] = tx;
-            if (write_occ) {
-                occ_lat[sst] = (int8_t)sp;
-                occ_lat[tst] = (int8_t)kSpV;
+            sxyz[pslot] = tx;
+            if (X.write_occ) {
+                X.occ[sst] = (int8_t)sp;
+                X.occ[tst] = (int8_t)kSpV;
+            }
+            if (sp == kSpO) ho++;
+            else hh++;
+        }
+        // displacement records: the hops of this step one after another
+        uint64_t hm = __ballot(go && sl == 0);
+        if (hm) {
+            const int64_t ks_l = X.disp_off + sst, kt_l = X.disp_off + tst;
+            const int hp = (hx + 1) | ((hy + 1) << 2) | ((hz + 1) << 4);
+            while (hm) {
+                const int l = __ffsll((unsigned long long)hm) - 1;
+                hm &= hm - 1;
+                const int64_t ks = readlane64(ks_l, l), kt = readlane64(kt_l, l);
+                const int h = __builtin_amdgcn_readlane(hp, l);
+                rec_hop(rec, rc, X.disp, lane, ks, kt, (h & 3) - 1, ((h >> 2) & 3) - 1,
+                        ((h >> 4) & 3) - 1);
             }
         }
-        // particle records: the vacancy moves sx -> tx, the ion tx -> sx
-        uint64_t mv = __ballot(rv && r_cur == sx);
-        uint64_t mi = __ballot(rv && r_cur == tx);
-        if (nrec + (mv == 0) + (mi == 0) > 64) {
-            flush();
-            mv = 0;
-            mi = 0;
-        }
-        int lv, lion;
-        if (stores_pending && (mv == 0 || mi == 0)) {
-            __builtin_amdgcn_s_waitcnt(0x0F70);
-            __builtin_amdgcn_wave_barrier();
-            stores_pending = false;
-        }
-        if (mv) {
-            lv = __ffsll((unsigned long long)mv) - 1;
-        } else {
-            lv = nrec++;
-            if (lane == lv) open_record(sx);
-        }
-        if (mi) {
-            lion = __ffsll((unsigned long long)mi) - 1;
-        } else {
-            lion = nrec++;
-            if (lane == lion) open_record(tx);
-        }
-        if (lane == lv) { r_cur = tx; ax += hx; ay += hy; az += hz; }
-        if (lane == lion) { r_cur = sx; ax -= hx; ay -= hy; az -= hz; }
-        if (sp == kSpO) hops_o++;
-        else hops_h++;
-        step++;
+        step += go ? 1u : 0u;
         wave_lds_fence();
-        if (ev_valid) {
+        if (ev_valid && go) {
             if (my_slot == pslot) my_xyz = tx;
             if (my_slot == pslot || nn_site(my_xyz, sx) || nn_site(my_xyz, tx)) refresh();
         }
     }
-    flush();
 }
 
 // ----------------------------------------------------------------------------
-// Lockstep phase kernel: one wave per tile of colour `colour`, every
-// fragment lattice of the set, footprint staged HBM -> LDS.
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_phase(DevPtrs P, int colour)
+// One wave runs nt <= K tiles of colour `colour` of one lattice: fragments
+// f0 .. f0+nt-1.  Streamed lattices stage their footprints from HBM into LDS
+// at lds0 + fp (fps bytes apart); resident lattices find their slots in the
+// LDS vacancy list.  The tiles run together, one per S = 64/K-lane segment;
+// a tile with more vacancies than S runs afterwards on the whole wave.
+// With `single`, every tile runs on the whole wave, one after another, and
+// a streamed lattice stages one footprint at a time.
+template <int K>
+__device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, int f0, int nt, int colour,
+                                          const GroupCall& X, const WaveLds& W, unsigned char* lds0,
+                                          int fp, int fps, bool resident, bool single, uint32_t* vlist,
+                                          int nv, const unsigned char* c2s, int lane, Rec& rec,
+                                          RecCtl& rc, uint32_t& ho, uint32_t& hh, bool& err)
+{
+    constexpr int S = 64 / K;
+    const int seg = lane / S, sl = lane & (S - 1);
+    const TileRec* trec = P.tiles + (size_t)colour * P.n_tiles + D.tile0 + f0;
+    if (lane < nt) W.rec[lane] = trec[lane];
+    if (lane < 16) W.cnt[lane] = 0;
+    if (lane < 12) W.k12[lane] = D.k12[lane];
+    wave_lds_fence();
+    const RateCtx C = {D.L[0], D.L[1], D.L[2], D.gb_period, D.gb_mask, W.k12};
+    int n_seg = 0;
+    if (!single) {
+        if (resident) {
+            collect_list(W, D, vlist, nv, c2s, colour, f0, nt, -1, S, lane);
+        } else {
+            for (int k = 0; k < nt; k++) {
+                TileGeo T = tile_geo_rec(W.rec[k]);
+                tile_lds_at(T, fp + k * fps);
+                stage_footprint(T, X.occ, lds0, lane);
+            }
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the staged footprints have landed
+            __builtin_amdgcn_wave_barrier();
+            for (int k = 0; k < nt; k++) {
+                TileGeo T = tile_geo_rec(W.rec[k]);
+                tile_lds_at(T, fp + k * fps);
+                scan_staged(W, T, lds0, D.L[0], D.L[1], D.L[2], k, k * S, S, lane);
+            }
+        }
+        wave_lds_fence();
+        // this lane's tile
+        TileGeo G = tile_geo_rec(W.rec[seg < nt ? seg : 0]);
+        if (resident) tile_lds_resident(G);
+        else tile_lds_at(G, fp + seg * fps);
+        n_seg = seg < nt ? W.cnt[seg] : 0;
+        if (n_seg <= S && sl < n_seg) sort_list(W, seg * S, n_seg, sl);
+        wave_lds_fence();
+        const int n_run = n_seg <= S ? n_seg : 0;
+        group_bkl<K>(G, C, lds0, W.xyz + seg * S, n_run, (uint32_t)(f0 + seg), X, lane, rec, rc, ho, hh);
+        wave_lds_fence();
+        if (resident && sl < n_run) list_update(W, G, D, vlist, seg * S, sl);
+    }
+    // tiles run on the whole wave: those that did not fit their segment, or all
+    uint64_t todo = single ? (nt >= 64 ? ~0ull : ((1ull << nt) - 1ull))
+                           : __ballot(sl == 0 && n_seg > S);
+    while (todo) {
+        wave_lds_fence();
+        const int b = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int q = single ? b : b / S;
+        if (lane == 0) W.cnt[8] = 0;
+        TileGeo T = tile_geo_rec(W.rec[q]);
+        if (resident) {
+            tile_lds_resident(T);
+            wave_lds_fence();
+            collect_list(W, D, vlist, nv, c2s, colour, f0, nt, q, 128, lane);
+        } else {
+            tile_lds_at(T, fp + (single ? 0 : q) * fps);
+            if (single) {
+                stage_footprint(T, X.occ, lds0, lane);
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+                __builtin_amdgcn_wave_barrier();
+            }
+            wave_lds_fence();
+            scan_staged(W, T, lds0, D.L[0], D.L[1], D.L[2], 8, 0, 128, lane);
+        }
+        wave_lds_fence();
+        const int n1 = W.cnt[8];
+        if (n1 > 128) {
+            err = true;
+            continue;
+        }
+        for (int l = lane; l < n1; l += 64) sort_list(W, 0, n1, l);
+        wave_lds_fence();
+        group_bkl<1>(T, C, lds0, W.xyz, n1, (uint32_t)(f0 + q), X, lane, rec, rc, ho, hh);
+        wave_lds_fence();
+        if (resident)
+            for (int l = lane; l < n1; l += 64) list_update(W, T, D, vlist, 0, l);
+    }
+    wave_lds_fence();
+}
+
+// ----------------------------------------------------------------------------
+// Lockstep phase kernel: one wave per group of K tiles of colour `colour`
+// (P.groups: lattice and first fragment), footprints staged HBM -> LDS.
+template <int K>
+__global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colour)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const int tile = blockIdx.x * WAVES + wv;
-    if (tile >= P.n_tiles) return;
-    const int lat = P.n_lat == 1 ? 0 : P.tile2lat[tile];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wv);
+    if (g >= P.n_groups) return;
+    const int2 gr = P.groups[g];
+    const int lat = __builtin_amdgcn_readfirstlane(gr.x);
+    const int f0 = __builtin_amdgcn_readfirstlane(gr.y);
     const LatDesc& D = P.desc[lat];
-    LatState* S = P.state + lat;
-    if (S->done) return;
-    const uint32_t cycle = (uint32_t)S->cycles;
-    const double t_sync = P.call[lat].t_sync;
-    const WaveScratch W = wave_scratch(smem + wv * P.lds_wave_bytes);
-    const int f = tile - D.tile0;
-    TileGeo G = tile_geo_rec(P.tiles[(size_t)colour * P.n_tiles + tile]);
-    tile_lds_private(G);
-    if (lane == 0) *W.cnt = 0;
-    if (lane < 12) W.k12[lane] = D.k12[lane];
-    wave_lds_fence();
-    collect_slots(G, D, W, (const unsigned char*)(P.occ + D.occ_off), lane, true);
-    wave_lds_fence();
-    const int n = *W.cnt;
-    if (n == 0) return;
-    if (n > kMaxSlots) {
-        if (lane == 0) atomicOr(&S->err, 1u);
-        return;
-    }
-    sort_slots(W, n, lane);
-    wave_lds_fence();
+    LatState* St = P.state + lat;
+    if (St->done) return;
+    const int ntiles = D.nf[0] * D.nf[1] * D.nf[2];
+    constexpr int KG = K == 1 ? 8 : K;  // K = 1: tiles one after another
+    const int nt = ntiles - f0 < K ? ntiles - f0 : K;
+    GroupCall X;
+    X.occ = P.occ + D.occ_off;
+    X.disp = P.disp;
+    X.disp_off = D.disp_off;
+    X.seed = D.seed;
+    X.lid = D.lattice_id;
+    X.cycle = (uint32_t)St->cycles;
+    X.ctag = ((uint32_t)colour << 8) | 2u;
+    X.t_sync = P.call[lat].t_sync;
+    X.write_occ = true;
+    unsigned char* base = smem + wv * P.lds_wave_bytes;
+    const WaveLds W = wave_lds(base);
+    Rec rec;
+    RecCtl rc;
+    rec_init(rec, rc);
     uint32_t ho = 0, hh = 0;
-    bool pending = false;
-    tile_bkl(G, W, W.occ, D, P.occ + D.occ_off, P.disp + D.disp_off, (uint32_t)f, cycle,
-             (uint32_t)colour, t_sync, n, lane, ho, hh, true, pending);
-    if (lane == 0 && (ho | hh)) {
+    bool err = false;
+    run_group<KG>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratch, P.fp_stride,
+                  false, K == 1, nullptr, 0, nullptr, lane, rec, rc, ho, hh, err);
+    rec_flush(rec, rc, P.disp);
+    constexpr int S = K == 1 ? 64 : 64 / K;
+    if ((lane & (S - 1)) == 0 && (ho | hh)) {
+        const int f = f0 + lane / S;
         unsigned long long* b = P.buckets + ((size_t)lat * kHopBuckets + (f & (kHopBuckets - 1))) * 2;
         if (ho) atomicAdd(b, (unsigned long long)ho);
         if (hh) atomicAdd(b + 1, (unsigned long long)hh);
     }
+    if (__ballot(err) && lane == 0) atomicOr(&St->err, 1u);
 }
 
 // Persistent batched kernel: one workgroup per lattice runs the whole call
 // (cycles of 8 phases, workgroup barrier between phases), so every lattice
 // advances at its own pace.  A lattice that fits is kept in LDS for the
-// whole call; otherwise each wave stages its tile's footprint from HBM.
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_batch(DevPtrs P)
+// whole call with a list of its vacancies; otherwise each wave stages its
+// tiles' footprints from HBM.  Each wave runs groups of D.group tiles.  A
+// lattice whose phase is one group runs on wave 0 alone, without barriers,
+// and keeps its displacement records across phases.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_batch(DevPtrs P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ unsigned long long hop_tot[2];
+    __shared__ int vlist_n;
     const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
     const int lat = P.batch_ids[blockIdx.x];
     const LatDesc& D = P.desc[lat];
-    LatState* S = P.state + lat;
-    const LatCall* C = P.call + lat;
+    LatState* St = P.state + lat;
+    const LatCall* Cl = P.call + lat;
     const bool resident = D.resident != 0;
-    unsigned char* slab = smem;
-    const WaveScratch W = wave_scratch(smem + P.lds_resident_bytes + wv * P.lds_wave_bytes);
+    const int K = D.group;
+    unsigned char* region = smem;
+    const WaveLds W = wave_lds(smem + P.lds_region_bytes + wv * kWaveScratch);
     int8_t* occ_lat = P.occ + D.occ_off;
-    int4* disp_lat = P.disp + D.disp_off;
     const int64_t nbytes = D.n_sites;
-    __shared__ int vlist_n;
-    uint32_t* vlist = (uint32_t*)(slab + (((nbytes + 15) & ~(int64_t)15) + 32));
+    // resident slab: occupancy, vacancy list, cell -> sub-block maps
+    uint32_t* vlist = (uint32_t*)(region + ((nbytes + 15) & ~(int64_t)15));
+    unsigned char* c2s = (unsigned char*)(vlist + ((D.n_vac + 3) & ~3));
     if (threadIdx.x == 0) vlist_n = 0;
     if (resident) {
         const int nch = (int)((nbytes + 15) >> 4);
         for (int j = threadIdx.x; j < nch; j += blockDim.x)
-            ((uint4*)slab)[j] = ((const uint4*)occ_lat)[j];
+            ((uint4*)region)[j] = ((const uint4*)occ_lat)[j];
+        const int32_t* m = P.c2s + D.c2s_off;
+        for (int j = threadIdx.x; j < D.L[0] + D.L[1] + D.L[2]; j += blockDim.x)
+            c2s[j] = (unsigned char)m[j];
     }
     __syncthreads();
     if (resident) {
-        // vacancy list, scanned in canonical order
         for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
             const int t = (int)(c % 3);
             const int64_t cell = c / 3;
             const int i = (int)(cell % D.L[0]);
             const int j = (int)((cell / D.L[0]) % D.L[1]);
             const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-            if (slab[store_index(D, P.bounds, P.c2s, i, j, k, t)] != kSpV) continue;
+            if (region[store_index(D, P.bounds, P.c2s, i, j, k, t)] != kSpV) continue;
             const int v = atomicAdd(&vlist_n, 1);
             if (v < D.n_vac)
                 vlist[v] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20) | ((uint32_t)t << 30);
         }
     }
     if (threadIdx.x < 2) hop_tot[threadIdx.x] = 0;
-    if (lane < 12) W.k12[lane] = D.k12[lane];
     __syncthreads();
     const int nv_list = vlist_n < D.n_vac ? vlist_n : D.n_vac;
     bool err = resident && vlist_n > D.n_vac;
-    const double t_sync = C->t_sync;
-    const uint64_t max_cycles = C->max_cycles, min_hops = C->min_hops;
-    const uint64_t cycle0 = S->cycles;
+    GroupCall X;
+    X.occ = occ_lat;
+    X.disp = P.disp;
+    X.disp_off = D.disp_off;
+    X.seed = D.seed;
+    X.lid = D.lattice_id;
+    X.t_sync = Cl->t_sync;
+    X.write_occ = !resident;
+    const uint64_t max_cycles = Cl->max_cycles, min_hops = Cl->min_hops;
+    const uint64_t cycle0 = St->cycles;
     const int ntiles = D.nf[0] * D.nf[1] * D.nf[2];
-    // A lattice with one tile per colour is run by wave 0 alone, without
-    // workgroup barriers; otherwise every phase ends with one.
-    const bool solo = ntiles == 1;
-    bool pending = false;
+    const int ngroups = (ntiles + K - 1) / K;
+    const bool solo = ngroups == 1;
+    unsigned char* occl = resident ? region : smem;
+    const int fp = resident ? 0 : wv * (K == 1 ? 1 : K) * D.fp_stride;
+    Rec rec;
+    RecCtl rc;
+    rec_init(rec, rc);
     uint64_t ncyc = 0;
     if (!solo || wv == 0) {
         while (ncyc < max_cycles) {
-            const uint32_t cycle = (uint32_t)(cycle0 + ncyc);
+            X.cycle = (uint32_t)(cycle0 + ncyc);
             for (int colour = 0; colour < 8; colour++) {
+                X.ctag = ((uint32_t)colour << 8) | 2u;
                 uint32_t ho = 0, hh = 0;
-                for (int f = wv; f < ntiles; f += nw) {
-                    TileGeo G = tile_geo_rec(P.tiles[(size_t)colour * P.n_tiles + D.tile0 + f]);
-                    if (lane == 0) *W.cnt = 0;
-                    wave_lds_fence();
-                    unsigned char* occl = resident ? slab : W.occ;
-                    if (resident) {
-                        tile_lds_resident(G);
-                        collect_from_list(G, D, W, vlist, nv_list, lane);
-                    } else {
-                        tile_lds_private(G);
-                        collect_slots(G, D, W, (const unsigned char*)occ_lat, lane, true);
-                    }
-                    wave_lds_fence();
-                    const int n = *W.cnt;
-                    if (n == 0) continue;
-                    if (n > kMaxSlots) {
-                        err = true;
-                        continue;
-                    }
-                    sort_slots(W, n, lane);
-                    wave_lds_fence();
-                    tile_bkl(G, W, occl, D, occ_lat, disp_lat, (uint32_t)f, cycle, (uint32_t)colour,
-                             t_sync, n, lane, ho, hh, !resident, pending);
-                    if (resident) {
-                        wave_lds_fence();
-                        update_list(G, D, W, vlist, n, lane);
-                    }
+                for (int g = wv; g < ngroups; g += nw) {
+                    const int f0 = g * K;
+                    const int nt = ntiles - f0 < K ? ntiles - f0 : K;
+                    run_group<8>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
+                                 vlist, nv_list, c2s, lane, rec, rc, ho, hh, err);
                 }
-                if (lane == 0 && (ho | hh)) {
-                    atomicAdd(&hop_tot[0], (unsigned long long)ho);
-                    atomicAdd(&hop_tot[1], (unsigned long long)hh);
-                }
+                // per-lane counts of segment leaders to the workgroup totals
+                if (ho) atomicAdd(&hop_tot[0], (unsigned long long)ho);
+                if (hh) atomicAdd(&hop_tot[1], (unsigned long long)hh);
                 if (solo) {
                     wave_lds_fence();
                 } else {
+                    rec_flush(rec, rc, P.disp);
                     __syncthreads();
-                    pending = false;  // the barrier waited for every store
+                    rc.pending = false;  // the barrier waited for every store
                 }
             }
             ncyc++;
@@ -895,19 +1189,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             if (min_hops > 0 && tot >= min_hops) break;
         }
     }
+    rec_flush(rec, rc, P.disp);
     __syncthreads();
     if (resident) {
         const int nch = (int)(nbytes >> 4);
         for (int j = threadIdx.x; j < nch; j += blockDim.x)
-            ((uint4*)occ_lat)[j] = ((const uint4*)slab)[j];
+            ((uint4*)occ_lat)[j] = ((const uint4*)region)[j];
         for (int64_t b = (int64_t)nch * 16 + threadIdx.x; b < nbytes; b += blockDim.x)
-            occ_lat[b] = (int8_t)slab[b];
+            occ_lat[b] = (int8_t)region[b];
     }
-    if (err && lane == 0) atomicOr(&S->err, 1u);
+    if (__ballot(err) && lane == 0) atomicOr(&St->err, 1u);
     if (threadIdx.x == 0) {
-        S->busy_ticks = __builtin_amdgcn_s_memrealtime() - t_begin;
-        S->cycles = cycle0 + ncyc;
-        S->done = 1u;
+        St->busy_ticks = __builtin_amdgcn_s_memrealtime() - t_begin;
+        St->cycles = cycle0 + ncyc;
+        St->done = 1u;
         unsigned long long* b = P.buckets + (size_t)lat * kHopBuckets * 2;
         b[0] += hop_tot[0];
         b[1] += hop_tot[1];
@@ -1260,6 +1555,7 @@ __global__ void k_scatter(DevPtrs P, int lat, const int8_t* occ_c)
     P.disp[D.disp_off + s] = make_int4(0, 0, 0, 0);
 }
 
+
 // ----------------------------------------------------------------------------
 // Launchers.
 int launch_init(const DevPtrs& P, const uint64_t* d_counts, int n_lat, void* stream)
@@ -1270,24 +1566,48 @@ int launch_init(const DevPtrs& P, const uint64_t* d_counts, int n_lat, void* str
     return (int)hipGetLastError();
 }
 
-int launch_phase(const DevPtrs& P, int colour, int lds_per_wave, void* stream)
+using PhaseFn = void (*)(DevPtrs, int);
+
+static PhaseFn phase_fn(int group)
 {
-    if (P.n_tiles == 0) return 0;
-    if (4 * lds_per_wave <= kMaxLdsPerBlock) {
-        const int blocks = (P.n_tiles + 3) / 4;
-        hipLaunchKernelGGL(k_phase<4>, dim3(blocks), dim3(256), (size_t)lds_per_wave * 4,
-                           (hipStream_t)stream, P, colour);
-    } else {
-        hipLaunchKernelGGL(k_phase<1>, dim3(P.n_tiles), dim3(64), (size_t)lds_per_wave,
-                           (hipStream_t)stream, P, colour);
-    }
+    return group == 8 ? k_phase<8> : (group == 4 ? k_phase<4> : (group == 2 ? k_phase<2> : k_phase<1>));
+}
+
+// Allow the lockstep workgroup's dynamic LDS beyond the default 64 KB.
+static hipError_t phase_lds_attr(int group, size_t lds)
+{
+    static size_t granted[9] = {0};
+    if (lds <= 65536 || lds <= granted[group]) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)phase_fn(group),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) granted[group] = lds;
+    return e;
+}
+
+// Waves per lockstep workgroup: kPhaseWaves while their LDS stays below
+// 64 KB (every staged footprint then has an LDS address below 2^16), else 1.
+static int phase_waves(const DevPtrs& P)
+{
+    return (size_t)P.lds_wave_bytes * kPhaseWaves <= 65536 ? kPhaseWaves : 1;
+}
+
+int launch_phase(const DevPtrs& P, int colour, int group, void* stream)
+{
+    if (P.n_groups == 0) return 0;
+    const int wpb = phase_waves(P);
+    const size_t lds = (size_t)P.lds_wave_bytes * wpb;
+    hipError_t e = phase_lds_attr(group, lds);
+    if (e != hipSuccess) return (int)e;
+    const int blocks = (P.n_groups + wpb - 1) / wpb;
+    hipLaunchKernelGGL(phase_fn(group), dim3(blocks), dim3(64 * wpb), lds, (hipStream_t)stream, P,
+                       colour);
     return (int)hipGetLastError();
 }
 
 int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream)
 {
     if (n_batch == 0) return 0;
-    const size_t lds = (size_t)P.lds_resident_bytes + (size_t)waves * P.lds_wave_bytes;
+    const size_t lds = (size_t)P.lds_region_bytes + (size_t)waves * kWaveScratch;
     hipError_t e = hipFuncSetAttribute((const void*)k_batch,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return (int)e;
@@ -1298,29 +1618,31 @@ int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream)
 // A graph of `cycles` consecutive lockstep cycles (8 phase kernels and the
 // cycle-end kernel each, chained), built from kernel nodes so that it can be
 // launched on any stream.  Holds no memset or copy nodes.
-int build_cycle_graph(const DevPtrs& P, int lds_per_wave, int cycles, hipGraphExec_t* out)
+int build_cycle_graph(const DevPtrs& P, int group, int cycles, hipGraphExec_t* out)
 {
+    const int wpb = phase_waves(P);
+    const size_t lds = (size_t)P.lds_wave_bytes * wpb;
+    hipError_t e = phase_lds_attr(group, lds);
+    if (e != hipSuccess) return (int)e;
     hipGraph_t g;
-    hipError_t e = hipGraphCreate(&g, 0);
+    e = hipGraphCreate(&g, 0);
     if (e != hipSuccess) return (int)e;
     DevPtrs args_p = P;  // argument values are copied into each node
     hipGraphNode_t prev = nullptr;
-    const bool four = 4 * lds_per_wave <= kMaxLdsPerBlock;
     int colours[8] = {0, 1, 2, 3, 4, 5, 6, 7};
     int begin0 = 0;
     for (int c = 0; c < cycles && e == hipSuccess; c++) {
         for (int col = 0; col < 9 && e == hipSuccess; col++) {
             hipKernelNodeParams kp = {};
             void* argv[3];
+            argv[0] = &args_p;
             if (col < 8) {
-                argv[0] = &args_p;
                 argv[1] = &colours[col];
-                kp.func = four ? (void*)k_phase<4> : (void*)k_phase<1>;
-                kp.gridDim = four ? dim3((P.n_tiles + 3) / 4) : dim3(P.n_tiles);
-                kp.blockDim = four ? dim3(256) : dim3(64);
-                kp.sharedMemBytes = (unsigned)(lds_per_wave * (four ? 4 : 1));
+                kp.func = (void*)phase_fn(group);
+                kp.gridDim = dim3((P.n_groups + wpb - 1) / wpb);
+                kp.blockDim = dim3(64 * wpb);
+                kp.sharedMemBytes = (unsigned)lds;
             } else {
-                argv[0] = &args_p;
                 argv[1] = &begin0;
                 kp.func = (void*)k_cycle;
                 kp.gridDim = dim3(P.n_lat);
@@ -1409,10 +1731,10 @@ int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_o
     return (int)hipGetLastError();
 }
 
-int phase_lds_per_wave(int max_footprint_bytes)
+int footprint_stride(int max_footprint_bytes)
 {
-    // footprint segments each padded to 16 bytes, plus alignment slack
-    return scratch_bytes() + ((max_footprint_bytes + 4 * 32 + 15) & ~15);
+    // four segments, each padded to whole 16-byte chunks from its alignment
+    return (max_footprint_bytes + 4 * 30 + 15) & ~15;
 }
 
 }  // namespace fkmc

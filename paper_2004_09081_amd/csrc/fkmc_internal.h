@@ -38,7 +38,9 @@ struct LatDesc {
     int32_t plain;
     int32_t resident;     // persistent kernel keeps the whole lattice in LDS
     int32_t n_vac;        // vacancies (conserved), sizes the resident vacancy list
-    int32_t pad0;
+    int32_t group;        // persistent kernel: tiles one wave runs at once (1, 4 or 8)
+    int32_t fp_stride;    // persistent kernel: LDS bytes of one staged footprint
+    int32_t pad1;
     uint32_t seed;
     uint32_t lattice_id;
     int32_t gb_period;
@@ -75,7 +77,7 @@ struct LatState {
 
 // Geometry of one tile (sub-block of one colour of one fragment), built on
 // the host: origin and width per axis, and the storage offsets of the four
-// footprint segments (brick, +x face, +y face, +z face).
+// footprint segments (brick, +x face, +y face, +z face).  48 bytes.
 struct TileRec {
     int64_t st[4];
     uint16_t ox, oy, oz;
@@ -98,13 +100,21 @@ struct DevPtrs {
     int32_t n_lat;
     int32_t n_tiles;               // fragment-mode tiles per colour, all lattices
     const int32_t* batch_ids;      // lattices run by the persistent kernel
-    int32_t lds_resident_bytes;    // LDS slab for a resident lattice (persistent kernel)
-    int32_t lds_wave_bytes;        // per-wave LDS scratch (footprint + slots)
+    const int2* groups;            // lockstep kernel: (lattice, first fragment) per wave
+    int32_t n_groups;
+    int32_t fp_stride;             // LDS bytes of one staged footprint
+    int32_t lds_region_bytes;      // persistent kernel: resident slab or staged footprints
+    int32_t lds_wave_bytes;        // lockstep kernel: per-wave scratch plus footprints
 };
+
+// Per-wave LDS scratch of both fragment kernels (slot lists, tile records,
+// rate table); staged footprints come after it.
+constexpr int kWaveScratch = 3104;
+constexpr int kPhaseWaves = 2;     // waves per lockstep workgroup
 
 // Kernel launchers (fkmc_device.hip).  All return a hipError_t value.
 int launch_init(const DevPtrs& P, const uint64_t* d_counts, int n_lat, void* stream);
-int launch_phase(const DevPtrs& P, int colour, int lds_per_wave, void* stream);
+int launch_phase(const DevPtrs& P, int colour, int group, void* stream);
 int launch_cycle_begin(const DevPtrs& P, void* stream);
 int launch_cycle_end(const DevPtrs& P, void* stream);
 int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void* stream);
@@ -114,11 +124,11 @@ int launch_gather(const DevPtrs& P, int lat, int64_t n_sites, int8_t* d_occ_cano
 int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_occ_canon,
                    void* stream);
 int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream);
-int build_cycle_graph(const DevPtrs& P, int lds_per_wave, int cycles, hipGraphExec_t* out);
+int build_cycle_graph(const DevPtrs& P, int group, int cycles, hipGraphExec_t* out);
 int launch_scatter_disp(const DevPtrs& P, int lat, int64_t n_sites, const int32_t* d_disp_canon,
                         void* stream);
-// LDS bytes one wave needs: slot scratch, plus a footprint copy when the
-// lattice is not resident.
-int phase_lds_per_wave(int max_footprint_bytes);
+// LDS bytes of one staged footprint of at most max_footprint_bytes sites
+// (four 16-byte-aligned segments).
+int footprint_stride(int max_footprint_bytes);
 
 }  // namespace fkmc

@@ -142,7 +142,7 @@ def features(specs) -> np.ndarray:
     return np.stack([surrogate_features(s) for s in specs]).astype(np.float64)
 
 
-def kmc_labels(specs, hop_target: int = 0, waves: int = 8, cycles: int = 0):
+def kmc_labels(specs, hop_target: int = 0, waves: int = 4, cycles: int = 0):
     """Run the lattices as one batched set (to hop_target hops each, or for
     a fixed number of synchronisation cycles) and return log10 D (m^2/s) of
     O and H with validity masks (at least MIN_HOPS hops of that species)."""

@@ -252,6 +252,32 @@ def test_schedules_match_oracle(schedule, waves):
         assert_same_state(g, i, lat, "%s/%d member %d" % (schedule, waves, i))
 
 
+# a dense lattice whose single tile overflows 8 and 16 slots
+GROUP_CASES = SCHED_CASES + [FRAG_CASES["dense_vac"]]
+
+
+@pytest.mark.parametrize("schedule,group", [("lockstep", 8), ("lockstep", 4), ("lockstep", 2),
+                                            ("lockstep", 1), ("persistent", 8), ("persistent", 1)])
+def test_tile_groups_match_oracle(schedule, group):
+    """Every tile-group size (tiles per wavefront), including tiles whose
+    vacancies overflow their segment's slots and run on the whole
+    wavefront, reproduces the oracle bit for bit."""
+    say("tile group parity", schedule, group)
+    lats = [c.oracle() for c in GROUP_CASES]
+    ts = [1.5 / (8.0 * l.k12[0]) for l in lats]
+    for lat, t in zip(lats, ts):
+        lat.advance(t, max_cycles=3)
+    g = gpu_set(GROUP_CASES)
+    g.set_schedule(schedule, 4)
+    g.set_group(group)
+    g.advance(ts, max_cycles=3)
+    stats = g.read_stats()
+    for i, lat in enumerate(lats):
+        assert stats[i]["cycles"] == lat.cycles and stats[i]["t"] == lat.t
+        assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops]
+        assert_same_state(g, i, lat, "%s/group %d member %d" % (schedule, group, i))
+
+
 def test_schedule_rejects_oversized_workgroup():
     from paper_2004_09081_amd import fkmc as F
     g = gpu_set(SCHED_CASES[1:3])
