@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-DEFAULT_CANDIDATES = (4, 6, 8, 12, 16, 24)
+DEFAULT_CANDIDATES = (4, 6, 8, 12, 16, 24, 64)
 
 
 def trial(specs, F, ts, cycles: int, waves: int):

@@ -718,7 +718,9 @@ static double mean_footprint_vacancies(const fkmc_lattice* L, uint32_t i)
 static fkmc_status prepare_lockstep(fkmc_lattice* L)
 {
     if (L->phase_group) return FKMC_OK;
-    int g = 8;
+    // at most 4: eight staged footprints per wave cost more occupancy than
+    // the shared steps save (measured on the 600^3 sweep)
+    int g = 4;
     for (int32_t i : L->batch_ids)
         g = std::min(g, pick_group(mean_footprint_vacancies(L, i), L->fp_stride, 32768 - kWaveScratch, true));
     if (L->group_override) g = L->group_override;
@@ -782,7 +784,7 @@ static fkmc_status prepare_call(fkmc_lattice* L, const double* t_sync, uint64_t 
 static fkmc_status plan_batch(fkmc_lattice* L)
 {
     const int waves = L->batch_waves;
-    const int bound = L->lds_budget - waves * kWaveScratch - 64;
+    const int bound = L->lds_budget - waves * kWaveScratch - kRecCache - 64;
     int region = 0;
     for (int32_t i : L->batch_ids) {
         LatDesc& D = L->desc[i];
@@ -794,6 +796,11 @@ static fkmc_status plan_batch(fkmc_lattice* L)
         for (int a = 0; a < 3; a++) small = small && D.nsb[a] <= 255 && g.L[a] <= 1023;
         D.n_vac = (int32_t)L->n_vac[i];
         D.resident = small ? 1 : 0;
+        // one fragment, in LDS, at most 32 vacancies: a block of lanes per vacancy
+        D.fast = small && !L->group_override && D.nf[0] == 1 && D.nf[1] == 1 && D.nf[2] == 1 &&
+                         L->n_vac[i] <= 32
+                     ? 1
+                     : 0;
         const int fps = footprint_stride((int)max_footprint(g));
         D.fp_stride = fps;
         if (L->group_override) {
@@ -804,12 +811,13 @@ static fkmc_status plan_batch(fkmc_lattice* L)
                 return fail(FKMC_E_UNSUPPORTED, "lattice %d: %d waves need %lld bytes of LDS", (int)i,
                             waves, (long long)waves * fps + waves * kWaveScratch);
         } else if (small) {
-            D.group = pick_group(lam, 0, 0, false);
+            // a lattice of fewer than 4 tiles per colour runs them one by one
+            D.group = D.nf[0] * D.nf[1] * D.nf[2] < 4 ? 1 : pick_group(lam, 0, 0, false);
             region = std::max<int>(region, (int)slab);
         } else {
             // staged footprints keep LDS addresses below 2^16
             const int area = std::min(bound, 65536);
-            D.group = pick_group(lam, fps, area / waves, false);
+            D.group = D.nf[0] * D.nf[1] * D.nf[2] < 4 ? 1 : pick_group(lam, fps, area / waves, false);
             if ((int64_t)waves * D.group * fps > area)
                 return fail(FKMC_E_UNSUPPORTED, "lattice %d: %d waves need %lld bytes of LDS", (int)i,
                             waves, (long long)waves * fps + waves * kWaveScratch);

@@ -49,10 +49,10 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
 {
 #pragma unroll
     for (int r = 0; r < 10; r++) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -224,22 +224,19 @@ struct TileGeo {
     int len0, len1, len2, len3;
 };
 
-// One of three or four register values by a runtime index.  The empty asm
-// makes the operands plain registers, so that the selection is never
-// turned into an indexed load from a private copy of the struct.
+// One of three or four values by a runtime index.  The operands are
+// values (not struct lvalues), so the selection stays a register select
+// and never becomes an indexed load from a private copy of the struct.
 __device__ __forceinline__ int pick3(int k, int a, int b, int c)
 {
-    asm volatile("" : "+v"(a), "+v"(b), "+v"(c));
     return k == 0 ? a : (k == 1 ? b : c);
 }
 __device__ __forceinline__ int pick4(int k, int a, int b, int c, int d)
 {
-    asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
     return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
 }
 __device__ __forceinline__ int64_t pick4(int k, int64_t a, int64_t b, int64_t c, int64_t d)
 {
-    asm volatile("" : "+v"(a), "+v"(b), "+v"(c), "+v"(d));
     return k == 0 ? a : (k == 1 ? b : (k == 2 ? c : d));
 }
 
@@ -454,18 +451,11 @@ __device__ __forceinline__ void rec_hop(Rec& r, RecCtl& c, int4* disp, int lane,
             r.old = disp[kt];
         }
     }
-    if (lane == lv) {
-        r.cur = kt;
-        r.ax += hx;
-        r.ay += hy;
-        r.az += hz;
-    }
-    if (lane == li) {
-        r.cur = ks;
-        r.ax -= hx;
-        r.ay -= hy;
-        r.az -= hz;
-    }
+    const int sv = lane == lv ? 1 : (lane == li ? -1 : 0);
+    r.cur = lane == lv ? kt : (lane == li ? ks : r.cur);
+    r.ax += sv * hx;
+    r.ay += sv * hy;
+    r.az += sv * hz;
 }
 
 // ----------------------------------------------------------------------------
@@ -619,10 +609,15 @@ __device__ __forceinline__ void scan_staged(const WaveLds& W, const TileGeo& G, 
         const int k = locate_chunk(c, n0, n1, n2, cj);
         const int al = (int)(seg_st(G, k) & 15);
         const int len = seg_len(G, k);
-#pragma nounroll
-        for (int b = 0; b < 16; b++) {
-            const uint32_t w = b < 4 ? v.x : (b < 8 ? v.y : (b < 12 ? v.z : v.w));
-            if (((w >> (8 * (b & 3))) & 0xff) != kSpV) continue;
+        // bit b of m: byte b holds a vacancy (the product gathers bit 1 of
+        // the four bytes of a word into its top nibble)
+        uint32_t m = (((v.x >> 1) & 0x01010101u) * 0x10204080u) >> 28;
+        m |= ((((v.y >> 1) & 0x01010101u) * 0x10204080u) >> 28) << 4;
+        m |= ((((v.z >> 1) & 0x01010101u) * 0x10204080u) >> 28) << 8;
+        m |= ((((v.w >> 1) & 0x01010101u) * 0x10204080u) >> 28) << 12;
+        while (m) {
+            const int b = __ffs(m) - 1;
+            m &= m - 1;
             const int li = 16 * cj + b - al;
             if (li < 0 || li >= len) continue;
             int lx, ly, lz, t;
@@ -681,9 +676,9 @@ __device__ __forceinline__ int owner_tile(const unsigned char* c2s, int L0, int 
 
 // Resident lattice: the slots of the group's tiles (or of tile `only`) from
 // the LDS vacancy list (i | j << 10 | k << 20 | type << 30).
-__device__ __forceinline__ void collect_list(const WaveLds& W, const LatDesc& D, const uint32_t* vlist,
-                                             int nv, const unsigned char* c2s, int colour, int f0,
-                                             int nt, int only, int cap, int lane)
+__device__ __forceinline__ void collect_list(const WaveLds& W, const TileRec* R, const LatDesc& D,
+                                             const uint32_t* vlist, int nv, const unsigned char* c2s,
+                                             int colour, int f0, int nt, int only, int cap, int lane)
 {
     for (int v = lane; v < nv; v += 64) {
         const uint32_t g = vlist[v];
@@ -691,7 +686,7 @@ __device__ __forceinline__ void collect_list(const WaveLds& W, const LatDesc& D,
         const int f = owner_tile(c2s, D.L[0], D.L[1], D.L[2], D.nf[0], D.nf[1], colour, i, j, k, t);
         const int q = f - f0;
         if (f < 0 || q < 0 || q >= nt || (only >= 0 && q != only)) continue;
-        const TileGeo G = tile_geo_rec(W.rec[q]);
+        const TileGeo G = tile_geo_rec(R[q]);
         int lx = i - G.ox, ly = j - G.oy, lz = k - G.oz;
         if (lx < 0) lx += D.L[0];
         if (ly < 0) ly += D.L[1];
@@ -898,14 +893,13 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         const int d = (int)((uint32_t)pick >> 29);
         int hx, hy, hz;
         const uint32_t tx = hop_target_xyz(sx, d, hx, hy, hz);
-        int spos = 0, tpos = 0;
-        int64_t sst = 0, tst = 0;
-        int sp = 0;
-        if (go) {
-            xyz_where(G, sx, spos, sst);
-            xyz_where(G, tx, tpos, tst);
-            sp = occl[tpos];
-        }
+        // (a segment without a hop has pick 0: local site (0,0,0), inside
+        // its footprint, so these addresses are valid either way)
+        int spos, tpos;
+        int64_t sst, tst;
+        xyz_where(G, sx, spos, sst);
+        xyz_where(G, tx, tpos, tst);
+        const int sp = occl[tpos];
         wave_lds_fence();
         if (go && sl == 0) {
             occl[spos] = (unsigned char)sp;
@@ -953,38 +947,43 @@ template <int K>
 __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, int f0, int nt, int colour,
                                           const GroupCall& X, const WaveLds& W, unsigned char* lds0,
                                           int fp, int fps, bool resident, bool single, uint32_t* vlist,
-                                          int nv, const unsigned char* c2s, int lane, Rec& rec,
-                                          RecCtl& rc, uint32_t& ho, uint32_t& hh, bool& err)
+                                          int nv, const unsigned char* c2s, const TileRec* cached,
+                                          int lane, Rec& rec, RecCtl& rc, uint32_t& ho, uint32_t& hh,
+                                          bool& err)
 {
     constexpr int S = 64 / K;
     const int seg = lane / S, sl = lane & (S - 1);
-    const TileRec* trec = P.tiles + (size_t)colour * P.n_tiles + D.tile0 + f0;
-    if (lane < nt) W.rec[lane] = trec[lane];
+    // tile records: an LDS cache of the whole call, or copied for this group
+    const TileRec* R = cached;
+    if (!cached) {
+        const TileRec* trec = P.tiles + (size_t)colour * P.n_tiles + D.tile0 + f0;
+        if (lane < nt) W.rec[lane] = trec[lane];
+        R = W.rec;
+    }
     if (lane < 16) W.cnt[lane] = 0;
-    if (lane < 12) W.k12[lane] = D.k12[lane];
     wave_lds_fence();
     const RateCtx C = {D.L[0], D.L[1], D.L[2], D.gb_period, D.gb_mask, W.k12};
     int n_seg = 0;
     if (!single) {
         if (resident) {
-            collect_list(W, D, vlist, nv, c2s, colour, f0, nt, -1, S, lane);
+            collect_list(W, R, D, vlist, nv, c2s, colour, f0, nt, -1, S, lane);
         } else {
             for (int k = 0; k < nt; k++) {
-                TileGeo T = tile_geo_rec(W.rec[k]);
+                TileGeo T = tile_geo_rec(R[k]);
                 tile_lds_at(T, fp + k * fps);
                 stage_footprint(T, X.occ, lds0, lane);
             }
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the staged footprints have landed
             __builtin_amdgcn_wave_barrier();
             for (int k = 0; k < nt; k++) {
-                TileGeo T = tile_geo_rec(W.rec[k]);
+                TileGeo T = tile_geo_rec(R[k]);
                 tile_lds_at(T, fp + k * fps);
                 scan_staged(W, T, lds0, D.L[0], D.L[1], D.L[2], k, k * S, S, lane);
             }
         }
         wave_lds_fence();
         // this lane's tile
-        TileGeo G = tile_geo_rec(W.rec[seg < nt ? seg : 0]);
+        TileGeo G = tile_geo_rec(R[seg < nt ? seg : 0]);
         if (resident) tile_lds_resident(G);
         else tile_lds_at(G, fp + seg * fps);
         n_seg = seg < nt ? W.cnt[seg] : 0;
@@ -1004,11 +1003,11 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
         todo &= todo - 1;
         const int q = single ? b : b / S;
         if (lane == 0) W.cnt[8] = 0;
-        TileGeo T = tile_geo_rec(W.rec[q]);
+        TileGeo T = tile_geo_rec(R[q]);
         if (resident) {
             tile_lds_resident(T);
             wave_lds_fence();
-            collect_list(W, D, vlist, nv, c2s, colour, f0, nt, q, 128, lane);
+            collect_list(W, R, D, vlist, nv, c2s, colour, f0, nt, q, 128, lane);
         } else {
             tile_lds_at(T, fp + (single ? 0 : q) * fps);
             if (single) {
@@ -1039,7 +1038,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
 // Lockstep phase kernel: one wave per group of K tiles of colour `colour`
 // (P.groups: lattice and first fragment), footprints staged HBM -> LDS.
 template <int K>
-__global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colour)
+__global__ __launch_bounds__(64 * kPhaseWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_phase(DevPtrs P, int colour)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
@@ -1072,8 +1071,9 @@ __global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colou
     rec_init(rec, rc);
     uint32_t ho = 0, hh = 0;
     bool err = false;
+    if (lane < 12) W.k12[lane] = D.k12[lane];
     run_group<KG>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratch, P.fp_stride,
-                  false, K == 1, nullptr, 0, nullptr, lane, rec, rc, ho, hh, err);
+                  false, K == 1, nullptr, 0, nullptr, nullptr, lane, rec, rc, ho, hh, err);
     rec_flush(rec, rc, P.disp);
     constexpr int S = K == 1 ? 64 : 64 / K;
     if ((lane & (S - 1)) == 0 && (ho | hh)) {
@@ -1083,6 +1083,233 @@ __global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colou
         if (hh) atomicAdd(b + 1, (unsigned long long)hh);
     }
     if (__ballot(err) && lane == 0) atomicOr(&St->err, 1u);
+}
+
+// ----------------------------------------------------------------------------
+// Single-fragment lattices held in LDS, with at most 32 vacancies: the
+// sub-blocks are the two halves of the lattice along each axis (lower half
+// ceil(L/2) cells), one tile per colour, and one wave runs everything.
+// A block of lanes owns each vacancy for the whole call (packed doubled
+// coordinates) and caches the rates of its 8 events; the occupancy sits in
+// LDS in canonical site order.  In each phase the slot order of the BKL
+// domain is the canonical order of the vacancies at phase start: every lane
+// computes its vacancy's rank once per phase, and each step moves the lane
+// totals into event order (ds_permute) before the prefix sum.  Vacancies outside the
+// phase's footprint have no active edge and contribute zero rates, which
+// changes no partial sum and no selection.
+
+__device__ __forceinline__ uint32_t pack_dbl(int X, int Y, int Z)
+{
+    return (uint32_t)X | ((uint32_t)Y << 11) | ((uint32_t)Z << 22);
+}
+
+// Canonical index of the site at doubled coordinates (X, Y, Z).
+__device__ __forceinline__ int canon_dbl(int L0, int L1, int X, int Y, int Z)
+{
+    return (((Z >> 1) * L1 + (Y >> 1)) * L0 + (X >> 1)) * 3 + site_type(X, Y);
+}
+
+// Storage offset of canonical cell (i,j,k), type t, when the lattice is one
+// fragment (sub-block bounds 0, ceil(L/2), L per axis).
+__device__ __forceinline__ int store_index_1f(int L0, int L1, int L2, int i, int j, int k, int t)
+{
+    const int h0 = (L0 + 1) >> 1, h1 = (L1 + 1) >> 1, h2 = (L2 + 1) >> 1;
+    const int x0 = i >= h0 ? h0 : 0, y0 = j >= h1 ? h1 : 0, z0 = k >= h2 ? h2 : 0;
+    const int wx = i >= h0 ? L0 - h0 : h0, wy = j >= h1 ? L1 - h1 : h1, wz = k >= h2 ? L2 - h2 : h2;
+    const int base = 3 * (z0 * L1 * L0 + wz * (y0 * L0 + wy * x0));
+    return base + brick_local(t, i - x0, j - y0, k - z0, wx, wy, wz);
+}
+
+__device__ __forceinline__ int store_dbl_1f(int L0, int L1, int L2, int X, int Y, int Z)
+{
+    return store_index_1f(L0, L1, L2, X >> 1, Y >> 1, Z >> 1, site_type(X, Y));
+}
+
+// Rate of event d of the vacancy at doubled coordinates (X,Y,Z) in phase
+// `colour`: zero unless the edge's owner cell (the cell of its midpoint)
+// lies in the sub-block of that colour and the target holds an ion.
+__device__ __forceinline__ double fast_rate(const RateCtx& C, const unsigned char* slab, int colour,
+                                            int X, int Y, int Z, int d)
+{
+    const int t = site_type(X, Y);
+    int hx, hy, hz;
+    hop_vec(t, d, hx, hy, hz);
+    int ox = (2 * X + hx) >> 2, oy = (2 * Y + hy) >> 2, oz = (2 * Z + hz) >> 2;
+    if (ox < 0) ox += C.L0;
+    if (oy < 0) oy += C.L1;
+    if (oz < 0) oz += C.L2;
+    const int col = (ox >= ((C.L0 + 1) >> 1) ? 1 : 0) | (oy >= ((C.L1 + 1) >> 1) ? 2 : 0) |
+                    (oz >= ((C.L2 + 1) >> 1) ? 4 : 0);
+    if (col != colour) return 0.0;
+    int TX = X + hx, TY = Y + hy, TZ = Z + hz;
+    if (TX < 0) TX += 2 * C.L0;
+    if (TX >= 2 * C.L0) TX -= 2 * C.L0;
+    if (TY < 0) TY += 2 * C.L1;
+    if (TY >= 2 * C.L1) TY -= 2 * C.L1;
+    if (TZ < 0) TZ += 2 * C.L2;
+    if (TZ >= 2 * C.L2) TZ -= 2 * C.L2;
+    const int sp = slab[canon_dbl(C.L0, C.L1, TX, TY, TZ)];
+    if (sp == kSpV) return 0.0;
+    int g = 0;
+    if (C.gbp > 0) {
+        const int tt = site_type(TX, TY);
+        g = gb_flag(C, t, pick3(t, X >> 1, Y >> 1, Z >> 1)) |
+            gb_flag(C, tt, pick3(tt, TX >> 1, TY >> 1, TZ >> 1));
+    }
+    return C.k12[(sp * 3 + hz + 1) * 2 + g];
+}
+
+// Periodic nearest neighbours (doubled coordinates differ by 1 on two axes).
+__device__ __forceinline__ bool nn_dbl(int L0, int L1, int L2, uint32_t a, uint32_t b)
+{
+    int dx = (int)(a & 2047) - (int)(b & 2047);
+    int dy = (int)((a >> 11) & 2047) - (int)((b >> 11) & 2047);
+    int dz = (int)(a >> 22) - (int)(b >> 22);
+    dx = dx < 0 ? -dx : dx;
+    dy = dy < 0 ? -dy : dy;
+    dz = dz < 0 ? -dz : dz;
+    if (dx == 2 * L0 - 1) dx = 1;
+    if (dy == 2 * L1 - 1) dy = 1;
+    if (dz == 2 * L2 - 1) dz = 1;
+    return dx * dx + dy * dy + dz * dz == 2;
+}
+
+// Runs the call's cycles on wave 0.  vlist holds the nv vacancies
+// (i | j << 10 | k << 20 | t << 30); slab the canonical occupancy.  Each
+// vacancy has G lanes (G = 8, 4, 2, 1 for nv <= 8, 16, 32, 64), lane q of
+// its block caching the rates of directions [q*8/G, (q+1)*8/G).  The draws
+// of a phase are computed ahead, one step per lane, 64 at a time.
+__device__ __forceinline__ void solo_fast(const LatDesc& D, unsigned char* slab, const uint32_t* vlist,
+                                          int nv, const RateCtx& C, GroupCall& X, uint64_t max_cycles,
+                                          uint64_t min_hops, uint64_t cycle0, int lane, uint64_t& ncyc,
+                                          unsigned long long& ho_tot, unsigned long long& hh_tot,
+                                          Rec& rec, RecCtl& rc)
+{
+    const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
+    const int lg = nv <= 8 ? 3 : (nv <= 16 ? 2 : (nv <= 32 ? 1 : 0));  // log2 G
+    const int G = 1 << lg, epl = 8 >> lg;
+    const int v = lane >> lg, q = lane & (G - 1), d0 = q * epl;
+    const bool valid = v < nv;
+    uint32_t pos = 0;
+    if (valid) {
+        const uint32_t g = vlist[v];
+        const int i = g & 1023, j = (g >> 10) & 1023, k = (g >> 20) & 1023, t = g >> 30;
+        pos = pack_dbl(2 * i + (t != 0), 2 * j + (t != 1), 2 * k + (t != 2));
+    }
+    double kk[8];
+#pragma unroll
+    for (int d = 0; d < 8; d++) kk[d] = 0.0;
+    double tot = 0.0;
+    int colour = 0;
+    auto rates = [&]() {
+        tot = 0.0;
+        const int Xs = pos & 2047, Ys = (pos >> 11) & 2047, Zs = pos >> 22;
+#pragma nounroll
+        for (int j = 0; j < epl; j++) {
+            const double r = fast_rate(C, slab, colour, Xs, Ys, Zs, d0 + j);
+            tot += r;
+#pragma unroll
+            for (int u = 0; u < 8; u++) kk[u] = u == j ? r : kk[u];
+        }
+    };
+    unsigned long long ho = 0, hh = 0;
+    while (ncyc < max_cycles) {
+        X.cycle = (uint32_t)(cycle0 + ncyc);
+        for (colour = 0; colour < 8; colour++) {
+            const uint32_t ctag = ((uint32_t)colour << 8) | 2u;
+            // slot order: canonical order of the vacancies at phase start
+            const int Xs = pos & 2047, Ys = (pos >> 11) & 2047, Zs = pos >> 22;
+            const int key = valid ? canon_dbl(L0, L1, Xs, Ys, Zs) : 0x7fffffff;
+            int rank = 0;
+            for (int j = 0; j < nv; j++) rank += (__builtin_amdgcn_readlane(key, j << lg) < key) ? 1 : 0;
+            const int dst = valid ? ((rank << lg) | q) : lane;  // unused lanes keep their place
+            const int inv = __builtin_amdgcn_ds_permute(dst << 2, lane);  // source lane of each place
+            if (valid) rates();
+            double tau = 0.0;
+            uint32_t step = 0;
+            double dr_sel = 0.0, dr_ln = 0.0;  // draw of step (step & ~63) + lane
+            for (;;) {
+                if ((step & 63) == 0) {
+                    uint32_t x0, x1, x2, x3;
+                    philox10(step + (uint32_t)lane, 0u, X.cycle, ctag, X.seed, X.lid, x0, x1, x2, x3);
+                    dr_sel = u53_lo(x0, x1);
+                    dr_ln = clock_ln(u53_hi(x2, x3));
+                }
+                const int lo = __builtin_amdgcn_ds_permute(dst << 2, __double2loint(tot));
+                const int hi = __builtin_amdgcn_ds_permute(dst << 2, __double2hiint(tot));
+                const double srt = __hiloint2double(hi, lo);  // lane totals in event order
+                const double incl = wave_scan_dpp(srt);
+                const double R = lane_value(incl, 63);
+                if (R == 0.0) break;
+                const int sl = (int)(step & 63);
+                const double u_sel = lane_value(dr_sel, sl);
+                const double dt = -lane_value(dr_ln, sl) / R;
+                const double tn = tau + dt;
+                if (tn > X.t_sync) break;
+                tau = tn;
+                const double y = u_sel * R;
+                const uint64_t mk = __ballot(incl > y);
+                int r;
+                bool fb = false;
+                if (mk) {
+                    r = __ffsll((unsigned long long)mk) - 1;
+                } else {
+                    r = 63 - __clzll((long long)__ballot(srt > 0.0));
+                    fb = true;
+                }
+                const int owner = __builtin_amdgcn_readlane(inv, r);
+                const double c0 = lane_value(incl, r) - lane_value(srt, r);
+                int dsel = 0;
+                if (lane == owner) {
+                    double cc = c0;
+                    int found = -1, last = -1;
+#pragma unroll
+                    for (int j = 0; j < 8; j++) {
+                        if (j < epl) {
+                            if (kk[j] > 0.0) last = j;
+                            cc += kk[j];
+                            if (!fb && found < 0 && cc > y) found = j;
+                        }
+                    }
+                    dsel = d0 + (found >= 0 ? found : last);
+                }
+                const int d = __builtin_amdgcn_readlane(dsel, owner);
+                const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)pos, owner);
+                const int SX = sx & 2047, SY = (sx >> 11) & 2047, SZ = sx >> 22;
+                int hx, hy, hz;
+                hop_vec(site_type(SX, SY), d, hx, hy, hz);
+                int TX = SX + hx, TY = SY + hy, TZ = SZ + hz;
+                if (TX < 0) TX += 2 * L0;
+                if (TX >= 2 * L0) TX -= 2 * L0;
+                if (TY < 0) TY += 2 * L1;
+                if (TY >= 2 * L1) TY -= 2 * L1;
+                if (TZ < 0) TZ += 2 * L2;
+                if (TZ >= 2 * L2) TZ -= 2 * L2;
+                const uint32_t tx = pack_dbl(TX, TY, TZ);
+                const int cs = canon_dbl(L0, L1, SX, SY, SZ), ct = canon_dbl(L0, L1, TX, TY, TZ);
+                const int sp = slab[ct];
+                wave_lds_fence();
+                if (lane == 0) {
+                    slab[cs] = (unsigned char)sp;
+                    slab[ct] = (unsigned char)kSpV;
+                }
+                const bool mover = valid && (lane >> lg) == (owner >> lg);
+                if (mover) pos = tx;
+                if (sp == kSpO) ho++;
+                else hh++;
+                rec_hop(rec, rc, X.disp, lane, X.disp_off + store_dbl_1f(L0, L1, L2, SX, SY, SZ),
+                        X.disp_off + store_dbl_1f(L0, L1, L2, TX, TY, TZ), hx, hy, hz);
+                step++;
+                wave_lds_fence();
+                if (valid && (mover || nn_dbl(L0, L1, L2, pos, sx) || nn_dbl(L0, L1, L2, pos, tx)))
+                    rates();
+            }
+        }
+        ncyc++;
+        if (min_hops > 0 && ho + hh >= min_hops) break;
+    }
+    ho_tot = ho;
+    hh_tot = hh;
 }
 
 // Persistent batched kernel: one workgroup per lattice runs the whole call
@@ -1115,7 +1342,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     uint32_t* vlist = (uint32_t*)(region + ((nbytes + 15) & ~(int64_t)15));
     unsigned char* c2s = (unsigned char*)(vlist + ((D.n_vac + 3) & ~3));
     if (threadIdx.x == 0) vlist_n = 0;
-    if (resident) {
+    const bool fast = D.fast != 0;
+    if (resident && fast) {
+        // canonical order
+        for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
+            const int t = (int)(c % 3);
+            const int64_t cell = c / 3;
+            const int i = (int)(cell % D.L[0]);
+            const int j = (int)((cell / D.L[0]) % D.L[1]);
+            const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
+            region[c] = (unsigned char)occ_lat[store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)];
+        }
+    } else if (resident) {
         const int nch = (int)((nbytes + 15) >> 4);
         for (int j = threadIdx.x; j < nch; j += blockDim.x)
             ((uint4*)region)[j] = ((const uint4*)occ_lat)[j];
@@ -1131,13 +1369,22 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             const int i = (int)(cell % D.L[0]);
             const int j = (int)((cell / D.L[0]) % D.L[1]);
             const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-            if (region[store_index(D, P.bounds, P.c2s, i, j, k, t)] != kSpV) continue;
+            if (region[fast ? c : store_index(D, P.bounds, P.c2s, i, j, k, t)] != kSpV) continue;
             const int v = atomicAdd(&vlist_n, 1);
             if (v < D.n_vac)
                 vlist[v] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20) | ((uint32_t)t << 30);
         }
     }
     if (threadIdx.x < 2) hop_tot[threadIdx.x] = 0;
+    if (lane < 12) W.k12[lane] = D.k12[lane];
+    const int ntiles = D.nf[0] * D.nf[1] * D.nf[2];
+    const int ngroups = (ntiles + K - 1) / K;
+    const bool solo = ngroups == 1;
+    // a lattice run by one wave keeps every colour's tile records in LDS
+    TileRec* rcache = (TileRec*)(smem + P.lds_region_bytes + nw * kWaveScratch);
+    if (solo)
+        for (int j = threadIdx.x; j < 8 * ntiles; j += blockDim.x)
+            rcache[j] = P.tiles[(size_t)(j / ntiles) * P.n_tiles + D.tile0 + j % ntiles];
     __syncthreads();
     const int nv_list = vlist_n < D.n_vac ? vlist_n : D.n_vac;
     bool err = resident && vlist_n > D.n_vac;
@@ -1151,16 +1398,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     X.write_occ = !resident;
     const uint64_t max_cycles = Cl->max_cycles, min_hops = Cl->min_hops;
     const uint64_t cycle0 = St->cycles;
-    const int ntiles = D.nf[0] * D.nf[1] * D.nf[2];
-    const int ngroups = (ntiles + K - 1) / K;
-    const bool solo = ngroups == 1;
     unsigned char* occl = resident ? region : smem;
     const int fp = resident ? 0 : wv * (K == 1 ? 1 : K) * D.fp_stride;
     Rec rec;
     RecCtl rc;
     rec_init(rec, rc);
     uint64_t ncyc = 0;
-    if (!solo || wv == 0) {
+    if (fast) {
+        if (wv == 0) {
+            const RateCtx C = {D.L[0], D.L[1], D.L[2], D.gb_period, D.gb_mask, W.k12};
+            unsigned long long fo = 0, fh = 0;
+            solo_fast(D, region, vlist, nv_list, C, X, max_cycles, min_hops, cycle0, lane, ncyc, fo, fh, rec,
+                      rc);
+            if (lane == 0) {
+                hop_tot[0] = fo;
+                hop_tot[1] = fh;
+            }
+        }
+    } else if (!solo || wv == 0) {
         while (ncyc < max_cycles) {
             X.cycle = (uint32_t)(cycle0 + ncyc);
             for (int colour = 0; colour < 8; colour++) {
@@ -1170,7 +1425,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                     const int f0 = g * K;
                     const int nt = ntiles - f0 < K ? ntiles - f0 : K;
                     run_group<8>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
-                                 vlist, nv_list, c2s, lane, rec, rc, ho, hh, err);
+                                 vlist, nv_list, c2s, solo ? rcache + colour * ntiles : nullptr, lane,
+                                 rec, rc, ho, hh, err);
                 }
                 // per-lane counts of segment leaders to the workgroup totals
                 if (ho) atomicAdd(&hop_tot[0], (unsigned long long)ho);
@@ -1191,7 +1447,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     rec_flush(rec, rc, P.disp);
     __syncthreads();
-    if (resident) {
+    if (resident && fast) {
+        for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
+            const int t = (int)(c % 3);
+            const int64_t cell = c / 3;
+            const int i = (int)(cell % D.L[0]);
+            const int j = (int)((cell / D.L[0]) % D.L[1]);
+            const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
+            occ_lat[store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)] = (int8_t)region[c];
+        }
+    } else if (resident) {
         const int nch = (int)(nbytes >> 4);
         for (int j = threadIdx.x; j < nch; j += blockDim.x)
             ((uint4*)occ_lat)[j] = ((const uint4*)region)[j];
@@ -1607,7 +1872,7 @@ int launch_phase(const DevPtrs& P, int colour, int group, void* stream)
 int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream)
 {
     if (n_batch == 0) return 0;
-    const size_t lds = (size_t)P.lds_region_bytes + (size_t)waves * kWaveScratch;
+    const size_t lds = (size_t)P.lds_region_bytes + (size_t)waves * kWaveScratch + kRecCache;
     hipError_t e = hipFuncSetAttribute((const void*)k_batch,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return (int)e;

@@ -40,7 +40,7 @@ struct LatDesc {
     int32_t n_vac;        // vacancies (conserved), sizes the resident vacancy list
     int32_t group;        // persistent kernel: tiles one wave runs at once (1, 4 or 8)
     int32_t fp_stride;    // persistent kernel: LDS bytes of one staged footprint
-    int32_t pad1;
+    int32_t fast;         // persistent kernel: one fragment, resident, <= 64 vacancies
     uint32_t seed;
     uint32_t lattice_id;
     int32_t gb_period;
@@ -111,6 +111,7 @@ struct DevPtrs {
 // rate table); staged footprints come after it.
 constexpr int kWaveScratch = 3104;
 constexpr int kPhaseWaves = 2;     // waves per lockstep workgroup
+constexpr int kRecCache = 8 * 8 * 48;  // persistent kernel: tile records of a one-group lattice
 
 // Kernel launchers (fkmc_device.hip).  All return a hipError_t value.
 int launch_init(const DevPtrs& P, const uint64_t* d_counts, int n_lat, void* stream);

@@ -278,6 +278,45 @@ def test_tile_groups_match_oracle(schedule, group):
         assert_same_state(g, i, lat, "%s/group %d member %d" % (schedule, group, i))
 
 
+# one fragment, held in LDS, at most 32 vacancies: a block of lanes per vacancy
+# (the 64-vacancy members take the tile path)
+FAST_CASES = [
+    Case((12, 10, 8), (12, 10, 8), seed=31, lattice_id=0, nv=20, nh=30, T=650.0, Ea_O=0.55,
+         Ea_H=0.5, E_z=2e8, gb_period=3, gb_mask=5, gb_dE=0.08),
+    Case((2, 2, 2), (2, 2, 2), seed=31, lattice_id=1, nv=3, nh=2, T=600.0, Ea_H=0.55),
+    Case((9, 7, 5), (16, 16, 16), seed=31, lattice_id=2, nv=40, nh=10, T=700.0, Ea_O=0.6,
+         Ea_H=0.45),
+    Case((16, 16, 16), (16, 16, 16), seed=31, lattice_id=3, nv=64, nh=300, T=500.0, Ea_O=0.5,
+         Ea_H=0.35),
+    Case((5, 6, 7), (5, 6, 7), seed=31, lattice_id=4, nv=64, nh=0, T=600.0),
+    Case((11, 3, 4), (20, 20, 20), seed=31, lattice_id=5, nv=1, nh=5, T=800.0, Ea_H=0.4),
+]
+
+
+@pytest.mark.parametrize("min_hops", [0, 1500])
+def test_single_fragment_lattices_match_oracle(min_hops):
+    """Single-fragment lattices held in LDS with a block of lanes per
+    vacancy (the persistent schedule's path for up to 32 vacancies), odd
+    sizes, L = 2, field and boundary planes on two axes: the oracle's
+    trajectories bit for bit, over several calls, with and without a hop
+    target."""
+    say("single-fragment parity", min_hops)
+    lats = [c.oracle() for c in FAST_CASES]
+    ts = [1.3 / (8.0 * l.k12[0]) for l in lats]
+    g = gpu_set(FAST_CASES)
+    g.set_schedule("persistent", 4)
+    for rep in range(2):
+        for lat, t in zip(lats, ts):
+            lat.advance(t, max_cycles=10**6 if min_hops else 5, min_hops=min_hops)
+        g.advance(ts, max_cycles=10**6 if min_hops else 5, min_hops=min_hops)
+        stats = g.read_stats()
+        for i, lat in enumerate(lats):
+            assert stats[i]["lds_resident"]
+            assert stats[i]["cycles"] == lat.cycles and stats[i]["t"] == lat.t, (i, rep)
+            assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops], (i, rep)
+            assert_same_state(g, i, lat, "single-fragment member %d rep %d" % (i, rep))
+
+
 def test_schedule_rejects_oversized_workgroup():
     from paper_2004_09081_amd import fkmc as F
     g = gpu_set(SCHED_CASES[1:3])
