@@ -221,7 +221,6 @@ struct TileGeo {
     int ox, oy, oz;  // global cell of local cell (0,0,0)
     int64_t st0, st1, st2, st3;
     int lds0, lds1, lds2, lds3;
-    int len0, len1, len2, len3;
 };
 
 // One of three or four values by a runtime index.  The operands are
@@ -249,9 +248,10 @@ __device__ __forceinline__ int seg_lds(const TileGeo& G, int k)
 {
     return pick4(k, G.lds0, G.lds1, G.lds2, G.lds3);
 }
+// Sites of footprint segment k: the brick, then the three faces.
 __device__ __forceinline__ int seg_len(const TileGeo& G, int k)
 {
-    return pick4(k, G.len0, G.len1, G.len2, G.len3);
+    return pick4(k, 3 * G.wx * G.wy * G.wz, G.wy * G.wz, G.wz * G.wx, G.wy * G.wx);
 }
 
 __device__ __forceinline__ TileGeo tile_geo_rec(const TileRec& R)
@@ -267,10 +267,6 @@ __device__ __forceinline__ TileGeo tile_geo_rec(const TileRec& R)
     G.st1 = R.st[1];
     G.st2 = R.st[2];
     G.st3 = R.st[3];
-    G.len0 = 3 * G.wx * G.wy * G.wz;
-    G.len1 = G.wy * G.wz;
-    G.len2 = G.wz * G.wx;
-    G.len3 = G.wy * G.wx;
     G.lds0 = G.lds1 = G.lds2 = G.lds3 = 0;
     return G;
 }
@@ -508,11 +504,11 @@ __device__ __forceinline__ void tile_lds_at(TileGeo& G, int base)
 {
     int off = base;
     G.lds0 = off + (int)(G.st0 & 15);
-    off += ((int)(G.st0 & 15) + G.len0 + 15) & ~15;
+    off += ((int)(G.st0 & 15) + seg_len(G, 0) + 15) & ~15;
     G.lds1 = off + (int)(G.st1 & 15);
-    off += ((int)(G.st1 & 15) + G.len1 + 15) & ~15;
+    off += ((int)(G.st1 & 15) + seg_len(G, 1) + 15) & ~15;
     G.lds2 = off + (int)(G.st2 & 15);
-    off += ((int)(G.st2 & 15) + G.len2 + 15) & ~15;
+    off += ((int)(G.st2 & 15) + seg_len(G, 2) + 15) & ~15;
     G.lds3 = off + (int)(G.st3 & 15);
 }
 
@@ -528,10 +524,10 @@ __device__ __forceinline__ void tile_lds_resident(TileGeo& G)
 // 16-byte chunk counts of the four staged segments.
 __device__ __forceinline__ void seg_chunks(const TileGeo& G, int& n0, int& n1, int& n2, int& n3)
 {
-    n0 = ((int)(G.st0 & 15) + G.len0 + 15) >> 4;
-    n1 = ((int)(G.st1 & 15) + G.len1 + 15) >> 4;
-    n2 = ((int)(G.st2 & 15) + G.len2 + 15) >> 4;
-    n3 = ((int)(G.st3 & 15) + G.len3 + 15) >> 4;
+    n0 = ((int)(G.st0 & 15) + seg_len(G, 0) + 15) >> 4;
+    n1 = ((int)(G.st1 & 15) + seg_len(G, 1) + 15) >> 4;
+    n2 = ((int)(G.st2 & 15) + seg_len(G, 2) + 15) >> 4;
+    n3 = ((int)(G.st3 & 15) + seg_len(G, 3) + 15) >> 4;
 }
 
 // Chunk c of the concatenated segments: segment k and chunk index within it.
@@ -782,16 +778,16 @@ struct GroupCall {
 // allows), each caching the rates of 8/G consecutive events; K = 1 with
 // n > 64 recomputes the rates from LDS at every step.  After a hop only the
 // events whose vacancy moved or whose target changed are recomputed.
-template <int K>
+template <int K, int E>
 __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, unsigned char* occl,
                                           uint32_t* sxyz, int n, uint32_t f, const GroupCall& X,
                                           int lane, Rec& rec, RecCtl& rc, uint32_t& ho, uint32_t& hh)
 {
-    constexpr int S = 64 / K;
+    constexpr int S = 64 / K;  // E: most events cached per lane
     const int sl = lane & (S - 1);
     const int sb = lane & ~(S - 1);
     const uint64_t segmask = S == 64 ? ~0ull : (((1ull << (S & 63)) - 1ull) << sb);
-    const bool cached = n <= S;
+    const bool cached = n * 8 <= S * E;
     int lg = 0;  // log2 lanes per slot
     if (cached && n > 0) lg = n * 8 <= S ? 3 : (n * 4 <= S ? 2 : (n * 2 <= S ? 1 : 0));
     const int epl = 8 >> lg;
@@ -803,9 +799,9 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
     const int m = (n + 63) >> 6;
     const int s0 = lane * m < n ? lane * m : n;
     const int s1 = s0 + m < n ? s0 + m : n;
-    double kk[8];
+    double kk[E];
 #pragma unroll
-    for (int d = 0; d < 8; d++) kk[d] = 0.0;
+    for (int d = 0; d < E; d++) kk[d] = 0.0;
     double ls = 0.0;
     auto refresh = [&]() {
         ls = 0.0;
@@ -814,7 +810,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             const double r = tile_rate(G, occl, C, my_xyz, my_d0 + j);
             ls += r;
 #pragma unroll
-            for (int q = 0; q < 8; q++) kk[q] = q == j ? r : kk[q];
+            for (int q = 0; q < E; q++) kk[q] = q == j ? r : kk[q];
         }
     };
     if (ev_valid) refresh();
@@ -822,8 +818,28 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
     double tau = 0.0;
     uint32_t step = 0;
     bool active = n > 0;
+    // draws computed ahead: lane sl of a segment holds the draw of step
+    // dbase + sl of its tile, refilled when the tile has used all S
+    uint32_t dbase = 0;
+    double dr_sel = 0.0, dr_ln = 0.0;
+    {
+        uint32_t x0, x1, x2, x3;
+        philox10((uint32_t)sl, f, X.cycle, X.ctag, X.seed, X.lid, x0, x1, x2, x3);
+        dr_sel = u53_lo(x0, x1);
+        dr_ln = clock_ln(u53_hi(x2, x3));
+    }
     for (;;) {
         if (__ballot(active) == 0) break;
+        const bool refill = active && step - dbase >= (uint32_t)S;
+        if (__ballot(refill)) {
+            if (refill) {
+                dbase = step;
+                uint32_t x0, x1, x2, x3;
+                philox10(step + (uint32_t)sl, f, X.cycle, X.ctag, X.seed, X.lid, x0, x1, x2, x3);
+                dr_sel = u53_lo(x0, x1);
+                dr_ln = clock_ln(u53_hi(x2, x3));
+            }
+        }
         if (K == 1 && !cached) {
             ls = 0.0;
             for (int s = s0; s < s1; s++) {
@@ -834,11 +850,10 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         const double lsv = active ? ls : 0.0;
         const double incl = seg_scan<S>(lsv, sl);
         const double R = S == 64 ? lane_value(incl, 63) : lane_pull(incl, lane | (S - 1));
-        uint32_t x0, x1, x2, x3;
-        philox10(step, f, X.cycle, X.ctag, X.seed, X.lid, x0, x1, x2, x3);
-        const double u_sel = u53_lo(x0, x1);
-        const double u_t = u53_hi(x2, x3);
-        const double dt = -clock_ln(u_t) / R;
+        const int dl = (int)(step - dbase);  // < S for an active tile
+        const double u_sel = S == 64 ? lane_value(dr_sel, dl) : lane_pull(dr_sel, sb + (dl & (S - 1)));
+        const double lnu = S == 64 ? lane_value(dr_ln, dl) : lane_pull(dr_ln, sb + (dl & (S - 1)));
+        const double dt = -lnu / R;
         const double tn = tau + dt;
         const bool go = active && R != 0.0 && tn <= X.t_sync;
         active = go;
@@ -857,7 +872,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             int found = -1, last = -1;
             if (cached) {
 #pragma unroll
-                for (int j = 0; j < 8; j++) {
+                for (int j = 0; j < E; j++) {
                     if (j < epl) {
                         if (kk[j] > 0.0) last = j;
                         Cc += kk[j];
@@ -940,10 +955,11 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
 // f0 .. f0+nt-1.  Streamed lattices stage their footprints from HBM into LDS
 // at lds0 + fp (fps bytes apart); resident lattices find their slots in the
 // LDS vacancy list.  The tiles run together, one per S = 64/K-lane segment;
-// a tile with more vacancies than S runs afterwards on the whole wave.
+// a tile with more vacancies than S/2 runs afterwards on the whole wave
+// (E1 cached events per lane there).
 // With `single`, every tile runs on the whole wave, one after another, and
 // a streamed lattice stages one footprint at a time.
-template <int K>
+template <int K, int E1>
 __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, int f0, int nt, int colour,
                                           const GroupCall& X, const WaveLds& W, unsigned char* lds0,
                                           int fp, int fps, bool resident, bool single, uint32_t* vlist,
@@ -951,7 +967,9 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
                                           int lane, Rec& rec, RecCtl& rc, uint32_t& ho, uint32_t& hh,
                                           bool& err)
 {
+    static_assert(K > 1, "tile groups of more than one tile");
     constexpr int S = 64 / K;
+    constexpr int FIT = S / 2;  // vacancies a segment holds (4 cached events per lane)
     const int seg = lane / S, sl = lane & (S - 1);
     // tile records: an LDS cache of the whole call, or copied for this group
     const TileRec* R = cached;
@@ -987,16 +1005,17 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
         if (resident) tile_lds_resident(G);
         else tile_lds_at(G, fp + seg * fps);
         n_seg = seg < nt ? W.cnt[seg] : 0;
-        if (n_seg <= S && sl < n_seg) sort_list(W, seg * S, n_seg, sl);
+        if (n_seg <= FIT && sl < n_seg) sort_list(W, seg * S, n_seg, sl);
         wave_lds_fence();
-        const int n_run = n_seg <= S ? n_seg : 0;
-        group_bkl<K>(G, C, lds0, W.xyz + seg * S, n_run, (uint32_t)(f0 + seg), X, lane, rec, rc, ho, hh);
+        const int n_run = n_seg <= FIT ? n_seg : 0;
+        group_bkl<K, 4>(G, C, lds0, W.xyz + seg * S, n_run, (uint32_t)(f0 + seg), X, lane, rec, rc, ho,
+                        hh);
         wave_lds_fence();
         if (resident && sl < n_run) list_update(W, G, D, vlist, seg * S, sl);
     }
     // tiles run on the whole wave: those that did not fit their segment, or all
     uint64_t todo = single ? (nt >= 64 ? ~0ull : ((1ull << nt) - 1ull))
-                           : __ballot(sl == 0 && n_seg > S);
+                           : __ballot(sl == 0 && n_seg > FIT);
     while (todo) {
         wave_lds_fence();
         const int b = __ffsll((unsigned long long)todo) - 1;
@@ -1026,7 +1045,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
         }
         for (int l = lane; l < n1; l += 64) sort_list(W, 0, n1, l);
         wave_lds_fence();
-        group_bkl<1>(T, C, lds0, W.xyz, n1, (uint32_t)(f0 + q), X, lane, rec, rc, ho, hh);
+        group_bkl<1, E1>(T, C, lds0, W.xyz, n1, (uint32_t)(f0 + q), X, lane, rec, rc, ho, hh);
         wave_lds_fence();
         if (resident)
             for (int l = lane; l < n1; l += 64) list_update(W, T, D, vlist, 0, l);
@@ -1072,7 +1091,7 @@ __global__ __launch_bounds__(64 * kPhaseWaves) __attribute__((amdgpu_waves_per_e
     uint32_t ho = 0, hh = 0;
     bool err = false;
     if (lane < 12) W.k12[lane] = D.k12[lane];
-    run_group<KG>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratch, P.fp_stride,
+    run_group<KG, 4>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratch, P.fp_stride,
                   false, K == 1, nullptr, 0, nullptr, nullptr, lane, rec, rc, ho, hh, err);
     rec_flush(rec, rc, P.disp);
     constexpr int S = K == 1 ? 64 : 64 / K;
@@ -1424,7 +1443,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                 for (int g = wv; g < ngroups; g += nw) {
                     const int f0 = g * K;
                     const int nt = ntiles - f0 < K ? ntiles - f0 : K;
-                    run_group<8>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
+                    run_group<8, 8>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
                                  vlist, nv_list, c2s, solo ? rcache + colour * ntiles : nullptr, lane,
                                  rec, rc, ho, hh, err);
                 }
