@@ -1539,6 +1539,15 @@ struct PlainSlot {
     uint64_t packed;  // i | j << 16 | k << 32 | t << 48
 };
 
+// Storage offset in plain mode: the whole lattice is one brick.
+__device__ __forceinline__ int64_t plain_store(const LatDesc& D, int i, int j, int k, int t)
+{
+    const int64_t V = (int64_t)D.L[0] * D.L[1] * D.L[2];
+    if (t == 0) return ((int64_t)i * D.L[2] + k) * D.L[1] + j;
+    if (t == 1) return V + ((int64_t)j * D.L[2] + k) * D.L[0] + i;
+    return 2 * V + ((int64_t)k * D.L[1] + j) * D.L[0] + i;
+}
+
 __device__ __forceinline__ double plain_rate(const LatDesc& D, const DevPtrs& P, uint64_t pk,
                                              int d, int64_t& tgt_store)
 {
@@ -1554,7 +1563,7 @@ __device__ __forceinline__ double plain_rate(const LatDesc& D, const DevPtrs& P,
     if (Z < 0) Z += 2 * D.L[2];
     if (Z >= 2 * D.L[2]) Z -= 2 * D.L[2];
     const int tt = site_type(X, Y);
-    tgt_store = store_index(D, P.bounds, P.c2s, X >> 1, Y >> 1, Z >> 1, tt);
+    tgt_store = plain_store(D, X >> 1, Y >> 1, Z >> 1, tt);
     const int sp = P.occ[D.occ_off + tgt_store];
     if (sp == kSpV) return 0.0;
     const int cs = t == 0 ? i : (t == 1 ? j : k);
@@ -1563,15 +1572,39 @@ __device__ __forceinline__ double plain_rate(const LatDesc& D, const DevPtrs& P,
     return D.k12[(sp * 3 + hz + 1) * 2 + g];
 }
 
+// Periodic nearest neighbours among packed cell/type positions.
+__device__ __forceinline__ bool plain_adjacent(const LatDesc& D, uint64_t a, uint64_t b)
+{
+    const int ta = (int)(a >> 48), tb = (int)(b >> 48);
+    int dX = (2 * (int)(a & 0xffff) + (ta != 0)) - (2 * (int)(b & 0xffff) + (tb != 0));
+    int dY = (2 * (int)((a >> 16) & 0xffff) + (ta != 1)) - (2 * (int)((b >> 16) & 0xffff) + (tb != 1));
+    int dZ = (2 * (int)((a >> 32) & 0xffff) + (ta != 2)) - (2 * (int)((b >> 32) & 0xffff) + (tb != 2));
+    dX = dX < 0 ? -dX : dX;
+    dY = dY < 0 ? -dY : dY;
+    dZ = dZ < 0 ? -dZ : dZ;
+    if (dX == 2 * D.L[0] - 1) dX = 1;
+    if (dY == 2 * D.L[1] - 1) dY = 1;
+    if (dZ == 2 * D.L[2] - 1) dZ = 1;
+    return dX * dX + dY * dY + dZ * dZ == 2;
+}
+
+// Each thread owns a contiguous range of slots; the total rate of every
+// slot is kept in LDS, so a step sums m <= 16 totals per thread, scans the
+// workgroup, evaluates the 8 rates of the selected slot only, and after the
+// hop re-evaluates just the slots next to its two sites.
 __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_t* ids)
 {
-    __shared__ uint64_t slots[kMaxPlainSlots];
+    extern __shared__ __align__(16) unsigned char psm[];
+    uint64_t* slots = (uint64_t*)psm;                     // [kMaxPlainSlots]
+    double* stot = (double*)(psm + 8 * kMaxPlainSlots);   // [kMaxPlainSlots]
     __shared__ int wcount[kPlainThreads / 64];
     __shared__ double wsum[kPlainThreads / 64];
     __shared__ uint64_t wmask[kPlainThreads / 64];
     __shared__ uint64_t wnz[kPlainThreads / 64];
     __shared__ int n_sh;
     __shared__ int ev_sh;
+    __shared__ int hop_slot;
+    __shared__ uint64_t hop_s, hop_t;  // packed positions of the hop's two sites
     const int lat = ids[blockIdx.x];
     const LatDesc& D = P.desc[lat];
     LatState* S = P.state + lat;
@@ -1593,7 +1626,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
             const int i = (int)(cell % D.L[0]);
             const int j = (int)((cell / D.L[0]) % D.L[1]);
             const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-            v = P.occ[D.occ_off + store_index(D, P.bounds, P.c2s, i, j, k, t)] == kSpV;
+            v = P.occ[D.occ_off + plain_store(D, i, j, k, t)] == kSpV;
             pk = (uint64_t)i | ((uint64_t)j << 16) | ((uint64_t)k << 32) | ((uint64_t)t << 48);
         }
         const uint64_t mk = __ballot(v);
@@ -1621,6 +1654,16 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
     const int m = (n + kPlainThreads - 1) / kPlainThreads;
     const int s0 = tid * m < n ? tid * m : n;
     const int s1 = s0 + m < n ? s0 + m : n;
+    auto slot_total = [&](int sidx) {
+        double r = 0.0;
+        for (int d = 0; d < 8; d++) {
+            int64_t ts;
+            r += plain_rate(D, P, slots[sidx], d, ts);
+        }
+        return r;
+    };
+    for (int sidx = s0; sidx < s1; sidx++) stot[sidx] = slot_total(sidx);
+    __syncthreads();
     double t = S->t;
     uint64_t draws = S->draws;
     const double horizon = C->t_sync;
@@ -1629,11 +1672,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
     uint64_t done = 0, ho = 0, hh = 0;
     while (done < target) {
         double ls = 0.0;
-        for (int s = s0; s < s1; s++)
-            for (int d = 0; d < 8; d++) {
-                int64_t ts;
-                ls += plain_rate(D, P, slots[s], d, ts);
-            }
+        for (int sidx = s0; sidx < s1; sidx++) ls += stot[sidx];
         double incl = wave_incl_scan(ls, lane);
         if (lane == 63) wsum[wv] = incl;
         __syncthreads();
@@ -1675,24 +1714,33 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
                 if (wnz[w]) sel = w * 64 + 63 - __clzll((long long)wnz[w]);
         }
         if (tid == sel) {
+            // the slot, then the direction, where the cumulative rate first exceeds y
             double Cc = incl - ls;
-            int ev = -1, last = -1;
-            for (int s = s0; s < s1 && ev < 0; s++)
-                for (int d = 0; d < 8; d++) {
-                    int64_t ts;
-                    const double k = plain_rate(D, P, slots[s], d, ts);
-                    if (k > 0.0) last = s * 8 + d;
-                    Cc += k;
-                    if (!fallback && Cc > y) { ev = s * 8 + d; break; }
+            int sp_slot = -1, last = -1;
+            for (int sidx = s0; sidx < s1; sidx++) {
+                if (stot[sidx] > 0.0) last = sidx;
+                if (!fallback && sp_slot < 0 && Cc + stot[sidx] > y) {
+                    sp_slot = sidx;
+                    break;
                 }
-            if (ev < 0) ev = last;
-            const int s = ev >> 3, d = ev & 7;
-            const uint64_t pk = slots[s];
+                Cc += stot[sidx];
+            }
+            if (sp_slot < 0) sp_slot = last;
+            const uint64_t pk = slots[sp_slot];
+            int dsel = -1, dlast = -1;
+            for (int d = 0; d < 8; d++) {
+                int64_t ts;
+                const double k = plain_rate(D, P, pk, d, ts);
+                if (k > 0.0) dlast = d;
+                Cc += k;
+                if (!fallback && dsel < 0 && Cc > y) dsel = d;
+            }
+            const int d = dsel >= 0 ? dsel : dlast;
             int64_t ts;
             plain_rate(D, P, pk, d, ts);
             const int i = (int)(pk & 0xffff), j = (int)((pk >> 16) & 0xffff), k = (int)((pk >> 32) & 0xffff);
             const int tp = (int)(pk >> 48);
-            const int64_t ss = store_index(D, P.bounds, P.c2s, i, j, k, tp);
+            const int64_t ss = plain_store(D, i, j, k, tp);
             int hx, hy, hz;
             hop_vec(tp, d, hx, hy, hz);
             const int sp = P.occ[D.occ_off + ts];
@@ -1711,15 +1759,25 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
             if (Y >= 2 * D.L[1]) Y -= 2 * D.L[1];
             if (Z < 0) Z += 2 * D.L[2];
             if (Z >= 2 * D.L[2]) Z -= 2 * D.L[2];
-            slots[s] = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) | ((uint64_t)(Z >> 1) << 32) |
-                       ((uint64_t)site_type(X, Y) << 48);
+            const uint64_t npk = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) |
+                                 ((uint64_t)(Z >> 1) << 32) | ((uint64_t)site_type(X, Y) << 48);
+            slots[sp_slot] = npk;
+            hop_slot = sp_slot;
+            hop_s = pk;
+            hop_t = npk;
             ev_sh = sp;
-            __threadfence_block();
+            __threadfence();  // the occupancy change is visible to the rate updates
         }
         __syncthreads();
         if (ev_sh == kSpO) ho++;
         else hh++;
         done++;
+        // slots whose events changed: the moved vacancy and those next to its two sites
+        const uint64_t ps = hop_s, pt = hop_t;
+        const int mv = hop_slot;
+        for (int sidx = s0; sidx < s1; sidx++)
+            if (sidx == mv || plain_adjacent(D, slots[sidx], ps) || plain_adjacent(D, slots[sidx], pt))
+                stot[sidx] = slot_total(sidx);
         __syncthreads();
     }
     if (tid == 0) {
@@ -1960,7 +2018,11 @@ int launch_cycle_begin(const DevPtrs& P, void* stream)
 int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void* stream)
 {
     if (n_plain == 0) return 0;
-    hipLaunchKernelGGL(k_plain, dim3(n_plain), dim3(kPlainThreads), 0, (hipStream_t)stream, P,
+    const size_t lds = (size_t)16 * kMaxPlainSlots;
+    hipError_t e = hipFuncSetAttribute((const void*)k_plain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k_plain, dim3(n_plain), dim3(kPlainThreads), lds, (hipStream_t)stream, P,
                        d_plain_ids);
     return (int)hipGetLastError();
 }
