@@ -718,9 +718,9 @@ static double mean_footprint_vacancies(const fkmc_lattice* L, uint32_t i)
 static fkmc_status prepare_lockstep(fkmc_lattice* L)
 {
     if (L->phase_group) return FKMC_OK;
-    // at most 2: more staged footprints per wave cost more occupancy than
+    // at most 4: more staged footprints per wave cost more occupancy than
     // the shared steps save (measured on the 600^3 sweep)
-    int g = 2;
+    int g = 4;
     for (int32_t i : L->batch_ids)
         g = std::min(g, pick_group(mean_footprint_vacancies(L, i), L->fp_stride, 32768 - kWaveScratch, true));
     if (L->group_override) g = L->group_override;

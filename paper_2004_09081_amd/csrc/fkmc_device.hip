@@ -1057,7 +1057,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
 // Lockstep phase kernel: one wave per group of K tiles of colour `colour`
 // (P.groups: lattice and first fragment), footprints staged HBM -> LDS.
 template <int K>
-__global__ __launch_bounds__(64 * kPhaseWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_phase(DevPtrs P, int colour)
+__global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colour)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
