@@ -15,7 +15,14 @@ from __future__ import annotations
 
 import numpy as np
 
-DEFAULT_CANDIDATES = (4, 6, 8, 12, 16, 24, 64)
+def whole_if_sparse(spec) -> int:
+    """One fragment (the whole lattice) for lattices of at most 32 cells and
+    32 vacancies (the library's one-lane-block-per-vacancy path), else
+    16-cell fragments."""
+    return spec.L[0] if max(spec.L) <= 32 and spec.n_vac <= 32 else 16
+
+
+DEFAULT_CANDIDATES = (4, 6, 8, 12, 16, 24, whole_if_sparse)
 
 
 def trial(specs, F, ts, cycles: int, waves: int):
@@ -38,8 +45,10 @@ def trial(specs, F, ts, cycles: int, waves: int):
 
 def tune(make_specs, hop_target: int, candidates=DEFAULT_CANDIDATES, cycles: int = 64,
          waves: int = 4, log=None):
-    """make_specs(frag) -> list of LatticeSpec with that fragment edge rule
-    (an int, or a callable of L).  Returns (per-lattice edge, report)."""
+    """make_specs(frag) -> list of LatticeSpec with fragment edge `frag`
+    (cells).  A candidate is an edge, or a function of a lattice's spec
+    giving its edge.  Returns (per-lattice edge, report); the edge is the
+    one the lattice ran with in its best trial."""
     from paper_2004_09081_amd import fkmc as F
     base = make_specs(8)
     n = len(base)
@@ -47,20 +56,29 @@ def tune(make_specs, hop_target: int, candidates=DEFAULT_CANDIDATES, cycles: int
     best_f = np.full(n, 8, dtype=np.int64)
     report = {}
     for c in candidates:
-        specs = make_specs(c)
+        label = c.__name__ if callable(c) else str(c)
+        if callable(c):
+            specs = make_specs(8)
+            for sp in specs:
+                sp.frag = (int(c(sp)),) * 3
+        else:
+            specs = make_specs(c)
+        used = np.array([sp.frag[0] for sp in specs], dtype=np.int64)
         ts = [sp.t_sync for sp in specs]
         try:
             ms, hpc = trial(specs, F, ts, cycles, waves)
         except F.FkmcError as e:
-            report[c] = "infeasible: %s" % e
+            report[label] = "infeasible: %s" % e
+            if log:
+                log("autotune F=%s: infeasible (%s)" % (label, e))
             continue
         pred = ms * hop_target / np.maximum(hpc, 1e-9)
         better = pred < best_t
         best_t[better] = pred[better]
-        best_f[better] = c
-        report[c] = {"max_pred_ms": float(pred.max()), "median_pred_ms": float(np.median(pred))}
+        best_f[better] = used[better]
+        report[label] = {"max_pred_ms": float(pred.max()), "median_pred_ms": float(np.median(pred))}
         if log:
-            log("autotune F=%s: slowest lattice predicted %.0f ms" % (c, pred.max()))
+            log("autotune F=%s: slowest lattice predicted %.0f ms" % (label, pred.max()))
     report["chosen_max_pred_ms"] = float(best_t.max())
     report["histogram"] = {int(k): int(v) for k, v in zip(*np.unique(best_f, return_counts=True))}
     return best_f, report
