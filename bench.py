@@ -88,7 +88,10 @@ def fragment_sizes(L: int, F: int):
 
 def footprint_bytes(spec) -> int:
     """Occupancy bytes one cycle's 8 phases read: every sub-block once plus
-    its three +faces (the footprint of each tile)."""
+    its three +faces (the footprint of each tile).  Plain lattices have no
+    cycles (0)."""
+    if spec.frag[0] == 0:
+        return 0
     ws = []
     for a in range(3):
         w = []
@@ -275,8 +278,9 @@ def main():
             fr = (lambda L: (L + 1) // 2) if args.frag == "half" else int(args.frag)
             specs = W.cfg4(n=args.lattices, hops=args.hops, frag=fr)
         desc = ("cfg4 batched ensemble: %d lattices, cube edge 16-64 cells, T 300-900 K, "
-                "x_H 0-0.3, x_V 1e-3..1e-2 log-uniform, E_z 0-1e7 V/m, fragment edge %s cells, "
-                "%d hops per lattice per step" % (len(specs), args.frag, hop_target))
+                "x_H 0-0.3, x_V 1e-3..1e-2 log-uniform, E_z 0-1e7 V/m, fragment edge %s cells "
+                "(0 = unfragmented BKL held in LDS), %d hops per lattice per step"
+                % (len(specs), args.frag, hop_target))
     elif args.workload == "cfg3":
         specs = [W.cfg3()]
         hop_target = 0
@@ -294,7 +298,8 @@ def main():
     torch.cuda.synchronize()
     log("setup %.2f s (%d lattices, %d sites)" % (time.perf_counter() - t_setup, len(specs),
                                                     sum(s.n_sites for s in specs)))
-    ts = [s.t_sync for s in specs]
+    # plain lattices (fragment edge 0) take no horizon: exactly hop_target hops
+    ts = [0.0 if s.frag[0] == 0 else s.t_sync for s in specs]
 
     def step():
         if args.workload == "cfg3":

@@ -223,6 +223,16 @@ fkmc_status fkmc_set_schedule(fkmc_lattice* lat, int32_t schedule, int32_t waves
  * value.  Results are identical for every group size. */
 fkmc_status fkmc_set_group(fkmc_lattice* lat, int32_t group);
 
+/* Plain lattices (Eqs. TransitionProb, eventSelection, TimeStep over the
+ * whole lattice): with enable = 1 (default) a plain lattice of at most 64
+ * vacancies whose occupancy fits in LDS (x and y edges up to 1023 cells, z
+ * up to 512) runs in the persistent kernel on one wavefront, its occupancy
+ * and per-slot rates held in LDS, in the same launch as the fragment
+ * lattices when those use the persistent schedule; every other plain lattice
+ * runs the HBM-resident plain kernel.  enable = 0 sends every plain lattice
+ * to the HBM kernel.  Results are identical either way. */
+fkmc_status fkmc_set_plain_lds(fkmc_lattice* lat, int32_t enable);
+
 /* Lockstep schedule: replay batches of 8 cycles from a prebuilt HIP graph
  * (1, default) or enqueue every kernel separately (0).  Results are
  * identical; event timing (fkmc_set_timing) always uses separate launches. */

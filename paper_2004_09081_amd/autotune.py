@@ -1,19 +1,26 @@
-"""Autotuner of the fragment edge for an ensemble run with the persistent
-schedule.
+"""Autotuner of the decomposition of each lattice of an ensemble run with
+the persistent schedule.
 
 The fragment edge F sets both the decomposition (part of the simulated
 dynamics, so it is recorded with the results) and the cost: small F gives
 many small tiles per phase, large F few tiles with long serial BKL chains.
-For every candidate F the whole ensemble runs a short trial on the GPU; the
-kernel's per-lattice busy timer gives the device time per cycle and the hop
-counters the hops per cycle, so the time to reach the hop target is
-predicted per lattice, and each lattice gets the candidate with the smallest
-prediction.  The critical path of the ensemble is the slowest lattice, so
-the choice is made lattice by lattice.
+F = 0 is the unfragmented method, plain BKL over the whole lattice, which
+the library runs in LDS on one wavefront for lattices of at most 64
+vacancies: one hop per step and no phases, the fastest choice for sparse
+small lattices, whose fragment phases hold about one hop each.  For every
+candidate the whole ensemble runs a short trial on the GPU; the kernel's
+per-lattice busy timer and hop counters give the device time per hop, so
+the time to reach the hop target is predicted per lattice, and each lattice
+gets the candidate with the smallest prediction.  The critical path of the
+ensemble is the slowest lattice, so the choice is made lattice by lattice.
 """
 from __future__ import annotations
 
 import numpy as np
+
+PLAIN_LDS_VACANCIES = 64
+PLAIN_LDS_BYTES = 60_000
+
 
 def whole_if_sparse(spec) -> int:
     """One fragment (the whole lattice) for lattices of at most 32 cells and
@@ -22,24 +29,45 @@ def whole_if_sparse(spec) -> int:
     return spec.L[0] if max(spec.L) <= 32 and spec.n_vac <= 32 else 16
 
 
-DEFAULT_CANDIDATES = (4, 6, 8, 12, 16, 24, whole_if_sparse)
+def plain_if_sparse(spec) -> int:
+    """Plain BKL (0) for lattices the library holds in LDS (at most 64
+    vacancies, occupancy plus rate cache well inside one workgroup's
+    share), else 16-cell fragments."""
+    n = 3 * spec.L[0] * spec.L[1] * spec.L[2]
+    fits = n + 4 * spec.n_vac + 8 * 8 * PLAIN_LDS_VACANCIES <= PLAIN_LDS_BYTES
+    return 0 if spec.n_vac <= PLAIN_LDS_VACANCIES and fits else 16
 
 
-def trial(specs, F, ts, cycles: int, waves: int):
-    """Per-lattice (ms per cycle, hops per cycle) for one fragment choice."""
+DEFAULT_CANDIDATES = (4, 6, 8, 12, 16, 24, whole_if_sparse, plain_if_sparse)
+
+
+def trial(specs, F, cycles: int, waves: int, plain_hops: int = 20_000):
+    """Per-lattice (device ms, hops) of a short trial: `cycles` cycles for
+    fragment lattices, then `plain_hops` hops for plain ones (a call with no
+    cycles runs only the plain lattices)."""
     from paper_2004_09081_amd.workloads import to_gpu
     geoms, rates = to_gpu(specs, F)
+    plain = np.array([sp.frag[0] == 0 for sp in specs])
+    ts = [0.0 if p else sp.t_sync for p, sp in zip(plain, specs)]
     s = F.LatticeSet(geoms)
     try:
         s.init_random([sp.n_vac for sp in specs], [sp.n_h for sp in specs])
         s.set_rates(rates)
         s.set_schedule("persistent", waves)
-        s.advance(ts, max_cycles=cycles, min_hops=0)
-        st = s.read_stats()
+        ms = np.zeros(len(specs))
+        hops = np.zeros(len(specs))
+        if not plain.all():
+            s.advance(ts, max_cycles=cycles, min_hops=0)
+            st = s.read_stats()
+            ms[~plain] = np.array([x["busy_ms"] for x in st])[~plain]
+            hops[~plain] = np.array([int(x["hops"][0]) + int(x["hops"][1]) for x in st])[~plain]
+        if plain.any():
+            s.advance(ts, max_cycles=0, min_hops=plain_hops)
+            st = s.read_stats()
+            ms[plain] = np.array([x["busy_ms"] for x in st])[plain]
+            hops[plain] = np.array([int(x["hops"][0]) + int(x["hops"][1]) for x in st])[plain]
     finally:
         s.close()
-    ms = np.array([x["busy_ms"] for x in st]) / cycles
-    hops = np.array([int(x["hops"][0]) + int(x["hops"][1]) for x in st], dtype=np.float64) / cycles
     return ms, hops
 
 
@@ -64,15 +92,14 @@ def tune(make_specs, hop_target: int, candidates=DEFAULT_CANDIDATES, cycles: int
         else:
             specs = make_specs(c)
         used = np.array([sp.frag[0] for sp in specs], dtype=np.int64)
-        ts = [sp.t_sync for sp in specs]
         try:
-            ms, hpc = trial(specs, F, ts, cycles, waves)
+            ms, hops = trial(specs, F, cycles, waves)
         except F.FkmcError as e:
             report[label] = "infeasible: %s" % e
             if log:
                 log("autotune F=%s: infeasible (%s)" % (label, e))
             continue
-        pred = ms * hop_target / np.maximum(hpc, 1e-9)
+        pred = ms * hop_target / np.maximum(hops, 1e-9)
         better = pred < best_t
         best_t[better] = pred[better]
         best_f[better] = used[better]

@@ -313,6 +313,9 @@ struct fkmc_lattice {
     hipGraphExec_t graph = nullptr;       // kGraphCycles lockstep cycles
     bool use_graph = true;
     bool last_persistent = false;  // the last fkmc_advance ran the persistent kernel
+    bool plain_lds = true;         // plain lattices that fit run in LDS in the persistent kernel
+    std::vector<int32_t> launch_ids;       // this call's persistent-kernel lattices
+    std::vector<int32_t> slow_plain_ids;   // this call's plain lattices kept in HBM
 };
 
 static constexpr int kGraphCycles = 8;
@@ -530,6 +533,8 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
         recs = tile_records(L->desc, Y, tile2lat);
         CREATE_OK(hipMemcpyAsync(w + Y.o_tiles, recs.data(), recs.size() * sizeof(TileRec), hipMemcpyHostToDevice, L->stream));
     }
+    L->slow_plain_ids = L->plain_ids;
+    L->launch_ids = L->batch_ids;
     if (!L->plain_ids.empty())
         CREATE_OK(hipMemcpyAsync(L->d_plain_ids, L->plain_ids.data(), L->plain_ids.size() * 4, hipMemcpyHostToDevice, L->stream));
     if (!L->batch_ids.empty())
@@ -781,14 +786,45 @@ static fkmc_status prepare_call(fkmc_lattice* L, const double* t_sync, uint64_t 
 // vacancy list, cell -> sub-block maps) or every wave's staged footprints,
 // so a lattice stays in LDS whenever its slab fits the region's bound (two
 // workgroups per CU).  Each lattice also gets its group size (8, 4 or 1).
-static fkmc_status plan_batch(fkmc_lattice* L)
+// Plain lattices in the list are held in LDS (plain_lds_fits).
+static int batch_lds_bound(const fkmc_lattice* L)
+{
+    return L->lds_budget - L->batch_waves * kWaveScratch - kRecCache - 64;
+}
+
+// LDS of a plain lattice run by the persistent kernel: canonical occupancy,
+// vacancy list, and the 8 rates of every slot.
+static int64_t plain_lds_bytes(const fkmc_lattice* L, uint32_t i)
+{
+    return ((L->desc[i].n_sites + 15) & ~(int64_t)15) + 4 * (((int64_t)L->n_vac[i] + 3) & ~3) +
+           8 * 8 * kPlainLdsSlots;
+}
+
+static bool plain_lds_fits(const fkmc_lattice* L, uint32_t i)
+{
+    const fkmc_geometry& g = L->geo[i];
+    if (!L->plain_lds || !L->desc[i].plain || L->n_vac[i] > (uint64_t)kPlainLdsSlots) return false;
+    // packed doubled coordinates: 11 bits for x and y, 10 for z
+    if (g.L[0] > 1023 || g.L[1] > 1023 || g.L[2] > 512) return false;
+    return plain_lds_bytes(L, i) <= std::min(batch_lds_bound(L), 65536);
+}
+
+static fkmc_status plan_batch(fkmc_lattice* L, const std::vector<int32_t>& ids)
 {
     const int waves = L->batch_waves;
-    const int bound = L->lds_budget - waves * kWaveScratch - kRecCache - 64;
+    const int bound = batch_lds_bound(L);
     int region = 0;
-    for (int32_t i : L->batch_ids) {
+    for (int32_t i : ids) {
         LatDesc& D = L->desc[i];
         const fkmc_geometry& g = L->geo[i];
+        if (D.plain) {
+            D.n_vac = (int32_t)L->n_vac[i];
+            D.resident = 1;
+            D.fast = 1;
+            D.group = 1;
+            region = std::max<int>(region, (int)plain_lds_bytes(L, i));
+            continue;
+        }
         const double lam = mean_footprint_vacancies(L, i);
         const int64_t slab = ((D.n_sites + 15) & ~(int64_t)15) + 4 * (((int64_t)L->n_vac[i] + 3) & ~3) +
                              g.L[0] + g.L[1] + g.L[2];
@@ -797,8 +833,9 @@ static fkmc_status plan_batch(fkmc_lattice* L)
         D.n_vac = (int32_t)L->n_vac[i];
         D.resident = small ? 1 : 0;
         // one fragment, in LDS, at most 32 vacancies: a block of lanes per vacancy
+        // (packed doubled coordinates give z 10 bits)
         D.fast = small && !L->group_override && D.nf[0] == 1 && D.nf[1] == 1 && D.nf[2] == 1 &&
-                         L->n_vac[i] <= 32
+                         g.L[2] <= 512 && L->n_vac[i] <= 32
                      ? 1
                      : 0;
         const int fps = footprint_stride((int)max_footprint(g));
@@ -849,28 +886,52 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
     if (!L) return fail(FKMC_E_INVALID, "null handle");
     const bool any_frag = L->Y.n_tiles > 0;
     if (any_frag && !t_sync) return fail(FKMC_E_INVALID, "t_sync required for fragment lattices");
+    // Plain lattices that fit run in LDS in the persistent kernel (with the
+    // fragment lattices when those use it); the others keep the HBM kernel.
+    const bool persist = any_frag && max_cycles > 0 && use_persistent(L);
+    std::vector<int32_t> ids, slow;
+    if (persist) ids = L->batch_ids;
+    for (int32_t i : L->plain_ids) {
+        L->desc[i].resident = 0;
+        if (plain_lds_fits(L, (uint32_t)i)) ids.push_back(i);
+        else slow.push_back(i);
+    }
+    // (both lists are read by the copies before prepare_call synchronises)
+    if (slow != L->slow_plain_ids) {
+        L->slow_plain_ids = slow;
+        if (!slow.empty())
+            HIP_OK(hipMemcpyAsync(L->d_plain_ids, L->slow_plain_ids.data(), slow.size() * 4,
+                                  hipMemcpyHostToDevice, L->stream));
+    }
+    if (ids != L->launch_ids) {
+        L->launch_ids = ids;
+        if (!ids.empty())
+            HIP_OK(hipMemcpyAsync(L->d_batch_ids, L->launch_ids.data(), ids.size() * 4, hipMemcpyHostToDevice,
+                                  L->stream));
+    }
     fkmc_status s = prepare_call(L, t_sync, max_cycles, min_hops, true);
     if (s) return s;
-    LAUNCH_OK(launch_plain(L->P, L->d_plain_ids, (int)L->plain_ids.size(), L->stream));
+    LAUNCH_OK(launch_plain(L->P, L->d_plain_ids, (int)slow.size(), L->stream));
     size_t ev_used = 0;
     if (L->timing && any_frag && L->ev.empty()) {
         L->ev.resize(2 * 2048);
         for (auto& e : L->ev) HIP_OK(hipEventCreate(&e));
     }
-    L->last_persistent = false;
-    if (any_frag && max_cycles > 0 && use_persistent(L)) {
-        L->last_persistent = true;
-        s = plan_batch(L);
+    L->last_persistent = persist;
+    if (!ids.empty()) {
+        s = plan_batch(L, ids);
         if (s) return s;
         DevPtrs P = L->P;
         P.lds_region_bytes = L->batch_region_bytes;
-        if (L->timing) HIP_OK(hipEventRecord(L->ev[0], L->stream));
-        LAUNCH_OK(launch_batch(P, (int)L->batch_ids.size(), L->batch_waves, L->stream));
-        if (L->timing) {
+        const bool timed = L->timing && persist;
+        if (timed) HIP_OK(hipEventRecord(L->ev[0], L->stream));
+        LAUNCH_OK(launch_batch(P, (int)ids.size(), L->batch_waves, L->stream));
+        if (timed) {
             HIP_OK(hipEventRecord(L->ev[1], L->stream));
             ev_used = 2;
         }
-    } else if (any_frag && max_cycles > 0) {
+    }
+    if (!persist && any_frag && max_cycles > 0) {
         s = prepare_lockstep(L);
         if (s) return s;
         LAUNCH_OK(launch_cycle_begin(L->P, L->stream));
@@ -1053,6 +1114,14 @@ fkmc_status fkmc_set_graph(fkmc_lattice* L, int32_t enable)
     return FKMC_OK;
 }
 
+fkmc_status fkmc_set_plain_lds(fkmc_lattice* L, int32_t enable)
+{
+    if (!L) return fail(FKMC_E_INVALID, "null handle");
+    if (enable != 0 && enable != 1) return fail(FKMC_E_INVALID, "enable must be 0 or 1");
+    L->plain_lds = enable != 0;
+    return FKMC_OK;
+}
+
 fkmc_status fkmc_set_group(fkmc_lattice* L, int32_t group)
 {
     if (!L) return fail(FKMC_E_INVALID, "null handle");
@@ -1141,6 +1210,8 @@ fkmc_status fkmc_read_stats(fkmc_lattice* L, fkmc_stats* out)
             o.draws = S.draws;
             o.hops[0] = S.hops[0];
             o.hops[1] = S.hops[1];
+            o.busy_ms = (double)S.busy_ticks / 100000.0;
+            o.lds_resident = L->desc[i].resident ? 1u : 0u;
         } else {
             o.t = L->t_frag[i];
             o.cycles = S.cycles;

@@ -1144,22 +1144,15 @@ __device__ __forceinline__ int store_dbl_1f(int L0, int L1, int L2, int X, int Y
     return store_index_1f(L0, L1, L2, X >> 1, Y >> 1, Z >> 1, site_type(X, Y));
 }
 
-// Rate of event d of the vacancy at doubled coordinates (X,Y,Z) in phase
-// `colour`: zero unless the edge's owner cell (the cell of its midpoint)
-// lies in the sub-block of that colour and the target holds an ion.
-__device__ __forceinline__ double fast_rate(const RateCtx& C, const unsigned char* slab, int colour,
-                                            int X, int Y, int Z, int d)
+// Rate of event d of the vacancy at doubled coordinates (X,Y,Z), every edge
+// active: zero when the target holds a vacancy, else the table entry for
+// (ion species, z step, boundary).
+__device__ __forceinline__ double dbl_rate(const RateCtx& C, const unsigned char* slab, int X, int Y,
+                                           int Z, int d)
 {
     const int t = site_type(X, Y);
     int hx, hy, hz;
     hop_vec(t, d, hx, hy, hz);
-    int ox = (2 * X + hx) >> 2, oy = (2 * Y + hy) >> 2, oz = (2 * Z + hz) >> 2;
-    if (ox < 0) ox += C.L0;
-    if (oy < 0) oy += C.L1;
-    if (oz < 0) oz += C.L2;
-    const int col = (ox >= ((C.L0 + 1) >> 1) ? 1 : 0) | (oy >= ((C.L1 + 1) >> 1) ? 2 : 0) |
-                    (oz >= ((C.L2 + 1) >> 1) ? 4 : 0);
-    if (col != colour) return 0.0;
     int TX = X + hx, TY = Y + hy, TZ = Z + hz;
     if (TX < 0) TX += 2 * C.L0;
     if (TX >= 2 * C.L0) TX -= 2 * C.L0;
@@ -1176,6 +1169,24 @@ __device__ __forceinline__ double fast_rate(const RateCtx& C, const unsigned cha
             gb_flag(C, tt, pick3(tt, TX >> 1, TY >> 1, TZ >> 1));
     }
     return C.k12[(sp * 3 + hz + 1) * 2 + g];
+}
+
+// Rate of event d in phase `colour`: zero unless the edge's owner cell (the
+// cell of its midpoint) lies in the sub-block of that colour.
+__device__ __forceinline__ double fast_rate(const RateCtx& C, const unsigned char* slab, int colour,
+                                            int X, int Y, int Z, int d)
+{
+    const int t = site_type(X, Y);
+    int hx, hy, hz;
+    hop_vec(t, d, hx, hy, hz);
+    int ox = (2 * X + hx) >> 2, oy = (2 * Y + hy) >> 2, oz = (2 * Z + hz) >> 2;
+    if (ox < 0) ox += C.L0;
+    if (oy < 0) oy += C.L1;
+    if (oz < 0) oz += C.L2;
+    const int col = (ox >= ((C.L0 + 1) >> 1) ? 1 : 0) | (oy >= ((C.L1 + 1) >> 1) ? 2 : 0) |
+                    (oz >= ((C.L2 + 1) >> 1) ? 4 : 0);
+    if (col != colour) return 0.0;
+    return dbl_rate(C, slab, X, Y, Z, d);
 }
 
 // Periodic nearest neighbours (doubled coordinates differ by 1 on two axes).
@@ -1331,13 +1342,180 @@ __device__ __forceinline__ void solo_fast(const LatDesc& D, unsigned char* slab,
     hh_tot = hh;
 }
 
+// ----------------------------------------------------------------------------
+// Plain BKL (Eqs. TransitionProb, eventSelection, TimeStep) on a lattice held
+// in LDS in canonical order, with at most 64 vacancies, on one wave.  Lane s
+// holds slot s: the slots are the vacancies in canonical order at the start
+// of the call, and a slot follows its vacancy.  Each lane keeps its slot's
+// rate total and the inclusive prefix of the totals; the 8 rates of every
+// slot sit in LDS.  A hop changes the events of the moved vacancy and of the
+// vacancies next to its two sites only: lanes 0-7 recompute such a slot's
+// rates (one direction each), and the prefix sums of that slot and every
+// later one move by the change of its total.  The rates are multiples of one
+// power of two with every partial sum below 2^53 of them, so these updates
+// give exactly the sums of a fresh pass in event order.
+
+// Storage offset in plain mode: the whole lattice is one brick.
+__device__ __forceinline__ int64_t plain_offset(int L0, int L1, int L2, int i, int j, int k, int t)
+{
+    const int64_t V = (int64_t)L0 * L1 * L2;
+    if (t == 0) return ((int64_t)i * L2 + k) * L1 + j;
+    if (t == 1) return V + ((int64_t)j * L2 + k) * L0 + i;
+    return 2 * V + ((int64_t)k * L1 + j) * L0 + i;
+}
+
+// Lanes 0-7: rate of direction `lane` of the vacancy at packed doubled
+// coordinates p, stored as krate[slot*8 + lane].  Returns the slot total
+// (wave-uniform).  All lanes must be active.
+__device__ __forceinline__ double plain_slot_rates(const RateCtx& C, const unsigned char* slab, double* krate,
+                                                   int slot, uint32_t p, int lane)
+{
+    double k = 0.0;
+    if (lane < 8) {
+        k = dbl_rate(C, slab, p & 2047, (p >> 11) & 2047, p >> 22, lane);
+        krate[slot * 8 + lane] = k;
+    }
+    return lane_value(seg_scan<8>(k, lane & 7), 7);
+}
+
+// Runs the call: exactly min_hops hops, stopping early when the next event
+// would land after t + t_sync (t_sync > 0; the clock then takes that value
+// and the draw is spent) or no event is possible.  Draw d uses Philox
+// counter (d_lo, d_hi, 0xFFFFFFFF, 3); draws are computed 64 ahead, one per
+// lane.  vlist holds the nv vacancies (i | j << 10 | k << 20 | t << 30).
+__device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab, const uint32_t* vlist, int nv,
+                                           double* krate, const RateCtx& C, int4* disp, LatState* St,
+                                           const LatCall* Cl, int lane, Rec& rec, RecCtl& rc)
+{
+    const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
+    const bool valid = lane < nv;
+    uint32_t p0 = 0;
+    int key = 0x7fffffff;
+    if (valid) {
+        const uint32_t g = vlist[lane];
+        const int i = g & 1023, j = (g >> 10) & 1023, k = (g >> 20) & 1023, t = g >> 30;
+        p0 = pack_dbl(2 * i + (t != 0), 2 * j + (t != 1), 2 * k + (t != 2));
+        key = ((k * L1 + j) * L0 + i) * 3 + t;
+    }
+    // slot = canonical rank at call start; unused lanes keep their place
+    int rank = valid ? 0 : lane;
+    for (int j = 0; j < nv; j++) rank += (valid && __builtin_amdgcn_readlane(key, j) < key) ? 1 : 0;
+    uint32_t pos = (uint32_t)__builtin_amdgcn_ds_permute(rank << 2, (int)p0);
+    double tot = 0.0;
+    if (valid) {
+        const int Xs = pos & 2047, Ys = (pos >> 11) & 2047, Zs = pos >> 22;
+#pragma nounroll
+        for (int d = 0; d < 8; d++) {
+            const double k = dbl_rate(C, slab, Xs, Ys, Zs, d);
+            krate[lane * 8 + d] = k;
+            tot += k;
+        }
+    }
+    double incl = wave_scan_dpp(tot);
+    double R = lane_value(incl, 63);
+    double t = St->t;
+    uint64_t draws = St->draws;
+    const double horizon = Cl->t_sync;
+    const double t_end = t + horizon;
+    const uint64_t target = Cl->min_hops;
+    uint64_t done = 0;
+    unsigned long long ho = 0, hh = 0;
+    int sl = 64;
+    double dr_sel = 0.0, dr_ln = 0.0;  // draw sl + (draws at the refill) is in lane sl
+    while (done < target) {
+        if (R == 0.0) break;
+        if (sl == 64) {
+            const uint64_t di = draws + (uint64_t)lane;
+            uint32_t x0, x1, x2, x3;
+            philox10((uint32_t)di, (uint32_t)(di >> 32), 0xFFFFFFFFu, 3u, D.seed, D.lattice_id, x0, x1, x2, x3);
+            dr_sel = u53_lo(x0, x1);
+            dr_ln = clock_ln(u53_hi(x2, x3));
+            sl = 0;
+        }
+        const double u_sel = lane_value(dr_sel, sl);
+        const double dt = -lane_value(dr_ln, sl) / R;
+        sl++;
+        draws++;
+        const double tn = t + dt;
+        if (horizon > 0.0 && tn > t_end) {
+            t = t_end;
+            break;
+        }
+        t = tn;
+        // slot: the first whose inclusive prefix exceeds y; then the direction
+        const double y = u_sel * R;
+        const uint64_t mk = __ballot(valid && incl > y);
+        int r;
+        bool fb = false;
+        if (mk) {
+            r = __ffsll((unsigned long long)mk) - 1;
+        } else {
+            r = 63 - __clzll((long long)__ballot(tot > 0.0));  // y rounded up to R
+            fb = true;
+        }
+        const double c0 = lane_value(incl, r) - lane_value(tot, r);
+        const double kv = lane < 8 ? krate[r * 8 + lane] : 0.0;
+        const double cs = seg_scan<8>(kv, lane & 7) + c0;
+        const uint64_t md = fb ? 0ull : __ballot(lane < 8 && cs > y);
+        const int d = md ? __ffsll((unsigned long long)md) - 1
+                         : 63 - __clzll((long long)__ballot(lane < 8 && kv > 0.0));
+        const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)pos, r);
+        const int SX = sx & 2047, SY = (sx >> 11) & 2047, SZ = sx >> 22;
+        const int ts = site_type(SX, SY);
+        int hx, hy, hz;
+        hop_vec(ts, d, hx, hy, hz);
+        int TX = SX + hx, TY = SY + hy, TZ = SZ + hz;
+        if (TX < 0) TX += 2 * L0;
+        if (TX >= 2 * L0) TX -= 2 * L0;
+        if (TY < 0) TY += 2 * L1;
+        if (TY >= 2 * L1) TY -= 2 * L1;
+        if (TZ < 0) TZ += 2 * L2;
+        if (TZ >= 2 * L2) TZ -= 2 * L2;
+        const uint32_t tx = pack_dbl(TX, TY, TZ);
+        const int tt = site_type(TX, TY);
+        const int cs_i = canon_dbl(L0, L1, SX, SY, SZ), ct_i = canon_dbl(L0, L1, TX, TY, TZ);
+        const int sp = slab[ct_i];
+        wave_lds_fence();
+        if (lane == 0) {
+            slab[cs_i] = (unsigned char)sp;
+            slab[ct_i] = (unsigned char)kSpV;
+        }
+        if (lane == r) pos = tx;
+        if (sp == kSpO) ho++;
+        else hh++;
+        rec_hop(rec, rc, disp, lane, D.disp_off + plain_offset(L0, L1, L2, SX >> 1, SY >> 1, SZ >> 1, ts),
+                D.disp_off + plain_offset(L0, L1, L2, TX >> 1, TY >> 1, TZ >> 1, tt), hx, hy, hz);
+        done++;
+        wave_lds_fence();
+        // slots whose events changed: the moved vacancy and those next to its two sites
+        uint64_t aff = __ballot(valid && (lane == r || nn_dbl(L0, L1, L2, pos, sx) || nn_dbl(L0, L1, L2, pos, tx)));
+        while (aff) {
+            const int a = __ffsll((unsigned long long)aff) - 1;
+            aff &= aff - 1;
+            const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)pos, a);
+            const double nt = plain_slot_rates(C, slab, krate, a, pa, lane);
+            const double delta = nt - lane_value(tot, a);
+            if (lane == a) tot = nt;
+            if (lane >= a) incl += delta;
+            R += delta;
+        }
+    }
+    if (lane == 0) {
+        St->t = t;
+        St->draws = draws;
+        St->hops[0] += ho;
+        St->hops[1] += hh;
+    }
+}
+
 // Persistent batched kernel: one workgroup per lattice runs the whole call
 // (cycles of 8 phases, workgroup barrier between phases), so every lattice
 // advances at its own pace.  A lattice that fits is kept in LDS for the
 // whole call with a list of its vacancies; otherwise each wave stages its
 // tiles' footprints from HBM.  Each wave runs groups of D.group tiles.  A
 // lattice whose phase is one group runs on wave 0 alone, without barriers,
-// and keeps its displacement records across phases.
+// and keeps its displacement records across phases.  Plain lattices held in
+// LDS run plain BKL on wave 0.
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_batch(DevPtrs P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1370,7 +1548,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             const int i = (int)(cell % D.L[0]);
             const int j = (int)((cell / D.L[0]) % D.L[1]);
             const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-            region[c] = (unsigned char)occ_lat[store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)];
+            region[c] = (unsigned char)occ_lat[D.plain ? plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)
+                                                       : store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)];
         }
     } else if (resident) {
         const int nch = (int)((nbytes + 15) >> 4);
@@ -1401,7 +1580,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     const bool solo = ngroups == 1;
     // a lattice run by one wave keeps every colour's tile records in LDS
     TileRec* rcache = (TileRec*)(smem + P.lds_region_bytes + nw * kWaveScratch);
-    if (solo)
+    if (solo && !D.plain)
         for (int j = threadIdx.x; j < 8 * ntiles; j += blockDim.x)
             rcache[j] = P.tiles[(size_t)(j / ntiles) * P.n_tiles + D.tile0 + j % ntiles];
     __syncthreads();
@@ -1423,7 +1602,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     RecCtl rc;
     rec_init(rec, rc);
     uint64_t ncyc = 0;
-    if (fast) {
+    if (fast && D.plain) {
+        if (wv == 0) {
+            const RateCtx C = {D.L[0], D.L[1], D.L[2], D.gb_period, D.gb_mask, W.k12};
+            solo_plain(D, region, vlist, nv_list, (double*)c2s, C, P.disp, St, Cl, lane, rec, rc);
+        }
+    } else if (fast) {
         if (wv == 0) {
             const RateCtx C = {D.L[0], D.L[1], D.L[2], D.gb_period, D.gb_mask, W.k12};
             unsigned long long fo = 0, fh = 0;
@@ -1473,7 +1657,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             const int i = (int)(cell % D.L[0]);
             const int j = (int)((cell / D.L[0]) % D.L[1]);
             const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-            occ_lat[store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)] = (int8_t)region[c];
+            occ_lat[D.plain ? plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)
+                            : store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)] = (int8_t)region[c];
         }
     } else if (resident) {
         const int nch = (int)(nbytes >> 4);
@@ -1539,13 +1724,9 @@ struct PlainSlot {
     uint64_t packed;  // i | j << 16 | k << 32 | t << 48
 };
 
-// Storage offset in plain mode: the whole lattice is one brick.
 __device__ __forceinline__ int64_t plain_store(const LatDesc& D, int i, int j, int k, int t)
 {
-    const int64_t V = (int64_t)D.L[0] * D.L[1] * D.L[2];
-    if (t == 0) return ((int64_t)i * D.L[2] + k) * D.L[1] + j;
-    if (t == 1) return V + ((int64_t)j * D.L[2] + k) * D.L[0] + i;
-    return 2 * V + ((int64_t)k * D.L[1] + j) * D.L[0] + i;
+    return plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t);
 }
 
 __device__ __forceinline__ double plain_rate(const LatDesc& D, const DevPtrs& P, uint64_t pk,
@@ -1605,6 +1786,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
     __shared__ int ev_sh;
     __shared__ int hop_slot;
     __shared__ uint64_t hop_s, hop_t;  // packed positions of the hop's two sites
+    const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
     const int lat = ids[blockIdx.x];
     const LatDesc& D = P.desc[lat];
     LatState* S = P.state + lat;
@@ -1785,6 +1967,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
         S->draws = draws;
         S->hops[0] += ho;
         S->hops[1] += hh;
+        S->busy_ticks = __builtin_amdgcn_s_memrealtime() - t_begin;
     }
 }
 

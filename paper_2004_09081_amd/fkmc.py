@@ -109,6 +109,7 @@ _SIGS = {
     "fkmc_set_schedule": [C.c_void_p, C.c_int32, C.c_int32],
     "fkmc_set_graph": [C.c_void_p, C.c_int32],
     "fkmc_set_group": [C.c_void_p, C.c_int32],
+    "fkmc_set_plain_lds": [C.c_void_p, C.c_int32],
     "fkmc_checkpoint_size": [C.c_void_p, C.c_uint32, _P(C.c_size_t)],
     "fkmc_checkpoint": [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t],
     "fkmc_restore": [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t],
@@ -270,6 +271,11 @@ class LatticeSet:
     def set_group(self, group: int = 0):
         """Tiles per wavefront (0 automatic; 1, 2, 4 or 8)."""
         _check(lib().fkmc_set_group(self._h, int(group)))
+
+    def set_plain_lds(self, on: bool):
+        """Plain lattices that fit run in LDS in the persistent kernel (True,
+        default) or every plain lattice runs the HBM kernel (False)."""
+        _check(lib().fkmc_set_plain_lds(self._h, 1 if on else 0))
 
     def set_timing(self, on: bool):
         _check(lib().fkmc_set_timing(self._h, 1 if on else 0))

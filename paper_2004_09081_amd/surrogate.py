@@ -156,10 +156,11 @@ def kmc_labels(specs, hop_target: int = 0, waves: int = 4, cycles: int = 0,
         s.init_random([sp.n_vac for sp in specs], [sp.n_h for sp in specs])
         s.set_rates(rates)
         s.set_schedule(schedule, waves)
+        ts = [0.0 if sp.frag[0] == 0 else sp.t_sync for sp in specs]  # plain: no horizon
         if cycles:
-            s.advance([sp.t_sync for sp in specs], max_cycles=cycles, min_hops=0)
+            s.advance(ts, max_cycles=cycles, min_hops=0)
         else:
-            s.advance([sp.t_sync for sp in specs], max_cycles=10**9, min_hops=hop_target)
+            s.advance(ts, max_cycles=10**9, min_hops=hop_target)
         st = s.read_stats()
     finally:
         s.close()

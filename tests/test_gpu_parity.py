@@ -101,15 +101,26 @@ PLAIN_CASES = {
     "plain_H": Case((6, 5, 7), seed=9, lattice_id=3, nv=20, nh=50, T=650.0, Ea_O=0.6, Ea_H=0.45),
     "plain_field_gb": Case((6, 6, 6), seed=10, nv=8, nh=0, T=500.0, Ea_O=0.5, E_z=2e8,
                            gb_period=3, gb_dE=0.1),
+    # 64 vacancies on 192 sites: most hops change a neighbouring slot too
+    "dense_64": Case((4, 4, 4), seed=12, lattice_id=5, nv=64, nh=40, T=700.0, Ea_O=0.6, Ea_H=0.5),
+    # one vacancy more than the LDS path holds: the HBM kernel runs it
+    "dense_65": Case((5, 4, 4), seed=13, nv=65, nh=10, T=700.0, Ea_O=0.6, Ea_H=0.5),
+    "edge2": Case((2, 3, 2), seed=14, nv=3, nh=4, T=650.0, Ea_O=0.6, Ea_H=0.5, E_z=1e8),
+    "ragged_gb": Case((9, 7, 11), seed=15, lattice_id=9, nv=33, nh=90, T=550.0, Ea_O=0.55,
+                      Ea_H=0.4, E_z=5e7, gb_period=4, gb_mask=7, gb_dE=0.08),
 }
 
 
+@pytest.mark.parametrize("lds", [True, False], ids=["lds", "hbm"])
 @pytest.mark.parametrize("name", list(PLAIN_CASES))
-def test_plain_matches_oracle(name):
+def test_plain_matches_oracle(name, lds):
+    """Plain BKL, in LDS on one wavefront (at most 64 vacancies) or in HBM on
+    a workgroup: draws, clock, hop counts and state equal the oracle's."""
     c = PLAIN_CASES[name]
-    say("plain parity", name)
+    say("plain parity", name, "lds" if lds else "hbm")
     lat = c.oracle()
     g = gpu_set([c])
+    g.set_plain_lds(lds)
     for n_hops in (1000, 2500):
         lat.advance_plain(n_hops)
         g.advance([0.0], 0, n_hops)
@@ -126,7 +137,36 @@ def test_plain_matches_oracle(name):
     st = g.read_stats()[0]
     assert lat.t == t0 + horizon
     assert st["t"] == lat.t and st["draws"] == lat.draws
+    assert st["lds_resident"] == (1 if lds and c.nv <= 64 else 0)
     assert_same_state(g, 0, lat, name + " horizon")
+
+
+def test_plain_lds_in_ensemble_launch():
+    """Plain lattices held in LDS share the persistent launch with fragment
+    lattices (hop targets: exact for plain, per cycle for fragments)."""
+    cases = [Case((10, 10, 10), (5, 5, 5), seed=31, lattice_id=i, nv=12 + 3 * i, nh=20, T=650.0,
+                  Ea_O=0.6, Ea_H=0.5) for i in range(3)]
+    cases += [Case((7, 8, 6), seed=31, lattice_id=10 + i, nv=5 + 17 * i, nh=30, T=600.0 + 50 * i,
+                   Ea_O=0.6, Ea_H=0.45, E_z=1e8 * i) for i in range(4)]
+    say("plain LDS lattices in the persistent launch", len(cases))
+    lats = [c.oracle() for c in cases]
+    ts = [0.0 if l.g.plain else 1.0 / (8.0 * l.k12[0]) for l in lats]
+    g = gpu_set(cases)
+    g.set_schedule("persistent", 4)
+    for rep in range(2):
+        for lat, t in zip(lats, ts):
+            if lat.g.plain:
+                lat.advance_plain(1500)
+            else:
+                lat.advance(t, max_cycles=10**6, min_hops=1500)
+        g.advance(ts, max_cycles=10**6, min_hops=1500)
+        st = g.read_stats()
+        for i, lat in enumerate(lats):
+            assert_same_state(g, i, lat, "member %d call %d" % (i, rep))
+            assert st[i]["t"] == lat.t
+            assert st[i]["hops"].tolist() == [int(x) for x in lat.hops]
+            if lat.g.plain:
+                assert st[i]["draws"] == lat.draws and st[i]["lds_resident"] == 1
 
 
 def test_batched_set_matches_oracle():
