@@ -793,11 +793,12 @@ static int batch_lds_bound(const fkmc_lattice* L)
 }
 
 // LDS of a plain lattice run by the persistent kernel: canonical occupancy,
-// vacancy list, and the 8 rates of every slot.
+// vacancy list, and the 8 rates of every slot (64, 128 or 256 slots).
 static int64_t plain_lds_bytes(const fkmc_lattice* L, uint32_t i)
 {
-    return ((L->desc[i].n_sites + 15) & ~(int64_t)15) + 4 * (((int64_t)L->n_vac[i] + 3) & ~3) +
-           8 * 8 * kPlainLdsSlots;
+    const uint64_t nv = L->n_vac[i];
+    const int64_t slots = nv <= 64 ? 64 : (nv <= 128 ? 128 : 256);
+    return ((L->desc[i].n_sites + 15) & ~(int64_t)15) + 4 * (((int64_t)nv + 3) & ~3) + 8 * 8 * slots;
 }
 
 static bool plain_lds_fits(const fkmc_lattice* L, uint32_t i)

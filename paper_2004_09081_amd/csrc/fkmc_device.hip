@@ -373,16 +373,20 @@ __device__ __forceinline__ uint32_t hop_target_xyz(uint32_t xyz, int d, int& hx,
 
 // ----------------------------------------------------------------------------
 // Displacement records.  A particle that hops gets a record in one lane of
-// the wave: the displacement index of its current site, its displacement
-// when the record opened (read from HBM then) and the hops since.  Records
-// are keyed by displacement index, so they stay valid across tiles and
-// phases for as long as one wave alone moves the lattice's particles; a
-// flush writes every record's displacement to its particle's current site
-// (all reads completed before any write).
+// the wave: the displacement index of its current site, the index of the
+// site it occupied when the record opened, and the hops since.  Records are
+// keyed by displacement index, so they stay valid across tiles and phases
+// for as long as one wave alone moves the lattice's particles.  Between two
+// flushes only this wave writes the entries of the sites its records touch,
+// and a record opens only for a particle on a site no hop has touched since
+// the last flush, so every origin still holds its particle's displacement in
+// HBM: a flush reads all origins (one round trip for all records, no load in
+// flight between flushes), waits, then writes each particle's displacement
+// to its current site.
 struct Rec {
-    int64_t cur;  // < 0: free
+    int64_t cur;   // < 0: free
+    int64_t orig;
     int ax, ay, az;
-    int4 old;
 };
 
 struct RecCtl {
@@ -393,8 +397,8 @@ struct RecCtl {
 __device__ __forceinline__ void rec_init(Rec& r, RecCtl& c)
 {
     r.cur = -1;
+    r.orig = 0;
     r.ax = r.ay = r.az = 0;
-    r.old = make_int4(0, 0, 0, 0);
     c.n = 0;
     c.pending = false;
 }
@@ -402,9 +406,15 @@ __device__ __forceinline__ void rec_init(Rec& r, RecCtl& c)
 __device__ __forceinline__ void rec_flush(Rec& r, RecCtl& c, int4* disp)
 {
     if (c.n == 0) return;
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): every record's read has returned
+    if (c.pending) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the last flush's stores have landed
+        __builtin_amdgcn_wave_barrier();
+    }
+    int4 o = make_int4(0, 0, 0, 0);
+    if (r.cur >= 0) o = disp[r.orig];
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // every read has returned before any write
     __builtin_amdgcn_wave_barrier();
-    if (r.cur >= 0) disp[r.cur] = make_int4(r.old.x + r.ax, r.old.y + r.ay, r.old.z + r.az, 0);
+    if (r.cur >= 0) disp[r.cur] = make_int4(o.x + r.ax, o.y + r.ay, o.z + r.az, 0);
     r.cur = -1;
     r.ax = r.ay = r.az = 0;
     c.n = 0;
@@ -423,29 +433,18 @@ __device__ __forceinline__ void rec_hop(Rec& r, RecCtl& c, int4* disp, int lane,
         mv = 0;
         mi = 0;
     }
-    if (c.pending && (mv == 0 || mi == 0)) {
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // the flushed stores have landed
-        __builtin_amdgcn_wave_barrier();
-        c.pending = false;
-    }
     int lv, li;
     if (mv) {
         lv = __ffsll((unsigned long long)mv) - 1;
     } else {
         lv = c.n++;
-        if (lane == lv) {
-            r.cur = ks;
-            r.old = disp[ks];
-        }
+        if (lane == lv) r.orig = ks;
     }
     if (mi) {
         li = __ffsll((unsigned long long)mi) - 1;
     } else {
         li = c.n++;
-        if (lane == li) {
-            r.cur = kt;
-            r.old = disp[kt];
-        }
+        if (lane == li) r.orig = kt;
     }
     const int sv = lane == lv ? 1 : (lane == li ? -1 : 0);
     r.cur = lane == lv ? kt : (lane == li ? ks : r.cur);
@@ -1344,16 +1343,17 @@ __device__ __forceinline__ void solo_fast(const LatDesc& D, unsigned char* slab,
 
 // ----------------------------------------------------------------------------
 // Plain BKL (Eqs. TransitionProb, eventSelection, TimeStep) on a lattice held
-// in LDS in canonical order, with at most 64 vacancies, on one wave.  Lane s
-// holds slot s: the slots are the vacancies in canonical order at the start
-// of the call, and a slot follows its vacancy.  Each lane keeps its slot's
-// rate total and the inclusive prefix of the totals; the 8 rates of every
-// slot sit in LDS.  A hop changes the events of the moved vacancy and of the
-// vacancies next to its two sites only: lanes 0-7 recompute such a slot's
-// rates (one direction each), and the prefix sums of that slot and every
-// later one move by the change of its total.  The rates are multiples of one
-// power of two with every partial sum below 2^53 of them, so these updates
-// give exactly the sums of a fresh pass in event order.
+// in LDS in canonical order, with at most 256 vacancies, on one wave.  The
+// slots are the vacancies in canonical order at the start of the call (a
+// slot follows its vacancy); lane l holds the P = 1, 2 or 4 consecutive
+// slots l*P .. l*P+P-1 with their rate totals, the lane's total and the
+// inclusive prefix of the lane totals.  The 8 rates of every slot sit in
+// LDS.  A hop changes the events of the moved vacancy and of the vacancies
+// next to its two sites only: lanes 0-7 recompute such a slot's rates (one
+// direction each), and the prefix sums of that lane and every later one
+// move by the change of its total.  The rates are multiples of one power of
+// two with every partial sum below 2^53 of them, so these updates give
+// exactly the sums of a fresh pass in event order.
 
 // Storage offset in plain mode: the whole lattice is one brick.
 __device__ __forceinline__ int64_t plain_offset(int L0, int L1, int L2, int i, int j, int k, int t)
@@ -1378,40 +1378,79 @@ __device__ __forceinline__ double plain_slot_rates(const RateCtx& C, const unsig
     return lane_value(seg_scan<8>(k, lane & 7), 7);
 }
 
+constexpr int kPlainPerLane = 4;  // slots per lane at most (256 vacancies)
+
 // Runs the call: exactly min_hops hops, stopping early when the next event
 // would land after t + t_sync (t_sync > 0; the clock then takes that value
 // and the draw is spent) or no event is possible.  Draw d uses Philox
 // counter (d_lo, d_hi, 0xFFFFFFFF, 3); draws are computed 64 ahead, one per
-// lane.  vlist holds the nv vacancies (i | j << 10 | k << 20 | t << 30).
-__device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab, const uint32_t* vlist, int nv,
+// lane.  vlist holds the nv vacancies (i | j << 10 | k << 20 | t << 30) and
+// is reordered here into slot order.
+__device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab, uint32_t* vlist, int nv,
                                            double* krate, const RateCtx& C, int4* disp, LatState* St,
                                            const LatCall* Cl, int lane, Rec& rec, RecCtl& rc)
 {
+    constexpr int PM = kPlainPerLane;
+    // descriptor fields in registers: the loop stores to global memory, so
+    // fields read through D would be loaded again (and waited for) each step
     const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
-    const bool valid = lane < nv;
-    uint32_t p0 = 0;
-    int key = 0x7fffffff;
-    if (valid) {
-        const uint32_t g = vlist[lane];
-        const int i = g & 1023, j = (g >> 10) & 1023, k = (g >> 20) & 1023, t = g >> 30;
-        p0 = pack_dbl(2 * i + (t != 0), 2 * j + (t != 1), 2 * k + (t != 2));
-        key = ((k * L1 + j) * L0 + i) * 3 + t;
-    }
-    // slot = canonical rank at call start; unused lanes keep their place
-    int rank = valid ? 0 : lane;
-    for (int j = 0; j < nv; j++) rank += (valid && __builtin_amdgcn_readlane(key, j) < key) ? 1 : 0;
-    uint32_t pos = (uint32_t)__builtin_amdgcn_ds_permute(rank << 2, (int)p0);
-    double tot = 0.0;
-    if (valid) {
-        const int Xs = pos & 2047, Ys = (pos >> 11) & 2047, Zs = pos >> 22;
-#pragma nounroll
-        for (int d = 0; d < 8; d++) {
-            const double k = dbl_rate(C, slab, Xs, Ys, Zs, d);
-            krate[lane * 8 + d] = k;
-            tot += k;
+    const int64_t disp_off = D.disp_off;
+    const uint32_t seed = D.seed, lid = D.lattice_id;
+    const int P = nv <= 64 ? 1 : (nv <= 128 ? 2 : 4);
+    // slot = canonical rank at call start: vacancy lane + 64 q is ranked,
+    // then written to vlist[rank] as packed doubled coordinates
+    uint32_t pv[PM];
+    int key[PM];
+#pragma unroll
+    for (int q = 0; q < PM; q++) {
+        const int v = lane + 64 * q;
+        pv[q] = 0;
+        key[q] = 0x7fffffff;
+        if (v < nv) {
+            const uint32_t g = vlist[v];
+            const int i = g & 1023, j = (g >> 10) & 1023, k = (g >> 20) & 1023, t = g >> 30;
+            pv[q] = pack_dbl(2 * i + (t != 0), 2 * j + (t != 1), 2 * k + (t != 2));
+            key[q] = ((k * L1 + j) * L0 + i) * 3 + t;
         }
     }
-    double incl = wave_scan_dpp(tot);
+    // (register arrays are indexed by unrolled constants only, so that they
+    // stay in registers)
+    int rank[PM] = {0, 0, 0, 0};
+#pragma unroll
+    for (int qq = 0; qq < PM; qq++) {
+        const int n_q = nv - 64 * qq < 64 ? nv - 64 * qq : 64;
+        for (int l = 0; l < n_q; l++) {
+            const int kv = __builtin_amdgcn_readlane(key[qq], l);
+#pragma unroll
+            for (int q = 0; q < PM; q++) rank[q] += kv < key[q] ? 1 : 0;
+        }
+    }
+    wave_lds_fence();
+#pragma unroll
+    for (int q = 0; q < PM; q++)
+        if (lane + 64 * q < nv) vlist[rank[q]] = pv[q];
+    wave_lds_fence();
+    uint32_t pos[PM];
+    double tot[PM];
+    bool valid[PM];
+#pragma unroll
+    for (int q = 0; q < PM; q++) {
+        const int sidx = lane * P + q;
+        valid[q] = q < P && sidx < nv;
+        pos[q] = valid[q] ? vlist[sidx] : 0u;
+        tot[q] = 0.0;
+        if (valid[q]) {
+            const int Xs = pos[q] & 2047, Ys = (pos[q] >> 11) & 2047, Zs = pos[q] >> 22;
+#pragma nounroll
+            for (int d = 0; d < 8; d++) {
+                const double k = dbl_rate(C, slab, Xs, Ys, Zs, d);
+                krate[sidx * 8 + d] = k;
+                tot[q] += k;
+            }
+        }
+    }
+    double T = (tot[0] + tot[1]) + (tot[2] + tot[3]);
+    double incl = wave_scan_dpp(T);
     double R = lane_value(incl, 63);
     double t = St->t;
     uint64_t draws = St->draws;
@@ -1427,7 +1466,7 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab
         if (sl == 64) {
             const uint64_t di = draws + (uint64_t)lane;
             uint32_t x0, x1, x2, x3;
-            philox10((uint32_t)di, (uint32_t)(di >> 32), 0xFFFFFFFFu, 3u, D.seed, D.lattice_id, x0, x1, x2, x3);
+            philox10((uint32_t)di, (uint32_t)(di >> 32), 0xFFFFFFFFu, 3u, seed, lid, x0, x1, x2, x3);
             dr_sel = u53_lo(x0, x1);
             dr_ln = clock_ln(u53_hi(x2, x3));
             sl = 0;
@@ -1442,24 +1481,45 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab
             break;
         }
         t = tn;
-        // slot: the first whose inclusive prefix exceeds y; then the direction
+        // lane: the first whose inclusive prefix exceeds y; then its slot,
+        // then the direction
         const double y = u_sel * R;
-        const uint64_t mk = __ballot(valid && incl > y);
-        int r;
+        const uint64_t mk = __ballot(lane * P < nv && incl > y);
+        int r, js = -1;
         bool fb = false;
+        double c0 = 0.0;
         if (mk) {
             r = __ffsll((unsigned long long)mk) - 1;
+            double c = lane_value(incl, r) - lane_value(T, r);
+#pragma unroll
+            for (int q = 0; q < PM; q++) {
+                if (q < P && js < 0) {
+                    const double tq = lane_value(tot[q], r);
+                    if (c + tq > y) js = q;
+                    else c += tq;
+                }
+            }
+            c0 = c;
         } else {
-            r = 63 - __clzll((long long)__ballot(tot > 0.0));  // y rounded up to R
+            r = 63 - __clzll((long long)__ballot(T > 0.0));  // y rounded up to R
+#pragma unroll
+            for (int q = 0; q < PM; q++)
+                if (q < P && lane_value(tot[q], r) > 0.0) js = q;
             fb = true;
         }
-        const double c0 = lane_value(incl, r) - lane_value(tot, r);
-        const double kv = lane < 8 ? krate[r * 8 + lane] : 0.0;
+        js = js < 0 ? 0 : js;
+        const int slot = r * P + js;
+        const double kv = lane < 8 ? krate[slot * 8 + lane] : 0.0;
         const double cs = seg_scan<8>(kv, lane & 7) + c0;
         const uint64_t md = fb ? 0ull : __ballot(lane < 8 && cs > y);
         const int d = md ? __ffsll((unsigned long long)md) - 1
                          : 63 - __clzll((long long)__ballot(lane < 8 && kv > 0.0));
-        const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)pos, r);
+        uint32_t sx = 0;
+#pragma unroll
+        for (int q = 0; q < PM; q++) {
+            const uint32_t sq = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], r);
+            if (q == js) sx = sq;
+        }
         const int SX = sx & 2047, SY = (sx >> 11) & 2047, SZ = sx >> 22;
         const int ts = site_type(SX, SY);
         int hx, hy, hz;
@@ -1480,24 +1540,33 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab
             slab[cs_i] = (unsigned char)sp;
             slab[ct_i] = (unsigned char)kSpV;
         }
-        if (lane == r) pos = tx;
+#pragma unroll
+        for (int q = 0; q < PM; q++)
+            if (lane == r && q == js) pos[q] = tx;
         if (sp == kSpO) ho++;
         else hh++;
-        rec_hop(rec, rc, disp, lane, D.disp_off + plain_offset(L0, L1, L2, SX >> 1, SY >> 1, SZ >> 1, ts),
-                D.disp_off + plain_offset(L0, L1, L2, TX >> 1, TY >> 1, TZ >> 1, tt), hx, hy, hz);
+        rec_hop(rec, rc, disp, lane, disp_off + plain_offset(L0, L1, L2, SX >> 1, SY >> 1, SZ >> 1, ts),
+                disp_off + plain_offset(L0, L1, L2, TX >> 1, TY >> 1, TZ >> 1, tt), hx, hy, hz);
         done++;
         wave_lds_fence();
         // slots whose events changed: the moved vacancy and those next to its two sites
-        uint64_t aff = __ballot(valid && (lane == r || nn_dbl(L0, L1, L2, pos, sx) || nn_dbl(L0, L1, L2, pos, tx)));
-        while (aff) {
-            const int a = __ffsll((unsigned long long)aff) - 1;
-            aff &= aff - 1;
-            const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)pos, a);
-            const double nt = plain_slot_rates(C, slab, krate, a, pa, lane);
-            const double delta = nt - lane_value(tot, a);
-            if (lane == a) tot = nt;
-            if (lane >= a) incl += delta;
-            R += delta;
+#pragma unroll
+        for (int q = 0; q < PM; q++) {
+            uint64_t aff = __ballot(valid[q] && ((lane == r && q == js) || nn_dbl(L0, L1, L2, pos[q], sx) ||
+                                                 nn_dbl(L0, L1, L2, pos[q], tx)));
+            while (aff) {
+                const int a = __ffsll((unsigned long long)aff) - 1;
+                aff &= aff - 1;
+                const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], a);
+                const double nt = plain_slot_rates(C, slab, krate, a * P + q, pa, lane);
+                const double delta = nt - lane_value(tot[q], a);
+                if (lane == a) {
+                    tot[q] = nt;
+                    T += delta;
+                }
+                if (lane >= a) incl += delta;
+                R += delta;
+            }
         }
     }
     if (lane == 0) {

@@ -103,8 +103,14 @@ PLAIN_CASES = {
                            gb_period=3, gb_dE=0.1),
     # 64 vacancies on 192 sites: most hops change a neighbouring slot too
     "dense_64": Case((4, 4, 4), seed=12, lattice_id=5, nv=64, nh=40, T=700.0, Ea_O=0.6, Ea_H=0.5),
-    # one vacancy more than the LDS path holds: the HBM kernel runs it
+    # LDS path with 2 and 4 slots per lane, at both ends of each range
     "dense_65": Case((5, 4, 4), seed=13, nv=65, nh=10, T=700.0, Ea_O=0.6, Ea_H=0.5),
+    "slots_128": Case((6, 5, 5), seed=16, lattice_id=2, nv=128, nh=30, T=650.0, Ea_O=0.6, Ea_H=0.5),
+    "slots_129": Case((6, 6, 5), seed=17, nv=129, nh=20, T=650.0, Ea_O=0.6, Ea_H=0.5, E_z=1e8),
+    "slots_256": Case((8, 7, 6), seed=18, lattice_id=4, nv=256, nh=100, T=600.0, Ea_O=0.6,
+                      Ea_H=0.45, gb_period=3, gb_dE=0.05),
+    # one vacancy more than the LDS path holds: the HBM kernel runs it
+    "hbm_257": Case((8, 7, 6), seed=19, nv=257, nh=40, T=600.0, Ea_O=0.6, Ea_H=0.45),
     "edge2": Case((2, 3, 2), seed=14, nv=3, nh=4, T=650.0, Ea_O=0.6, Ea_H=0.5, E_z=1e8),
     "ragged_gb": Case((9, 7, 11), seed=15, lattice_id=9, nv=33, nh=90, T=550.0, Ea_O=0.55,
                       Ea_H=0.4, E_z=5e7, gb_period=4, gb_mask=7, gb_dE=0.08),
@@ -114,8 +120,8 @@ PLAIN_CASES = {
 @pytest.mark.parametrize("lds", [True, False], ids=["lds", "hbm"])
 @pytest.mark.parametrize("name", list(PLAIN_CASES))
 def test_plain_matches_oracle(name, lds):
-    """Plain BKL, in LDS on one wavefront (at most 64 vacancies) or in HBM on
-    a workgroup: draws, clock, hop counts and state equal the oracle's."""
+    """Plain BKL, in LDS on one wavefront (at most 256 vacancies) or in HBM
+    on a workgroup: draws, clock, hop counts and state equal the oracle's."""
     c = PLAIN_CASES[name]
     say("plain parity", name, "lds" if lds else "hbm")
     lat = c.oracle()
@@ -137,7 +143,7 @@ def test_plain_matches_oracle(name, lds):
     st = g.read_stats()[0]
     assert lat.t == t0 + horizon
     assert st["t"] == lat.t and st["draws"] == lat.draws
-    assert st["lds_resident"] == (1 if lds and c.nv <= 64 else 0)
+    assert st["lds_resident"] == (1 if lds and c.nv <= 256 else 0)
     assert_same_state(g, 0, lat, name + " horizon")
 
 
@@ -146,7 +152,7 @@ def test_plain_lds_in_ensemble_launch():
     lattices (hop targets: exact for plain, per cycle for fragments)."""
     cases = [Case((10, 10, 10), (5, 5, 5), seed=31, lattice_id=i, nv=12 + 3 * i, nh=20, T=650.0,
                   Ea_O=0.6, Ea_H=0.5) for i in range(3)]
-    cases += [Case((7, 8, 6), seed=31, lattice_id=10 + i, nv=5 + 17 * i, nh=30, T=600.0 + 50 * i,
+    cases += [Case((7, 8, 6), seed=31, lattice_id=10 + i, nv=5 + 60 * i, nh=30, T=600.0 + 50 * i,
                    Ea_O=0.6, Ea_H=0.45, E_z=1e8 * i) for i in range(4)]
     say("plain LDS lattices in the persistent launch", len(cases))
     lats = [c.oracle() for c in cases]
