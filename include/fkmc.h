@@ -224,10 +224,10 @@ fkmc_status fkmc_set_schedule(fkmc_lattice* lat, int32_t schedule, int32_t waves
 fkmc_status fkmc_set_group(fkmc_lattice* lat, int32_t group);
 
 /* Plain lattices (Eqs. TransitionProb, eventSelection, TimeStep over the
- * whole lattice): with enable = 1 (default) a plain lattice of at most 256
- * vacancies whose occupancy fits in LDS (x and y edges up to 1023 cells, z
- * up to 512) runs in the persistent kernel on one wavefront, its occupancy
- * and per-slot rates held in LDS, in the same launch as the fragment
+ * whole lattice): with enable = 1 (default) a plain lattice of at most 512
+ * vacancies whose occupancy (2 bits per site) and per-slot rates fit in the
+ * persistent kernel's LDS share (x and y edges up to 1023 cells, z up to
+ * 512) runs there on one wavefront, in the same launch as the fragment
  * lattices when those use the persistent schedule; every other plain lattice
  * runs the HBM-resident plain kernel.  enable = 0 sends every plain lattice
  * to the HBM kernel.  Results are identical either way. */

@@ -5,7 +5,7 @@ The fragment edge F sets both the decomposition (part of the simulated
 dynamics, so it is recorded with the results) and the cost: small F gives
 many small tiles per phase, large F few tiles with long serial BKL chains.
 F = 0 is the unfragmented method, plain BKL over the whole lattice, which
-the library runs in LDS on one wavefront for lattices of at most 256
+the library runs in LDS on one wavefront for lattices of at most 512
 vacancies: one hop per step and no phases, the fastest choice for sparse
 small lattices, whose fragment phases hold about one hop each.  For every
 candidate the whole ensemble runs a short trial on the GPU; the kernel's
@@ -18,8 +18,8 @@ from __future__ import annotations
 
 import numpy as np
 
-PLAIN_LDS_VACANCIES = 256
-PLAIN_LDS_BYTES = 60_000
+PLAIN_LDS_VACANCIES = 512
+PLAIN_LDS_BYTES = 62_000
 
 
 def whole_if_sparse(spec) -> int:
@@ -30,12 +30,12 @@ def whole_if_sparse(spec) -> int:
 
 
 def plain_if_sparse(spec) -> int:
-    """Plain BKL (0) for lattices the library holds in LDS (at most 256
-    vacancies, occupancy plus rate cache well inside one workgroup's
-    share), else 16-cell fragments."""
+    """Plain BKL (0) for lattices the library holds in LDS (at most 512
+    vacancies; occupancy at 2 bits per site plus the rate cache inside one
+    workgroup's share), else 16-cell fragments."""
     n = 3 * spec.L[0] * spec.L[1] * spec.L[2]
-    slots = 64 if spec.n_vac <= 64 else (128 if spec.n_vac <= 128 else 256)
-    fits = n + 4 * spec.n_vac + 8 * 8 * slots <= PLAIN_LDS_BYTES
+    slots = next(s for s in (64, 128, 256, 512) if spec.n_vac <= s) if spec.n_vac <= 512 else 512
+    fits = (n + 15) // 16 * 4 + 4 * spec.n_vac + 9 * 8 * slots <= PLAIN_LDS_BYTES
     return 0 if spec.n_vac <= PLAIN_LDS_VACANCIES and fits else 16
 
 

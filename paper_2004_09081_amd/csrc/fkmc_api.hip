@@ -792,13 +792,15 @@ static int batch_lds_bound(const fkmc_lattice* L)
     return L->lds_budget - L->batch_waves * kWaveScratch - kRecCache - 64;
 }
 
-// LDS of a plain lattice run by the persistent kernel: canonical occupancy,
-// vacancy list, and the 8 rates of every slot (64, 128 or 256 slots).
+// LDS of a plain lattice run by the persistent kernel: canonical occupancy
+// at 2 bits per site, vacancy list, and the 8 rates (8 bytes each) and
+// target species (1 byte each) of every slot (64, 128, 256 or 512 slots).
 static int64_t plain_lds_bytes(const fkmc_lattice* L, uint32_t i)
 {
     const uint64_t nv = L->n_vac[i];
-    const int64_t slots = nv <= 64 ? 64 : (nv <= 128 ? 128 : 256);
-    return ((L->desc[i].n_sites + 15) & ~(int64_t)15) + 4 * (((int64_t)nv + 3) & ~3) + 8 * 8 * slots;
+    const int64_t slots = nv <= 64 ? 64 : (nv <= 128 ? 128 : (nv <= 256 ? 256 : 512));
+    const int64_t words = (L->desc[i].n_sites + 15) >> 4;
+    return ((4 * words + 15) & ~(int64_t)15) + 4 * (((int64_t)nv + 3) & ~3) + (8 + 1) * 8 * slots;
 }
 
 static bool plain_lds_fits(const fkmc_lattice* L, uint32_t i)

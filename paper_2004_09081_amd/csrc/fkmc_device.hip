@@ -1343,17 +1343,18 @@ __device__ __forceinline__ void solo_fast(const LatDesc& D, unsigned char* slab,
 
 // ----------------------------------------------------------------------------
 // Plain BKL (Eqs. TransitionProb, eventSelection, TimeStep) on a lattice held
-// in LDS in canonical order, with at most 256 vacancies, on one wave.  The
-// slots are the vacancies in canonical order at the start of the call (a
-// slot follows its vacancy); lane l holds the P = 1, 2 or 4 consecutive
-// slots l*P .. l*P+P-1 with their rate totals, the lane's total and the
-// inclusive prefix of the lane totals.  The 8 rates of every slot sit in
-// LDS.  A hop changes the events of the moved vacancy and of the vacancies
-// next to its two sites only: lanes 0-7 recompute such a slot's rates (one
-// direction each), and the prefix sums of that lane and every later one
-// move by the change of its total.  The rates are multiples of one power of
-// two with every partial sum below 2^53 of them, so these updates give
-// exactly the sums of a fresh pass in event order.
+// in LDS, 2 bits per site in canonical order, with at most 512 vacancies, on
+// one wave.  The slots are the vacancies in canonical order at the start of
+// the call (a slot follows its vacancy); lane l holds the P = 1, 2, 4 or 8
+// consecutive slots l*P .. l*P+P-1 with their rate totals, the lane's total
+// and the inclusive prefix of the lane totals.  The 8 rates of every slot
+// and the species of its 8 targets sit in LDS.  After a hop one 16-lane pass
+// reads the neighbours of both sites: lanes 0-7 give the moved vacancy its
+// new rates, and a vacancy found next to either site (rare) has its slot
+// recomputed; the prefix sums of a changed lane and every later one move by
+// the change of its total.  The rates are multiples of one power of two with
+// every partial sum below 2^53 of them, so these updates give exactly the
+// sums of a fresh pass in event order.
 
 // Storage offset in plain mode: the whole lattice is one brick.
 __device__ __forceinline__ int64_t plain_offset(int L0, int L1, int L2, int i, int j, int k, int t)
@@ -1364,48 +1365,103 @@ __device__ __forceinline__ int64_t plain_offset(int L0, int L1, int L2, int i, i
     return 2 * V + ((int64_t)k * L1 + j) * L0 + i;
 }
 
-// Lanes 0-7: rate of direction `lane` of the vacancy at packed doubled
-// coordinates p, stored as krate[slot*8 + lane].  Returns the slot total
-// (wave-uniform).  All lanes must be active.
-__device__ __forceinline__ double plain_slot_rates(const RateCtx& C, const unsigned char* slab, double* krate,
-                                                   int slot, uint32_t p, int lane)
+// 2-bit species of canonical site c.
+__device__ __forceinline__ int pk_get(const uint32_t* ps, int c)
+{
+    return (int)((ps[c >> 4] >> ((c & 15) << 1)) & 3u);
+}
+
+// Single writer (one lane) per call.
+__device__ __forceinline__ void pk_set(uint32_t* ps, int c, int v)
+{
+    const int sh = (c & 15) << 1;
+    const uint32_t w = ps[c >> 4];
+    ps[c >> 4] = (w & ~(3u << sh)) | ((uint32_t)v << sh);
+}
+
+// Neighbour d of the site at packed doubled coordinates p: its canonical
+// index and packed coordinates, and the column of the rate table (z step,
+// boundary flag): the rate for ion species X is k12[X*6 + col].
+__device__ __forceinline__ int plain_nb(const RateCtx& C, uint32_t p, int d, uint32_t& np, int& col)
+{
+    const int X = p & 2047, Y = (p >> 11) & 2047, Z = p >> 22;
+    const int t = site_type(X, Y);
+    int hx, hy, hz;
+    hop_vec(t, d, hx, hy, hz);
+    int TX = X + hx, TY = Y + hy, TZ = Z + hz;
+    if (TX < 0) TX += 2 * C.L0;
+    if (TX >= 2 * C.L0) TX -= 2 * C.L0;
+    if (TY < 0) TY += 2 * C.L1;
+    if (TY >= 2 * C.L1) TY -= 2 * C.L1;
+    if (TZ < 0) TZ += 2 * C.L2;
+    if (TZ >= 2 * C.L2) TZ -= 2 * C.L2;
+    np = pack_dbl(TX, TY, TZ);
+    int g = 0;
+    if (C.gbp > 0) {
+        const int tt = site_type(TX, TY);
+        g = gb_flag(C, t, pick3(t, X >> 1, Y >> 1, Z >> 1)) |
+            gb_flag(C, tt, pick3(tt, TX >> 1, TY >> 1, TZ >> 1));
+    }
+    col = (hz + 1) * 2 + g;
+    return canon_dbl(C.L0, C.L1, TX, TY, TZ);
+}
+
+// Rate of a hop onto a target holding species sp (0 for a vacancy); the
+// table entries of both ions are read together with the target.
+__device__ __forceinline__ double plain_rate_of(const RateCtx& C, const uint32_t* ps, int cn, int col, int& sp)
+{
+    const double kO = C.k12[col], kH = C.k12[6 + col];
+    sp = pk_get(ps, cn);
+    return sp == kSpO ? kO : (sp == kSpH ? kH : 0.0);
+}
+
+// Lanes 0-7: rate and target species of direction `lane` of the vacancy at
+// packed doubled coordinates p, stored for slot `slot`.  Returns the slot
+// total (wave-uniform).  All lanes must be active.
+__device__ __forceinline__ double plain_slot_rates(const RateCtx& C, const uint32_t* ps, double* krate,
+                                                   unsigned char* kspec, int slot, uint32_t p, int lane)
 {
     double k = 0.0;
     if (lane < 8) {
-        k = dbl_rate(C, slab, p & 2047, (p >> 11) & 2047, p >> 22, lane);
+        uint32_t np;
+        int col, sp;
+        const int cn = plain_nb(C, p, lane, np, col);
+        k = plain_rate_of(C, ps, cn, col, sp);
         krate[slot * 8 + lane] = k;
+        kspec[slot * 8 + lane] = (unsigned char)sp;
     }
     return lane_value(seg_scan<8>(k, lane & 7), 7);
 }
-
-constexpr int kPlainPerLane = 4;  // slots per lane at most (256 vacancies)
 
 // Runs the call: exactly min_hops hops, stopping early when the next event
 // would land after t + t_sync (t_sync > 0; the clock then takes that value
 // and the draw is spent) or no event is possible.  Draw d uses Philox
 // counter (d_lo, d_hi, 0xFFFFFFFF, 3); draws are computed 64 ahead, one per
 // lane.  vlist holds the nv vacancies (i | j << 10 | k << 20 | t << 30) and
-// is reordered here into slot order.
-__device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab, uint32_t* vlist, int nv,
-                                           double* krate, const RateCtx& C, int4* disp, LatState* St,
-                                           const LatCall* Cl, int lane, Rec& rec, RecCtl& rc)
+// is reordered here into slot order.  P = slots per lane (nv <= 64 P).
+// (Register arrays are indexed by unrolled constants only, so that they
+// stay in registers.)
+template <int P>
+__device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint32_t* vlist, int nv,
+                                           double* krate, unsigned char* kspec, const RateCtx& C, int4* disp,
+                                           LatState* St, const LatCall* Cl, int lane, Rec& rec, RecCtl& rc)
 {
-    constexpr int PM = kPlainPerLane;
+    constexpr int PM = P;
     // descriptor fields in registers: the loop stores to global memory, so
     // fields read through D would be loaded again (and waited for) each step
     const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
     const int64_t disp_off = D.disp_off;
     const uint32_t seed = D.seed, lid = D.lattice_id;
-    const int P = nv <= 64 ? 1 : (nv <= 128 ? 2 : 4);
     // slot = canonical rank at call start: vacancy lane + 64 q is ranked,
     // then written to vlist[rank] as packed doubled coordinates
     uint32_t pv[PM];
-    int key[PM];
+    int key[PM], rank[PM];
 #pragma unroll
     for (int q = 0; q < PM; q++) {
         const int v = lane + 64 * q;
         pv[q] = 0;
         key[q] = 0x7fffffff;
+        rank[q] = 0;
         if (v < nv) {
             const uint32_t g = vlist[v];
             const int i = g & 1023, j = (g >> 10) & 1023, k = (g >> 20) & 1023, t = g >> 30;
@@ -1413,9 +1469,6 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab
             key[q] = ((k * L1 + j) * L0 + i) * 3 + t;
         }
     }
-    // (register arrays are indexed by unrolled constants only, so that they
-    // stay in registers)
-    int rank[PM] = {0, 0, 0, 0};
 #pragma unroll
     for (int qq = 0; qq < PM; qq++) {
         const int n_q = nv - 64 * qq < 64 ? nv - 64 * qq : 64;
@@ -1436,20 +1489,25 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab
 #pragma unroll
     for (int q = 0; q < PM; q++) {
         const int sidx = lane * P + q;
-        valid[q] = q < P && sidx < nv;
+        valid[q] = sidx < nv;
         pos[q] = valid[q] ? vlist[sidx] : 0u;
         tot[q] = 0.0;
         if (valid[q]) {
-            const int Xs = pos[q] & 2047, Ys = (pos[q] >> 11) & 2047, Zs = pos[q] >> 22;
 #pragma nounroll
             for (int d = 0; d < 8; d++) {
-                const double k = dbl_rate(C, slab, Xs, Ys, Zs, d);
+                uint32_t np;
+                int col, sp;
+                const int cn = plain_nb(C, pos[q], d, np, col);
+                const double k = plain_rate_of(C, ps, cn, col, sp);
                 krate[sidx * 8 + d] = k;
+                kspec[sidx * 8 + d] = (unsigned char)sp;
                 tot[q] += k;
             }
         }
     }
-    double T = (tot[0] + tot[1]) + (tot[2] + tot[3]);
+    double T = 0.0;
+#pragma unroll
+    for (int q = 0; q < PM; q++) T += tot[q];
     double incl = wave_scan_dpp(T);
     double R = lane_value(incl, 63);
     double t = St->t;
@@ -1491,12 +1549,16 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab
         if (mk) {
             r = __ffsll((unsigned long long)mk) - 1;
             double c = lane_value(incl, r) - lane_value(T, r);
+            if (P == 1) {
+                js = 0;
+            } else {
 #pragma unroll
-            for (int q = 0; q < PM; q++) {
-                if (q < P && js < 0) {
-                    const double tq = lane_value(tot[q], r);
-                    if (c + tq > y) js = q;
-                    else c += tq;
+                for (int q = 0; q < PM; q++) {
+                    if (js < 0) {
+                        const double tq = lane_value(tot[q], r);
+                        if (c + tq > y) js = q;
+                        else c += tq;
+                    }
                 }
             }
             c0 = c;
@@ -1504,68 +1566,95 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, unsigned char* slab
             r = 63 - __clzll((long long)__ballot(T > 0.0));  // y rounded up to R
 #pragma unroll
             for (int q = 0; q < PM; q++)
-                if (q < P && lane_value(tot[q], r) > 0.0) js = q;
+                if (lane_value(tot[q], r) > 0.0) js = q;
             fb = true;
         }
         js = js < 0 ? 0 : js;
         const int slot = r * P + js;
         const double kv = lane < 8 ? krate[slot * 8 + lane] : 0.0;
+        const int kspv = lane < 8 ? (int)kspec[slot * 8 + lane] : 0;
         const double cs = seg_scan<8>(kv, lane & 7) + c0;
         const uint64_t md = fb ? 0ull : __ballot(lane < 8 && cs > y);
         const int d = md ? __ffsll((unsigned long long)md) - 1
                          : 63 - __clzll((long long)__ballot(lane < 8 && kv > 0.0));
+        const int sp = __builtin_amdgcn_readlane(kspv, d);
         uint32_t sx = 0;
+        double tot_old = 0.0;
 #pragma unroll
         for (int q = 0; q < PM; q++) {
-            const uint32_t sq = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], r);
-            if (q == js) sx = sq;
+            if (q == js) {
+                sx = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], r);
+                tot_old = lane_value(tot[q], r);
+            }
         }
+        uint32_t tx;
+        int colx;
+        const int ct_i = plain_nb(C, sx, d, tx, colx);
         const int SX = sx & 2047, SY = (sx >> 11) & 2047, SZ = sx >> 22;
-        const int ts = site_type(SX, SY);
-        int hx, hy, hz;
-        hop_vec(ts, d, hx, hy, hz);
-        int TX = SX + hx, TY = SY + hy, TZ = SZ + hz;
-        if (TX < 0) TX += 2 * L0;
-        if (TX >= 2 * L0) TX -= 2 * L0;
-        if (TY < 0) TY += 2 * L1;
-        if (TY >= 2 * L1) TY -= 2 * L1;
-        if (TZ < 0) TZ += 2 * L2;
-        if (TZ >= 2 * L2) TZ -= 2 * L2;
-        const uint32_t tx = pack_dbl(TX, TY, TZ);
-        const int tt = site_type(TX, TY);
-        const int cs_i = canon_dbl(L0, L1, SX, SY, SZ), ct_i = canon_dbl(L0, L1, TX, TY, TZ);
-        const int sp = slab[ct_i];
-        wave_lds_fence();
+        const int TX = tx & 2047, TY = (tx >> 11) & 2047, TZ = tx >> 22;
+        const int cs_i = canon_dbl(L0, L1, SX, SY, SZ);
         if (lane == 0) {
-            slab[cs_i] = (unsigned char)sp;
-            slab[ct_i] = (unsigned char)kSpV;
+            pk_set(ps, cs_i, sp);
+            pk_set(ps, ct_i, kSpV);
         }
 #pragma unroll
         for (int q = 0; q < PM; q++)
             if (lane == r && q == js) pos[q] = tx;
         if (sp == kSpO) ho++;
         else hh++;
-        rec_hop(rec, rc, disp, lane, disp_off + plain_offset(L0, L1, L2, SX >> 1, SY >> 1, SZ >> 1, ts),
-                disp_off + plain_offset(L0, L1, L2, TX >> 1, TY >> 1, TZ >> 1, tt), hx, hy, hz);
+        int hx, hy, hz;
+        hop_vec(site_type(SX, SY), d, hx, hy, hz);
+        rec_hop(rec, rc, disp, lane,
+                disp_off + plain_offset(L0, L1, L2, SX >> 1, SY >> 1, SZ >> 1, site_type(SX, SY)),
+                disp_off + plain_offset(L0, L1, L2, TX >> 1, TY >> 1, TZ >> 1, site_type(TX, TY)), hx, hy, hz);
         done++;
-        wave_lds_fence();
-        // slots whose events changed: the moved vacancy and those next to its two sites
+        // one pass over the neighbours of both sites: lanes 0-7 around the
+        // moved vacancy's new site (its new rates), lanes 8-15 around its old
+        // site (now the ion); a vacancy there (other than the mover) has
+        // changed events
+        uint32_t nb = 0;
+        int spn = kSpO;
+        double kn = 0.0;
+        if (lane < 16) {
+            int col;
+            const int cn = plain_nb(C, lane < 8 ? tx : sx, lane & 7, nb, col);
+            kn = plain_rate_of(C, ps, cn, col, spn);
+            if (lane < 8) {
+                krate[slot * 8 + lane] = kn;
+                kspec[slot * 8 + lane] = (unsigned char)spn;
+            } else {
+                kn = 0.0;
+            }
+        }
+        {
+            const double nt = lane_value(seg_scan<8>(kn, lane & 7), 7);
+            const double delta = nt - tot_old;
 #pragma unroll
-        for (int q = 0; q < PM; q++) {
-            uint64_t aff = __ballot(valid[q] && ((lane == r && q == js) || nn_dbl(L0, L1, L2, pos[q], sx) ||
-                                                 nn_dbl(L0, L1, L2, pos[q], tx)));
-            while (aff) {
-                const int a = __ffsll((unsigned long long)aff) - 1;
-                aff &= aff - 1;
-                const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], a);
-                const double nt = plain_slot_rates(C, slab, krate, a * P + q, pa, lane);
-                const double delta = nt - lane_value(tot[q], a);
-                if (lane == a) {
-                    tot[q] = nt;
-                    T += delta;
+            for (int q = 0; q < PM; q++)
+                if (lane == r && q == js) tot[q] = nt;
+            if (lane == r) T += delta;
+            if (lane >= r) incl += delta;
+            R += delta;
+        }
+        uint64_t aff = __ballot(lane < 16 && spn == kSpV && nb != tx);
+        while (aff) {
+            const int l = __ffsll((unsigned long long)aff) - 1;
+            aff &= aff - 1;
+            const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)nb, l);
+#pragma unroll
+            for (int q = 0; q < PM; q++) {
+                const uint64_t m = __ballot(valid[q] && pos[q] == pa);
+                if (m) {
+                    const int a = __ffsll((unsigned long long)m) - 1;
+                    const double na = plain_slot_rates(C, ps, krate, kspec, a * P + q, pa, lane);
+                    const double delta = na - lane_value(tot[q], a);
+                    if (lane == a) {
+                        tot[q] = na;
+                        T += delta;
+                    }
+                    if (lane >= a) incl += delta;
+                    R += delta;
                 }
-                if (lane >= a) incl += delta;
-                R += delta;
             }
         }
     }
@@ -1609,7 +1698,40 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     unsigned char* c2s = (unsigned char*)(vlist + ((D.n_vac + 3) & ~3));
     if (threadIdx.x == 0) vlist_n = 0;
     const bool fast = D.fast != 0;
-    if (resident && fast) {
+    // plain lattice held in LDS: 2 bits per site in canonical order (16
+    // sites per word), then the vacancy list, the slots' rates and the
+    // species of their targets
+    const bool packed = fast && D.plain;
+    const int n_words = (int)((nbytes + 15) >> 4);
+    uint32_t* pslab = (uint32_t*)region;
+    const int plain_slots = D.n_vac <= 64 ? 64 : (D.n_vac <= 128 ? 128 : (D.n_vac <= 256 ? 256 : 512));
+    if (packed) {
+        vlist = (uint32_t*)(region + ((4 * n_words + 15) & ~15));
+        c2s = (unsigned char*)(vlist + ((D.n_vac + 3) & ~3));
+    }
+    __syncthreads();
+    if (packed) {
+        for (int w = threadIdx.x; w < n_words; w += blockDim.x) {
+            uint32_t word = 0;
+            for (int b = 0; b < 16; b++) {
+                const int64_t c = 16 * (int64_t)w + b;
+                if (c >= nbytes) break;
+                const int t = (int)(c % 3);
+                const int64_t cell = c / 3;
+                const int i = (int)(cell % D.L[0]);
+                const int j = (int)((cell / D.L[0]) % D.L[1]);
+                const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
+                const uint32_t sp = (uint32_t)occ_lat[plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)] & 3u;
+                word |= sp << (2 * b);
+                if (sp == (uint32_t)kSpV) {
+                    const int v = atomicAdd(&vlist_n, 1);
+                    if (v < D.n_vac)
+                        vlist[v] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20) | ((uint32_t)t << 30);
+                }
+            }
+            pslab[w] = word;
+        }
+    } else if (resident && fast) {
         // canonical order
         for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
             const int t = (int)(c % 3);
@@ -1617,8 +1739,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             const int i = (int)(cell % D.L[0]);
             const int j = (int)((cell / D.L[0]) % D.L[1]);
             const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-            region[c] = (unsigned char)occ_lat[D.plain ? plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)
-                                                       : store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)];
+            region[c] = (unsigned char)occ_lat[store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)];
         }
     } else if (resident) {
         const int nch = (int)((nbytes + 15) >> 4);
@@ -1629,7 +1750,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             c2s[j] = (unsigned char)m[j];
     }
     __syncthreads();
-    if (resident) {
+    if (resident && !packed) {
         for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
             const int t = (int)(c % 3);
             const int64_t cell = c / 3;
@@ -1671,10 +1792,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     RecCtl rc;
     rec_init(rec, rc);
     uint64_t ncyc = 0;
-    if (fast && D.plain) {
+    if (packed) {
         if (wv == 0) {
             const RateCtx C = {D.L[0], D.L[1], D.L[2], D.gb_period, D.gb_mask, W.k12};
-            solo_plain(D, region, vlist, nv_list, (double*)c2s, C, P.disp, St, Cl, lane, rec, rc);
+            double* krate = (double*)c2s;
+            unsigned char* kspec = (unsigned char*)(krate + 8 * plain_slots);
+            if (plain_slots == 64)
+                solo_plain<1>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane, rec, rc);
+            else if (plain_slots == 128)
+                solo_plain<2>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane, rec, rc);
+            else if (plain_slots == 256)
+                solo_plain<4>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane, rec, rc);
+            else
+                solo_plain<8>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane, rec, rc);
         }
     } else if (fast) {
         if (wv == 0) {
@@ -1719,15 +1849,23 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     rec_flush(rec, rc, P.disp);
     __syncthreads();
-    if (resident && fast) {
+    if (packed) {
         for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
             const int t = (int)(c % 3);
             const int64_t cell = c / 3;
             const int i = (int)(cell % D.L[0]);
             const int j = (int)((cell / D.L[0]) % D.L[1]);
             const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-            occ_lat[D.plain ? plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)
-                            : store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)] = (int8_t)region[c];
+            occ_lat[plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)] = (int8_t)pk_get(pslab, (int)c);
+        }
+    } else if (resident && fast) {
+        for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
+            const int t = (int)(c % 3);
+            const int64_t cell = c / 3;
+            const int i = (int)(cell % D.L[0]);
+            const int j = (int)((cell / D.L[0]) % D.L[1]);
+            const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
+            occ_lat[store_index_1f(D.L[0], D.L[1], D.L[2], i, j, k, t)] = (int8_t)region[c];
         }
     } else if (resident) {
         const int nch = (int)(nbytes >> 4);

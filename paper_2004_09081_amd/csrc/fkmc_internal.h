@@ -26,7 +26,7 @@ constexpr int kMaxWidth = 100;      // largest sub-block edge (cells)
 constexpr int kMaxLdsPerBlock = 65536;  // dynamic LDS of one phase workgroup
 constexpr int kMaxSlots = 128;      // vacancies per fragment-mode footprint
 constexpr int kMaxPlainSlots = 4096;  // vacancies per plain-mode lattice
-constexpr int kPlainLdsSlots = 256;   // vacancies per plain lattice held in LDS
+constexpr int kPlainLdsSlots = 512;   // vacancies per plain lattice held in LDS
 constexpr int kHopBuckets = 256;    // spread of the per-lattice hop counters
 constexpr int kStatFields = 10;     // count, r(3), rr(6)
 
@@ -42,7 +42,7 @@ struct LatDesc {
     int32_t group;        // persistent kernel: tiles one wave runs at once (1, 4 or 8)
     int32_t fp_stride;    // persistent kernel: LDS bytes of one staged footprint
     int32_t fast;         // persistent kernel: vacancy-centric path (one fragment with <= 32
-                          // vacancies, or plain with <= 256), lattice held in LDS
+                          // vacancies, or plain with <= 512), lattice held in LDS
     uint32_t seed;
     uint32_t lattice_id;
     int32_t gb_period;

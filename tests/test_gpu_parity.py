@@ -109,8 +109,14 @@ PLAIN_CASES = {
     "slots_129": Case((6, 6, 5), seed=17, nv=129, nh=20, T=650.0, Ea_O=0.6, Ea_H=0.5, E_z=1e8),
     "slots_256": Case((8, 7, 6), seed=18, lattice_id=4, nv=256, nh=100, T=600.0, Ea_O=0.6,
                       Ea_H=0.45, gb_period=3, gb_dE=0.05),
+    "slots_257": Case((8, 7, 6), seed=19, nv=257, nh=40, T=600.0, Ea_O=0.6, Ea_H=0.45),
+    "slots_512": Case((10, 9, 8), seed=20, lattice_id=6, nv=512, nh=200, T=620.0, Ea_O=0.6,
+                      Ea_H=0.45, E_z=5e7),
     # one vacancy more than the LDS path holds: the HBM kernel runs it
-    "hbm_257": Case((8, 7, 6), seed=19, nv=257, nh=40, T=600.0, Ea_O=0.6, Ea_H=0.45),
+    "hbm_513": Case((10, 9, 8), seed=21, nv=513, nh=50, T=620.0, Ea_O=0.6, Ea_H=0.45),
+    # 110,160 sites: held in LDS only at 2 bits per site
+    "packed_big": Case((36, 34, 30), seed=22, lattice_id=7, nv=100, nh=5000, T=600.0, Ea_O=0.6,
+                       Ea_H=0.4, E_z=2e7, gb_period=10, gb_dE=0.1),
     "edge2": Case((2, 3, 2), seed=14, nv=3, nh=4, T=650.0, Ea_O=0.6, Ea_H=0.5, E_z=1e8),
     "ragged_gb": Case((9, 7, 11), seed=15, lattice_id=9, nv=33, nh=90, T=550.0, Ea_O=0.55,
                       Ea_H=0.4, E_z=5e7, gb_period=4, gb_mask=7, gb_dE=0.08),
@@ -120,7 +126,7 @@ PLAIN_CASES = {
 @pytest.mark.parametrize("lds", [True, False], ids=["lds", "hbm"])
 @pytest.mark.parametrize("name", list(PLAIN_CASES))
 def test_plain_matches_oracle(name, lds):
-    """Plain BKL, in LDS on one wavefront (at most 256 vacancies) or in HBM
+    """Plain BKL, in LDS on one wavefront (at most 512 vacancies) or in HBM
     on a workgroup: draws, clock, hop counts and state equal the oracle's."""
     c = PLAIN_CASES[name]
     say("plain parity", name, "lds" if lds else "hbm")
@@ -143,7 +149,7 @@ def test_plain_matches_oracle(name, lds):
     st = g.read_stats()[0]
     assert lat.t == t0 + horizon
     assert st["t"] == lat.t and st["draws"] == lat.draws
-    assert st["lds_resident"] == (1 if lds and c.nv <= 256 else 0)
+    assert st["lds_resident"] == (1 if lds and c.nv <= 512 else 0)
     assert_same_state(g, 0, lat, name + " horizon")
 
 
