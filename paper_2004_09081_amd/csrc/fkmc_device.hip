@@ -157,12 +157,19 @@ __device__ __forceinline__ Brick brick_of(const LatDesc& D, const int32_t* bound
     return b;
 }
 
+// Index of local cell (lx,ly,lz), type t, in a brick of wx*wy*wz cells:
+//   type 0: (x wz + z) wy + y;  type 1: V + (y wz + z) wx + x;
+//   type 2: 2V + (z wy + y) wx + x   (V = wx wy wz).
+// Written with selects only (no branches): plane t has the type's own axis
+// slowest, then z (y for type 2), then y (type 0) or x.
 __device__ __forceinline__ int brick_local(int t, int lx, int ly, int lz, int wx, int wy, int wz)
 {
-    const int V = wx * wy * wz;
-    if (t == 0) return (lx * wz + lz) * wy + ly;
-    if (t == 1) return V + (ly * wz + lz) * wx + lx;
-    return 2 * V + (lz * wy + ly) * wx + lx;
+    const int a = t == 0 ? lx : (t == 1 ? ly : lz);
+    const int b = t == 2 ? ly : lz;
+    const int c = t == 0 ? ly : lx;
+    const int mid = t == 2 ? wy : wz;
+    const int fast = t == 0 ? wy : wx;
+    return t * (wx * wy * wz) + (a * mid + b) * fast + c;
 }
 
 // Storage offset (within the lattice) of canonical cell (i,j,k), type t.
@@ -271,13 +278,24 @@ __device__ __forceinline__ TileGeo tile_geo_rec(const TileRec& R)
     return G;
 }
 
+// Footprint segment and local index of local cell (lx,ly,lz), type t: the
+// brick (0), or the +face of the type's own axis (1 + t) when that
+// coordinate equals the sub-block width.  A face is ordered like one plane
+// of the brick without its slowest axis, so both indices share the
+// in-plane part.  Selects only, no branches.
 __device__ __forceinline__ int fp_local(const TileGeo& G, int lx, int ly, int lz, int t, int& li)
 {
-    if (t == 0 && lx == G.wx) { li = lz * G.wy + ly; return 1; }
-    if (t == 1 && ly == G.wy) { li = lz * G.wx + lx; return 2; }
-    if (t == 2 && lz == G.wz) { li = ly * G.wx + lx; return 3; }
-    li = brick_local(t, lx, ly, lz, G.wx, G.wy, G.wz);
-    return 0;
+    const int wx = G.wx, wy = G.wy, wz = G.wz;  // values: the selects below stay in registers
+    const int a = pick3(t, lx, ly, lz);
+    const int wa = pick3(t, wx, wy, wz);
+    const int b = t == 2 ? ly : lz;
+    const int c = t == 0 ? ly : lx;
+    const int mid = t == 2 ? wy : wz;
+    const int fast = t == 0 ? wy : wx;
+    const int inplane = b * fast + c;
+    const bool face = a == wa;
+    li = face ? inplane : t * (wx * wy * wz) + a * mid * fast + inplane;
+    return face ? t + 1 : 0;
 }
 
 
@@ -335,13 +353,15 @@ __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned cha
     int hx, hy, hz;
     hop_vec(t, d, hx, hy, hz);
     const int ox = (2 * X + hx) >> 2, oy = (2 * Y + hy) >> 2, oz = (2 * Z + hz) >> 2;
-    if (ox < 0 || ox >= G.wx || oy < 0 || oy >= G.wy || oz < 0 || oz >= G.wz) return 0.0;
+    const bool in = ox >= 0 && ox < G.wx && oy >= 0 && oy < G.wy && oz >= 0 && oz < G.wz;
     const int tX = X + hx, tY = Y + hy, tZ = Z + hz;
     const int tt = site_type(tX, tY);
     int li;
     const int seg = fp_local(G, tX >> 1, tY >> 1, tZ >> 1, tt, li);
-    const int sp = occl[seg_lds(G, seg) + li];
-    if (sp == kSpV) return 0.0;
+    // (an active edge's target is in the footprint; an inactive edge reads
+    // the first brick byte instead, so every address stays in bounds)
+    const int lds0 = G.lds0;
+    const int sp = occl[in ? seg_lds(G, seg) + li : lds0];
     int g = 0;
     if (C.gbp > 0) {
         int cs = pick3(t, G.ox + (X >> 1), G.oy + (Y >> 1), G.oz + (Z >> 1));
@@ -352,7 +372,9 @@ __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned cha
         if (ct >= Lt) ct -= Lt;
         g = gb_flag(C, t, cs) | gb_flag(C, tt, ct);
     }
-    return C.k12[(sp * 3 + hz + 1) * 2 + g];
+    const int col = (hz + 1) * 2 + g;
+    const double kO = C.k12[col], kH = C.k12[6 + col];
+    return (!in || sp == kSpV) ? 0.0 : (sp == kSpO ? kO : kH);
 }
 
 __device__ __forceinline__ bool nn_site(uint32_t a, uint32_t b)
