@@ -228,6 +228,7 @@ struct TileGeo {
     int ox, oy, oz;  // global cell of local cell (0,0,0)
     int64_t st0, st1, st2, st3;
     int lds0, lds1, lds2, lds3;
+    uint64_t ldsp;   // lds0..lds3 as 16-bit fields (LDS positions stay below 2^16)
 };
 
 // One of three or four values by a runtime index.  The operands are
@@ -253,7 +254,13 @@ __device__ __forceinline__ int64_t seg_st(const TileGeo& G, int k)
 }
 __device__ __forceinline__ int seg_lds(const TileGeo& G, int k)
 {
-    return pick4(k, G.lds0, G.lds1, G.lds2, G.lds3);
+    return (int)((G.ldsp >> (16 * k)) & 0xffffu);  // one shift, no select chain
+}
+
+__device__ __forceinline__ void pack_lds(TileGeo& G)
+{
+    G.ldsp = (uint64_t)(uint32_t)G.lds0 | ((uint64_t)(uint32_t)G.lds1 << 16) |
+             ((uint64_t)(uint32_t)G.lds2 << 32) | ((uint64_t)(uint32_t)G.lds3 << 48);
 }
 // Sites of footprint segment k: the brick, then the three faces.
 __device__ __forceinline__ int seg_len(const TileGeo& G, int k)
@@ -275,6 +282,7 @@ __device__ __forceinline__ TileGeo tile_geo_rec(const TileRec& R)
     G.st2 = R.st[2];
     G.st3 = R.st[3];
     G.lds0 = G.lds1 = G.lds2 = G.lds3 = 0;
+    G.ldsp = 0;
     return G;
 }
 
@@ -304,14 +312,13 @@ __device__ __forceinline__ uint32_t pack_xyz(int X, int Y, int Z)
     return (uint32_t)X | ((uint32_t)Y << 10) | ((uint32_t)Z << 20);
 }
 
-// LDS position / storage offset of the site at packed local doubled coords.
-__device__ __forceinline__ void xyz_where(const TileGeo& G, uint32_t xyz, int& lds, int64_t& st)
+// LDS position of the site at packed local doubled coords; its footprint
+// segment and local index in k, li.
+__device__ __forceinline__ int xyz_lds(const TileGeo& G, uint32_t xyz, int& k, int& li)
 {
     const int X = xyz & 1023, Y = (xyz >> 10) & 1023, Z = xyz >> 20;
-    int li;
-    const int k = fp_local(G, X >> 1, Y >> 1, Z >> 1, site_type(X, Y), li);
-    lds = seg_lds(G, k) + li;
-    st = seg_st(G, k) + li;
+    k = fp_local(G, X >> 1, Y >> 1, Z >> 1, site_type(X, Y), li);
+    return seg_lds(G, k) + li;
 }
 
 // ----------------------------------------------------------------------------
@@ -531,6 +538,7 @@ __device__ __forceinline__ void tile_lds_at(TileGeo& G, int base)
     G.lds2 = off + (int)(G.st2 & 15);
     off += ((int)(G.st2 & 15) + seg_len(G, 2) + 15) & ~15;
     G.lds3 = off + (int)(G.st3 & 15);
+    pack_lds(G);
 }
 
 // LDS positions when the whole lattice sits in LDS at its storage offsets.
@@ -540,6 +548,7 @@ __device__ __forceinline__ void tile_lds_resident(TileGeo& G)
     G.lds1 = (int)G.st1;
     G.lds2 = (int)G.st2;
     G.lds3 = (int)G.st3;
+    pack_lds(G);
 }
 
 // 16-byte chunk counts of the four staged segments.
@@ -931,13 +940,15 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         const uint32_t tx = hop_target_xyz(sx, d, hx, hy, hz);
         // (a segment without a hop has pick 0: local site (0,0,0), inside
         // its footprint, so these addresses are valid either way)
-        int spos, tpos;
-        int64_t sst, tst;
-        xyz_where(G, sx, spos, sst);
-        xyz_where(G, tx, tpos, tst);
+        int sk, sli, tk, tli;
+        const int spos = xyz_lds(G, sx, sk, sli);
+        const int tpos = xyz_lds(G, tx, tk, tli);
         const int sp = occl[tpos];
         wave_lds_fence();
+        int64_t sst = 0, tst = 0;  // storage offsets, in the lanes that apply a hop
         if (go && sl == 0) {
+            sst = seg_st(G, sk) + sli;
+            tst = seg_st(G, tk) + tli;
             occl[spos] = (unsigned char)sp;
             occl[tpos] = (unsigned char)kSpV;
             sxyz[pslot] = tx;
