@@ -1471,15 +1471,19 @@ __device__ __forceinline__ double plain_slot_rates(const RateCtx& C, const uint3
 // and the draw is spent) or no event is possible.  Draw d uses Philox
 // counter (d_lo, d_hi, 0xFFFFFFFF, 3); draws are computed 64 ahead, one per
 // lane.  vlist holds the nv vacancies (i | j << 10 | k << 20 | t << 30) and
-// is reordered here into slot order.  P = slots per lane (nv <= 64 P).
-// (Register arrays are indexed by unrolled constants only, so that they
-// stay in registers.)
+// is reordered here into slot order.
+//
+// Slot s sits in lane s mod 64, column q = s / 64 (P columns, nv <= 64 P),
+// so event order runs down column 0, then column 1, ...  Each column keeps
+// the inclusive prefix of its slot totals over the lanes, and its total
+// (wave-uniform); the selected slot is found from the column totals and
+// one ballot.  (Register arrays are indexed by unrolled constants only, so
+// that they stay in registers.)
 template <int P>
 __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint32_t* vlist, int nv,
                                            double* krate, unsigned char* kspec, const RateCtx& C, int4* disp,
                                            LatState* St, const LatCall* Cl, int lane, Rec& rec, RecCtl& rc)
 {
-    constexpr int PM = P;
     // descriptor fields in registers: the loop stores to global memory, so
     // fields read through D would be loaded again (and waited for) each step
     const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
@@ -1487,10 +1491,10 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
     const uint32_t seed = D.seed, lid = D.lattice_id;
     // slot = canonical rank at call start: vacancy lane + 64 q is ranked,
     // then written to vlist[rank] as packed doubled coordinates
-    uint32_t pv[PM];
-    int key[PM], rank[PM];
+    uint32_t pv[P];
+    int key[P], rank[P];
 #pragma unroll
-    for (int q = 0; q < PM; q++) {
+    for (int q = 0; q < P; q++) {
         const int v = lane + 64 * q;
         pv[q] = 0;
         key[q] = 0x7fffffff;
@@ -1503,25 +1507,25 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
         }
     }
 #pragma unroll
-    for (int qq = 0; qq < PM; qq++) {
+    for (int qq = 0; qq < P; qq++) {
         const int n_q = nv - 64 * qq < 64 ? nv - 64 * qq : 64;
         for (int l = 0; l < n_q; l++) {
             const int kv = __builtin_amdgcn_readlane(key[qq], l);
 #pragma unroll
-            for (int q = 0; q < PM; q++) rank[q] += kv < key[q] ? 1 : 0;
+            for (int q = 0; q < P; q++) rank[q] += kv < key[q] ? 1 : 0;
         }
     }
     wave_lds_fence();
 #pragma unroll
-    for (int q = 0; q < PM; q++)
+    for (int q = 0; q < P; q++)
         if (lane + 64 * q < nv) vlist[rank[q]] = pv[q];
     wave_lds_fence();
-    uint32_t pos[PM];
-    double tot[PM];
-    bool valid[PM];
+    uint32_t pos[P];
+    double tot[P], incl[P], colT[P];
+    bool valid[P];
 #pragma unroll
-    for (int q = 0; q < PM; q++) {
-        const int sidx = lane * P + q;
+    for (int q = 0; q < P; q++) {
+        const int sidx = 64 * q + lane;
         valid[q] = sidx < nv;
         pos[q] = valid[q] ? vlist[sidx] : 0u;
         tot[q] = 0.0;
@@ -1537,12 +1541,12 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
                 tot[q] += k;
             }
         }
+        incl[q] = wave_scan_dpp(tot[q]);
+        colT[q] = lane_value(incl[q], 63);
     }
-    double T = 0.0;
+    double R = 0.0;
 #pragma unroll
-    for (int q = 0; q < PM; q++) T += tot[q];
-    double incl = wave_scan_dpp(T);
-    double R = lane_value(incl, 63);
+    for (int q = 0; q < P; q++) R += colT[q];
     double t = St->t;
     uint64_t draws = St->draws;
     const double horizon = Cl->t_sync;
@@ -1572,38 +1576,46 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             break;
         }
         t = tn;
-        // lane: the first whose inclusive prefix exceeds y; then its slot,
-        // then the direction
+        // the slot whose inclusive prefix first exceeds y: its column from
+        // the column totals, its lane from one ballot; then the direction
         const double y = u_sel * R;
-        const uint64_t mk = __ballot(lane * P < nv && incl > y);
-        int r, js = -1;
+        int js = -1, r = 0;
         bool fb = false;
-        double c0 = 0.0;
-        if (mk) {
-            r = __ffsll((unsigned long long)mk) - 1;
-            double c = lane_value(incl, r) - lane_value(T, r);
-            if (P == 1) {
-                js = 0;
-            } else {
+        double c0 = 0.0, tot_old = 0.0;
+        uint32_t sx = 0;
+        {
+            double base = 0.0;
 #pragma unroll
-                for (int q = 0; q < PM; q++) {
-                    if (js < 0) {
-                        const double tq = lane_value(tot[q], r);
-                        if (c + tq > y) js = q;
-                        else c += tq;
+            for (int q = 0; q < P; q++) {
+                if (js < 0) {
+                    if (base + colT[q] > y) {
+                        js = q;
+                        const uint64_t mk = __ballot(valid[q] && base + incl[q] > y);
+                        r = __ffsll((unsigned long long)mk) - 1;
+                        c0 = base + lane_value(incl[q], r) - lane_value(tot[q], r);
+                        tot_old = lane_value(tot[q], r);
+                        sx = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], r);
+                    } else {
+                        base += colT[q];
                     }
                 }
             }
-            c0 = c;
-        } else {
-            r = 63 - __clzll((long long)__ballot(T > 0.0));  // y rounded up to R
-#pragma unroll
-            for (int q = 0; q < PM; q++)
-                if (lane_value(tot[q], r) > 0.0) js = q;
-            fb = true;
         }
-        js = js < 0 ? 0 : js;
-        const int slot = r * P + js;
+        if (js < 0) {
+            // y rounded up to R: the last slot with a positive total
+            fb = true;
+#pragma unroll
+            for (int q = 0; q < P; q++) {
+                const uint64_t nz = __ballot(tot[q] > 0.0);
+                if (nz) {
+                    js = q;
+                    r = 63 - __clzll((long long)nz);
+                    tot_old = lane_value(tot[q], r);
+                    sx = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], r);
+                }
+            }
+        }
+        const int slot = 64 * js + r;
         const double kv = lane < 8 ? krate[slot * 8 + lane] : 0.0;
         const int kspv = lane < 8 ? (int)kspec[slot * 8 + lane] : 0;
         const double cs = seg_scan<8>(kv, lane & 7) + c0;
@@ -1611,15 +1623,6 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
         const int d = md ? __ffsll((unsigned long long)md) - 1
                          : 63 - __clzll((long long)__ballot(lane < 8 && kv > 0.0));
         const int sp = __builtin_amdgcn_readlane(kspv, d);
-        uint32_t sx = 0;
-        double tot_old = 0.0;
-#pragma unroll
-        for (int q = 0; q < PM; q++) {
-            if (q == js) {
-                sx = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], r);
-                tot_old = lane_value(tot[q], r);
-            }
-        }
         uint32_t tx;
         int colx;
         const int ct_i = plain_nb(C, sx, d, tx, colx);
@@ -1631,7 +1634,7 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             pk_set(ps, ct_i, kSpV);
         }
 #pragma unroll
-        for (int q = 0; q < PM; q++)
+        for (int q = 0; q < P; q++)
             if (lane == r && q == js) pos[q] = tx;
         if (sp == kSpO) ho++;
         else hh++;
@@ -1663,10 +1666,13 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             const double nt = lane_value(seg_scan<8>(kn, lane & 7), 7);
             const double delta = nt - tot_old;
 #pragma unroll
-            for (int q = 0; q < PM; q++)
-                if (lane == r && q == js) tot[q] = nt;
-            if (lane == r) T += delta;
-            if (lane >= r) incl += delta;
+            for (int q = 0; q < P; q++) {
+                if (q == js) {
+                    if (lane == r) tot[q] = nt;
+                    if (lane >= r) incl[q] += delta;
+                    colT[q] += delta;
+                }
+            }
             R += delta;
         }
         uint64_t aff = __ballot(lane < 16 && spn == kSpV && nb != tx);
@@ -1675,17 +1681,15 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             aff &= aff - 1;
             const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)nb, l);
 #pragma unroll
-            for (int q = 0; q < PM; q++) {
+            for (int q = 0; q < P; q++) {
                 const uint64_t m = __ballot(valid[q] && pos[q] == pa);
                 if (m) {
                     const int a = __ffsll((unsigned long long)m) - 1;
-                    const double na = plain_slot_rates(C, ps, krate, kspec, a * P + q, pa, lane);
+                    const double na = plain_slot_rates(C, ps, krate, kspec, 64 * q + a, pa, lane);
                     const double delta = na - lane_value(tot[q], a);
-                    if (lane == a) {
-                        tot[q] = na;
-                        T += delta;
-                    }
-                    if (lane >= a) incl += delta;
+                    if (lane == a) tot[q] = na;
+                    if (lane >= a) incl[q] += delta;
+                    colT[q] += delta;
                     R += delta;
                 }
             }
