@@ -1404,22 +1404,23 @@ __device__ __forceinline__ int pk_get(const uint32_t* ps, int c)
     return (int)((ps[c >> 4] >> ((c & 15) << 1)) & 3u);
 }
 
-// Single writer (one lane) per call.
+// Set the 2-bit species of site c: two LDS atomics without return (clear,
+// then set), so nothing waits for a read of the word.
 __device__ __forceinline__ void pk_set(uint32_t* ps, int c, int v)
 {
     const int sh = (c & 15) << 1;
-    const uint32_t w = ps[c >> 4];
-    ps[c >> 4] = (w & ~(3u << sh)) | ((uint32_t)v << sh);
+    atomicAnd(&ps[c >> 4], ~(3u << sh));
+    atomicOr(&ps[c >> 4], (uint32_t)v << sh);
 }
 
 // Neighbour d of the site at packed doubled coordinates p: its canonical
 // index and packed coordinates, and the column of the rate table (z step,
 // boundary flag): the rate for ion species X is k12[X*6 + col].
-__device__ __forceinline__ int plain_nb(const RateCtx& C, uint32_t p, int d, uint32_t& np, int& col)
+__device__ __forceinline__ int plain_nb(const RateCtx& C, uint32_t p, int d, uint32_t& np, int& col,
+                                        int& hx, int& hy, int& hz)
 {
     const int X = p & 2047, Y = (p >> 11) & 2047, Z = p >> 22;
     const int t = site_type(X, Y);
-    int hx, hy, hz;
     hop_vec(t, d, hx, hy, hz);
     int TX = X + hx, TY = Y + hy, TZ = Z + hz;
     if (TX < 0) TX += 2 * C.L0;
@@ -1437,6 +1438,20 @@ __device__ __forceinline__ int plain_nb(const RateCtx& C, uint32_t p, int d, uin
     }
     col = (hz + 1) * 2 + g;
     return canon_dbl(C.L0, C.L1, TX, TY, TZ);
+}
+
+__device__ __forceinline__ int plain_nb(const RateCtx& C, uint32_t p, int d, uint32_t& np, int& col)
+{
+    int hx, hy, hz;
+    return plain_nb(C, p, d, np, col, hx, hy, hz);
+}
+
+// Storage offset in plain mode for a lattice held in LDS (fewer than 2^31
+// sites, so 32-bit arithmetic).
+__device__ __forceinline__ int plain_offset32(int L0, int L1, int L2, int i, int j, int k, int t)
+{
+    const int V = L0 * L1 * L2;
+    return t == 0 ? (i * L2 + k) * L1 + j : (t == 1 ? V + (j * L2 + k) * L0 + i : 2 * V + (k * L1 + j) * L0 + i);
 }
 
 // Rate of a hop onto a target holding species sp (0 for a vacancy); the
@@ -1624,8 +1639,8 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
                          : 63 - __clzll((long long)__ballot(lane < 8 && kv > 0.0));
         const int sp = __builtin_amdgcn_readlane(kspv, d);
         uint32_t tx;
-        int colx;
-        const int ct_i = plain_nb(C, sx, d, tx, colx);
+        int colx, hx, hy, hz;
+        const int ct_i = plain_nb(C, sx, d, tx, colx, hx, hy, hz);
         const int SX = sx & 2047, SY = (sx >> 11) & 2047, SZ = sx >> 22;
         const int TX = tx & 2047, TY = (tx >> 11) & 2047, TZ = tx >> 22;
         const int cs_i = canon_dbl(L0, L1, SX, SY, SZ);
@@ -1638,11 +1653,9 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             if (lane == r && q == js) pos[q] = tx;
         if (sp == kSpO) ho++;
         else hh++;
-        int hx, hy, hz;
-        hop_vec(site_type(SX, SY), d, hx, hy, hz);
         rec_hop(rec, rc, disp, lane,
-                disp_off + plain_offset(L0, L1, L2, SX >> 1, SY >> 1, SZ >> 1, site_type(SX, SY)),
-                disp_off + plain_offset(L0, L1, L2, TX >> 1, TY >> 1, TZ >> 1, site_type(TX, TY)), hx, hy, hz);
+                disp_off + plain_offset32(L0, L1, L2, SX >> 1, SY >> 1, SZ >> 1, site_type(SX, SY)),
+                disp_off + plain_offset32(L0, L1, L2, TX >> 1, TY >> 1, TZ >> 1, site_type(TX, TY)), hx, hy, hz);
         done++;
         // one pass over the neighbours of both sites: lanes 0-7 around the
         // moved vacancy's new site (its new rates), lanes 8-15 around its old
