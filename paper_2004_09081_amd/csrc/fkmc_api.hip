@@ -899,6 +899,21 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         if (plain_lds_fits(L, (uint32_t)i)) ids.push_back(i);
         else slow.push_back(i);
     }
+    // Order of the persistent launch (results do not depend on it): after a
+    // call in which every lattice ran it, the heaviest half by that call's
+    // device time goes first, heaviest first, then the rest lightest first,
+    // so that workgroups dispatched half a launch apart (which share a
+    // compute unit when every workgroup is resident) pair heavy with light.
+    {
+        bool timed = ids.size() >= 2;
+        for (int32_t i : ids) timed = timed && L->h_state[i].busy_ticks > 0;
+        if (timed) {
+            std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
+                return L->h_state[a].busy_ticks > L->h_state[b].busy_ticks;
+            });
+            std::reverse(ids.begin() + (ids.size() + 1) / 2, ids.end());
+        }
+    }
     // (both lists are read by the copies before prepare_call synchronises)
     if (slow != L->slow_plain_ids) {
         L->slow_plain_ids = slow;
