@@ -889,12 +889,25 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         active = go;
         if (go) tau = tn;
         const double y = u_sel * R;
-        const uint64_t mk = __ballot(go && incl > y) & segmask;
-        const uint64_t nz = __ballot(go && lsv > 0.0) & segmask;
-        const bool fb = mk == 0;
-        int sel = lane;
-        if (mk) sel = __ffsll((unsigned long long)mk) - 1;
-        else if (nz) sel = 63 - __clzll((long long)nz);
+        const uint64_t mk_all = __ballot(go && incl > y);
+        const uint64_t nz_all = __ballot(go && lsv > 0.0);
+        bool fb;
+        int sel;
+        if (S < 64) {
+            // this segment's bits as a 32-bit mask: selects, no branches
+            const uint32_t sm = S >= 32 ? 0xffffffffu : ((1u << (S & 31)) - 1u);
+            const uint32_t m = (uint32_t)(mk_all >> sb) & sm;
+            const uint32_t z = (uint32_t)(nz_all >> sb) & sm;
+            fb = m == 0u;
+            sel = m ? sb + (int)__builtin_ctz(m) : (z ? sb + 31 - (int)__builtin_clz(z) : lane);
+        } else {
+            const uint64_t mk = mk_all & segmask;
+            const uint64_t nz = nz_all & segmask;
+            fb = mk == 0;
+            sel = lane;
+            if (mk) sel = __ffsll((unsigned long long)mk) - 1;
+            else if (nz) sel = 63 - __clzll((long long)nz);
+        }
         // the selected lane of each segment picks the event
         int pick = 0, pslot = 0;
         if (go && lane == sel) {
