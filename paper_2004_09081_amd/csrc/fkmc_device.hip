@@ -1460,11 +1460,11 @@ __device__ __forceinline__ int plain_nb(const RateCtx& C, uint32_t p, int d, uin
 }
 
 // Storage offset in plain mode for a lattice held in LDS (fewer than 2^31
-// sites, so 32-bit arithmetic).
+// sites, so 32-bit arithmetic): the whole lattice is one brick, so this is
+// the brick index with the lattice as the brick (selects, no branches).
 __device__ __forceinline__ int plain_offset32(int L0, int L1, int L2, int i, int j, int k, int t)
 {
-    const int V = L0 * L1 * L2;
-    return t == 0 ? (i * L2 + k) * L1 + j : (t == 1 ? V + (j * L2 + k) * L0 + i : 2 * V + (k * L1 + j) * L0 + i);
+    return brick_local(t, i, j, k, L0, L1, L2);
 }
 
 // Rate of a hop onto a target holding species sp (0 for a vacancy); the
