@@ -833,14 +833,17 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
 #pragma unroll
     for (int d = 0; d < E; d++) kk[d] = 0.0;
     double ls = 0.0;
+    // (unrolled: each rate goes straight to its register; events past
+    // this lane's epl are skipped, and a block no lane needs is branched
+    // over)
     auto refresh = [&]() {
         ls = 0.0;
-#pragma nounroll
-        for (int j = 0; j < epl; j++) {
-            const double r = tile_rate(G, occl, C, my_xyz, my_d0 + j);
-            ls += r;
 #pragma unroll
-            for (int q = 0; q < E; q++) kk[q] = q == j ? r : kk[q];
+        for (int j = 0; j < E; j++) {
+            if (j < epl) {
+                kk[j] = tile_rate(G, occl, C, my_xyz, my_d0 + j);
+                ls += kk[j];
+            }
         }
     };
     if (ev_valid) refresh();
