@@ -128,7 +128,9 @@ typedef struct {
                               workgroup took in the last fkmc_advance (ms) */
     uint32_t lds_resident; /* 1 if the last fkmc_advance ran the persistent
                               schedule with this lattice held in LDS */
-    uint32_t reserved;
+    uint32_t tile_group;   /* tiles a wavefront ran at once in the last
+                              fkmc_advance on the persistent schedule (8, 4
+                              or 1; 0 for other runs and plain lattices) */
 } fkmc_stats;
 
 /* Required byte sizes of the occ, disp and work buffers for n lattices. */
@@ -219,8 +221,10 @@ fkmc_status fkmc_set_schedule(fkmc_lattice* lat, int32_t schedule, int32_t waves
  * runs afterwards on the whole wavefront.  group = 0 (default) chooses per
  * lattice from the mean vacancy count of a footprint; otherwise the
  * lockstep schedule uses group (1, 2, 4 or 8) and the persistent schedule
- * uses 8 when group is 8 and 1 (whole wavefront per tile) for any other
- * value.  Results are identical for every group size. */
+ * uses 8 or 4 when group is 8 or 4 and 1 (whole wavefront per tile) for any
+ * other value, or when the staged footprints of that many tiles per
+ * wavefront do not fit its LDS.  Results are identical for every group
+ * size. */
 fkmc_status fkmc_set_group(fkmc_lattice* lat, int32_t group);
 
 /* Plain lattices (Eqs. TransitionProb, eventSelection, TimeStep over the

@@ -694,7 +694,7 @@ fkmc_status fkmc_get_rate_table(const fkmc_lattice* L, uint32_t i, double* k12, 
 // vacancies on average: the largest group (each tile then has 64/group
 // lanes and slots) for which at most 2 % of the tiles overflow their slots
 // (Poisson tail), within `lds` bytes of staged footprints per wave; groups
-// of 8 or 1 only unless `all`.
+// of 8, 4 or 1 only unless `all` (the lockstep kernel also runs 2).
 static int pick_group(double lam, int fp_stride, int lds, bool all)
 {
     auto fits = [&](int slots) {
@@ -706,7 +706,7 @@ static int pick_group(double lam, int fp_stride, int lds, bool all)
         return 1.0 - c <= 0.02;
     };
     for (int g = 8; g > 1; g /= 2) {
-        if (g != 8 && !all) continue;
+        if (g == 2 && !all) continue;
         if (fits(64 / g) && (int64_t)g * fp_stride <= lds) return g;
     }
     return 1;
@@ -844,7 +844,7 @@ static fkmc_status plan_batch(fkmc_lattice* L, const std::vector<int32_t>& ids)
         const int fps = footprint_stride((int)max_footprint(g));
         D.fp_stride = fps;
         if (L->group_override) {
-            D.group = L->group_override == 8 ? 8 : 1;
+            D.group = L->group_override == 8 || L->group_override == 4 ? L->group_override : 1;
             if (!small && (int64_t)waves * D.group * fps > std::min(bound, 65536)) D.group = 1;
             region = std::max<int>(region, small ? (int)slab : waves * D.group * fps);
             if (!small && (int64_t)waves * fps > std::min(bound, 65536))
@@ -1235,6 +1235,7 @@ fkmc_status fkmc_read_stats(fkmc_lattice* L, fkmc_stats* out)
             o.cycles = S.cycles;
             o.busy_ms = (double)S.busy_ticks / 100000.0;  // 100 MHz real-time counter
             o.lds_resident = L->last_persistent && L->desc[i].resident ? 1u : 0u;
+            o.tile_group = L->last_persistent ? (uint32_t)L->desc[i].group : 0u;
             for (int b = 0; b < kHopBuckets; b++) {
                 o.hops[0] += bk[((size_t)i * kHopBuckets + b) * 2];
                 o.hops[1] += bk[((size_t)i * kHopBuckets + b) * 2 + 1];

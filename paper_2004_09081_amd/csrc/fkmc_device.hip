@@ -122,6 +122,17 @@ __device__ __forceinline__ void wave_lds_fence()
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Order this wave's LDS accesses across lanes without waiting for them: the
+// LDS serves one wave's instructions in issue order, so a later read by any
+// lane sees an earlier write by any other; the wavefront-scope fences only
+// keep the compiler from moving accesses across this point.
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double wave_incl_scan(double v, int lane)
 {
 #pragma unroll
@@ -960,7 +971,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         const int spos = xyz_lds(G, sx, sk, sli);
         const int tpos = xyz_lds(G, tx, tk, tli);
         const int sp = occl[tpos];
-        wave_lds_fence();
+        wave_lds_order();
         int64_t sst = 0, tst = 0;  // storage offsets, in the lanes that apply a hop
         if (go && sl == 0) {
             sst = seg_st(G, sk) + sli;
@@ -990,7 +1001,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             }
         }
         step += go ? 1u : 0u;
-        wave_lds_fence();
+        wave_lds_order();
         if (ev_valid && go) {
             if (my_slot == pslot) my_xyz = tx;
             if (my_slot == pslot || nn_site(my_xyz, sx) || nn_site(my_xyz, tx)) refresh();
@@ -1366,7 +1377,7 @@ __device__ __forceinline__ void solo_fast(const LatDesc& D, unsigned char* slab,
                 const uint32_t tx = pack_dbl(TX, TY, TZ);
                 const int cs = canon_dbl(L0, L1, SX, SY, SZ), ct = canon_dbl(L0, L1, TX, TY, TZ);
                 const int sp = slab[ct];
-                wave_lds_fence();
+                wave_lds_order();
                 if (lane == 0) {
                     slab[cs] = (unsigned char)sp;
                     slab[ct] = (unsigned char)kSpV;
@@ -1378,7 +1389,7 @@ __device__ __forceinline__ void solo_fast(const LatDesc& D, unsigned char* slab,
                 rec_hop(rec, rc, X.disp, lane, X.disp_off + store_dbl_1f(L0, L1, L2, SX, SY, SZ),
                         X.disp_off + store_dbl_1f(L0, L1, L2, TX, TY, TZ), hx, hy, hz);
                 step++;
-                wave_lds_fence();
+                wave_lds_order();
                 if (valid && (mover || nn_dbl(L0, L1, L2, pos, sx) || nn_dbl(L0, L1, L2, pos, tx)))
                     rates();
             }
@@ -1470,6 +1481,82 @@ __device__ __forceinline__ int plain_offset32(int L0, int L1, int L2, int i, int
     return brick_local(t, i, j, k, L0, L1, L2);
 }
 
+// Storage offset (within the lattice) of canonical site c in plain mode.
+__device__ __forceinline__ int plain_site_offset(uint32_t c, uint32_t L0, uint32_t L1, uint32_t L2)
+{
+    const uint32_t cell = c / 3u, t = c - 3u * cell;
+    const uint32_t row = cell / L0, i = cell - row * L0;
+    const uint32_t k = row / L1, j = row - k * L1;
+    return plain_offset32((int)L0, (int)L1, (int)L2, (int)i, (int)j, (int)k, (int)t);
+}
+
+// Displacement records of the plain path in LDS, as the tile path keeps
+// them (one record per lane, for the particle now at site cur that started
+// the open run at site orig, with its displacement since), keyed by
+// canonical site index: the storage offsets are worked out only when the
+// records are written back, by every lane at once.
+struct PlainRec {
+    int cur;  // < 0: free
+    int orig;
+    int ax, ay, az;
+    int n;         // records in use (wave-uniform)
+    bool pending;  // stores of the last flush may still be in flight
+};
+
+__device__ __forceinline__ void prec_flush(PlainRec& r, int4* disp, int64_t disp_off, int L0, int L1, int L2)
+{
+    if (r.n == 0) return;
+    if (r.pending) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the last flush's stores have landed
+        __builtin_amdgcn_wave_barrier();
+    }
+    int4 o = make_int4(0, 0, 0, 0);
+    int64_t dst = 0;
+    if (r.cur >= 0) {
+        o = disp[disp_off + plain_site_offset((uint32_t)r.orig, L0, L1, L2)];
+        dst = disp_off + plain_site_offset((uint32_t)r.cur, L0, L1, L2);
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // every read has returned before any write
+    __builtin_amdgcn_wave_barrier();
+    if (r.cur >= 0) disp[dst] = make_int4(o.x + r.ax, o.y + r.ay, o.z + r.az, 0);
+    r.cur = -1;
+    r.ax = r.ay = r.az = 0;
+    r.n = 0;
+    r.pending = true;
+}
+
+// The vacancy at canonical site cs swaps with the ion at ct, the vacancy
+// moving by h (all wave-uniform).
+__device__ __forceinline__ void prec_hop(PlainRec& r, int4* disp, int64_t disp_off, int L0, int L1, int L2,
+                                         int lane, int cs, int ct, int hx, int hy, int hz)
+{
+    uint64_t mv = __ballot(r.cur == cs);
+    uint64_t mi = __ballot(r.cur == ct);
+    if (r.n + (mv == 0) + (mi == 0) > 64) {
+        prec_flush(r, disp, disp_off, L0, L1, L2);
+        mv = 0;
+        mi = 0;
+    }
+    int lv, li;
+    if (mv) {
+        lv = __ffsll((unsigned long long)mv) - 1;
+    } else {
+        lv = r.n++;
+        if (lane == lv) r.orig = cs;
+    }
+    if (mi) {
+        li = __ffsll((unsigned long long)mi) - 1;
+    } else {
+        li = r.n++;
+        if (lane == li) r.orig = ct;
+    }
+    const int sv = lane == lv ? 1 : (lane == li ? -1 : 0);
+    r.cur = lane == lv ? ct : (lane == li ? cs : r.cur);
+    r.ax += sv * hx;
+    r.ay += sv * hy;
+    r.az += sv * hz;
+}
+
 // Rate of a hop onto a target holding species sp (0 for a vacancy); the
 // table entries of both ions are read together with the target.
 __device__ __forceinline__ double plain_rate_of(const RateCtx& C, const uint32_t* ps, int cn, int col, int& sp)
@@ -1502,19 +1589,19 @@ __device__ __forceinline__ double plain_slot_rates(const RateCtx& C, const uint3
 // and the draw is spent) or no event is possible.  Draw d uses Philox
 // counter (d_lo, d_hi, 0xFFFFFFFF, 3); draws are computed 64 ahead, one per
 // lane.  vlist holds the nv vacancies (i | j << 10 | k << 20 | t << 30) and
-// is reordered here into slot order.
+// is rewritten here as the packed doubled coordinates of each slot.
 //
-// Slot s sits in lane s mod 64, column q = s / 64 (P columns, nv <= 64 P),
-// so event order runs down column 0, then column 1, ...  Each column keeps
-// the inclusive prefix of its slot totals over the lanes, and its total
-// (wave-uniform); the selected slot is found from the column totals and
-// one ballot.  (Register arrays are indexed by unrolled constants only, so
-// that they stay in registers.)
+// The 8P events of lane l's slots are entries l*8P .. l*8P+8P-1 of the rate
+// table, in event order.  Each lane keeps the total of its block and the
+// inclusive prefix of the block totals over the lanes, so a selection is
+// one ballot over the prefixes (the block), one read of the block's rates
+// into lanes 0 .. 8P-1, their prefix sum and a second ballot (the event).
 template <int P>
 __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint32_t* vlist, int nv,
                                            double* krate, unsigned char* kspec, const RateCtx& C, int4* disp,
-                                           LatState* St, const LatCall* Cl, int lane, Rec& rec, RecCtl& rc)
+                                           LatState* St, const LatCall* Cl, int lane)
 {
+    constexpr int NE = 8 * P;  // events per block
     // descriptor fields in registers: the loop stores to global memory, so
     // fields read through D would be loaded again (and waited for) each step
     const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
@@ -1551,33 +1638,36 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
     for (int q = 0; q < P; q++)
         if (lane + 64 * q < nv) vlist[rank[q]] = pv[q];
     wave_lds_fence();
-    uint32_t pos[P];
-    double tot[P], incl[P], colT[P];
-    bool valid[P];
-#pragma unroll
-    for (int q = 0; q < P; q++) {
-        const int sidx = 64 * q + lane;
-        valid[q] = sidx < nv;
-        pos[q] = valid[q] ? vlist[sidx] : 0u;
-        tot[q] = 0.0;
-        if (valid[q]) {
+    // the rates of every slot (zero past the last vacancy: a block read
+    // covers whole blocks) and the block totals
+    double bsum = 0.0;
 #pragma nounroll
-            for (int d = 0; d < 8; d++) {
+    for (int q = 0; q < P; q++) {
+        const int sidx = lane * P + q;
+        const bool v = sidx < nv;
+        const uint32_t p = v ? vlist[sidx] : 0u;
+#pragma nounroll
+        for (int d = 0; d < 8; d++) {
+            double k = 0.0;
+            int sp = kSpV;
+            if (v) {
                 uint32_t np;
-                int col, sp;
-                const int cn = plain_nb(C, pos[q], d, np, col);
-                const double k = plain_rate_of(C, ps, cn, col, sp);
-                krate[sidx * 8 + d] = k;
-                kspec[sidx * 8 + d] = (unsigned char)sp;
-                tot[q] += k;
+                int col;
+                k = plain_rate_of(C, ps, plain_nb(C, p, d, np, col), col, sp);
             }
+            krate[sidx * 8 + d] = k;
+            kspec[sidx * 8 + d] = (unsigned char)sp;
+            bsum += k;
         }
-        incl[q] = wave_scan_dpp(tot[q]);
-        colT[q] = lane_value(incl[q], 63);
     }
-    double R = 0.0;
-#pragma unroll
-    for (int q = 0; q < P; q++) R += colT[q];
+    double bincl = wave_scan_dpp(bsum);
+    double R = lane_value(bincl, 63);
+    PlainRec pr;
+    pr.cur = -1;
+    pr.orig = 0;
+    pr.ax = pr.ay = pr.az = 0;
+    pr.n = 0;
+    pr.pending = false;
     double t = St->t;
     uint64_t draws = St->draws;
     const double horizon = Cl->t_sync;
@@ -1607,71 +1697,41 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             break;
         }
         t = tn;
-        // the slot whose inclusive prefix first exceeds y: its column from
-        // the column totals, its lane from one ballot; then the direction
+        // the event whose inclusive prefix first exceeds y: its block from
+        // one ballot, then the event inside the block from a second; when y
+        // rounded up to R, the last event with a positive rate
         const double y = u_sel * R;
-        int js = -1, r = 0;
-        bool fb = false;
-        double c0 = 0.0, tot_old = 0.0;
-        uint32_t sx = 0;
-        {
-            double base = 0.0;
-#pragma unroll
-            for (int q = 0; q < P; q++) {
-                if (js < 0) {
-                    if (base + colT[q] > y) {
-                        js = q;
-                        const uint64_t mk = __ballot(valid[q] && base + incl[q] > y);
-                        r = __ffsll((unsigned long long)mk) - 1;
-                        c0 = base + lane_value(incl[q], r) - lane_value(tot[q], r);
-                        tot_old = lane_value(tot[q], r);
-                        sx = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], r);
-                    } else {
-                        base += colT[q];
-                    }
-                }
-            }
-        }
-        if (js < 0) {
-            // y rounded up to R: the last slot with a positive total
-            fb = true;
-#pragma unroll
-            for (int q = 0; q < P; q++) {
-                const uint64_t nz = __ballot(tot[q] > 0.0);
-                if (nz) {
-                    js = q;
-                    r = 63 - __clzll((long long)nz);
-                    tot_old = lane_value(tot[q], r);
-                    sx = (uint32_t)__builtin_amdgcn_readlane((int)pos[q], r);
-                }
-            }
-        }
-        const int slot = 64 * js + r;
-        const double kv = lane < 8 ? krate[slot * 8 + lane] : 0.0;
-        const int kspv = lane < 8 ? (int)kspec[slot * 8 + lane] : 0;
-        const double cs = seg_scan<8>(kv, lane & 7) + c0;
-        const uint64_t md = fb ? 0ull : __ballot(lane < 8 && cs > y);
-        const int d = md ? __ffsll((unsigned long long)md) - 1
-                         : 63 - __clzll((long long)__ballot(lane < 8 && kv > 0.0));
-        const int sp = __builtin_amdgcn_readlane(kspv, d);
+        const uint64_t mb = __ballot(bincl > y);
+        const bool fb = mb == 0;
+        const int r = fb ? 63 - __clzll((long long)__ballot(bsum > 0.0)) : __ffsll((unsigned long long)mb) - 1;
+        const double c0 = lane_value(bincl, r) - lane_value(bsum, r);
+        const int eb = r * NE;
+        const double kv = lane < NE ? krate[eb + lane] : 0.0;
+        const int kspv = lane < NE ? (int)kspec[eb + lane] : 0;
+        const uint32_t pvv = lane < P && r * P + lane < nv ? vlist[r * P + lane] : 0u;
+        const double cs = seg_scan<NE>(kv, lane & (NE - 1)) + c0;
+        const uint64_t me = fb ? 0ull : __ballot(lane < NE && cs > y);
+        const int e = me ? __ffsll((unsigned long long)me) - 1
+                         : 63 - __clzll((long long)__ballot(lane < NE && kv > 0.0));
+        const int j = e >> 3, d = e & 7;
+        const int slot = r * P + j;
+        const int sp = __builtin_amdgcn_readlane(kspv, e);
+        // the slot's old total: its 8 events in the block's prefix sum
+        const double tot_old = lane_value(cs, (j << 3) | 7) - (j ? lane_value(cs, (j << 3) - 1) : c0);
+        const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)pvv, j);
         uint32_t tx;
         int colx, hx, hy, hz;
         const int ct_i = plain_nb(C, sx, d, tx, colx, hx, hy, hz);
         const int SX = sx & 2047, SY = (sx >> 11) & 2047, SZ = sx >> 22;
-        const int TX = tx & 2047, TY = (tx >> 11) & 2047, TZ = tx >> 22;
         const int cs_i = canon_dbl(L0, L1, SX, SY, SZ);
         if (lane == 0) {
             pk_set(ps, cs_i, sp);
             pk_set(ps, ct_i, kSpV);
+            vlist[slot] = tx;
         }
-#pragma unroll
-        for (int q = 0; q < P; q++)
-            if (lane == r && q == js) pos[q] = tx;
         if (sp == kSpO) ho++;
         else hh++;
-        rec_hop(rec, rc, disp, lane,
-                disp_off + plain_offset32(L0, L1, L2, SX >> 1, SY >> 1, SZ >> 1, site_type(SX, SY)),
-                disp_off + plain_offset32(L0, L1, L2, TX >> 1, TY >> 1, TZ >> 1, site_type(TX, TY)), hx, hy, hz);
+        prec_hop(pr, disp, disp_off, L0, L1, L2, lane, cs_i, ct_i, hx, hy, hz);
         done++;
         // one pass over the neighbours of both sites: lanes 0-7 around the
         // moved vacancy's new site (its new rates), lanes 8-15 around its old
@@ -1692,16 +1752,9 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             }
         }
         {
-            const double nt = lane_value(seg_scan<8>(kn, lane & 7), 7);
-            const double delta = nt - tot_old;
-#pragma unroll
-            for (int q = 0; q < P; q++) {
-                if (q == js) {
-                    if (lane == r) tot[q] = nt;
-                    if (lane >= r) incl[q] += delta;
-                    colT[q] += delta;
-                }
-            }
+            const double delta = lane_value(seg_scan<8>(kn, lane & 7), 7) - tot_old;
+            if (lane == r) bsum += delta;
+            if (lane >= r) bincl += delta;
             R += delta;
         }
         uint64_t aff = __ballot(lane < 16 && spn == kSpV && nb != tx);
@@ -1709,21 +1762,25 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             const int l = __ffsll((unsigned long long)aff) - 1;
             aff &= aff - 1;
             const uint32_t pa = (uint32_t)__builtin_amdgcn_readlane((int)nb, l);
+            // its slot, from the lanes' slot positions
+            int hit = -1;
 #pragma unroll
-            for (int q = 0; q < P; q++) {
-                const uint64_t m = __ballot(valid[q] && pos[q] == pa);
-                if (m) {
-                    const int a = __ffsll((unsigned long long)m) - 1;
-                    const double na = plain_slot_rates(C, ps, krate, kspec, 64 * q + a, pa, lane);
-                    const double delta = na - lane_value(tot[q], a);
-                    if (lane == a) tot[q] = na;
-                    if (lane >= a) incl[q] += delta;
-                    colT[q] += delta;
-                    R += delta;
-                }
+            for (int q = 0; q < P; q++)
+                if (lane * P + q < nv && vlist[lane * P + q] == pa) hit = q;
+            const uint64_t m = __ballot(hit >= 0);
+            if (m) {
+                const int al = __ffsll((unsigned long long)m) - 1;
+                const int a = al * P + __builtin_amdgcn_readlane(hit, al);
+                const double ko = lane < 8 ? krate[a * 8 + lane] : 0.0;
+                const double old = lane_value(seg_scan<8>(ko, lane & 7), 7);
+                const double dl = plain_slot_rates(C, ps, krate, kspec, a, pa, lane) - old;
+                if (lane == al) bsum += dl;
+                if (lane >= al) bincl += dl;
+                R += dl;
             }
         }
     }
+    prec_flush(pr, disp, disp_off, L0, L1, L2);
     if (lane == 0) {
         St->t = t;
         St->draws = draws;
@@ -1864,13 +1921,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             double* krate = (double*)c2s;
             unsigned char* kspec = (unsigned char*)(krate + 8 * plain_slots);
             if (plain_slots == 64)
-                solo_plain<1>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane, rec, rc);
+                solo_plain<1>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
             else if (plain_slots == 128)
-                solo_plain<2>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane, rec, rc);
+                solo_plain<2>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
             else if (plain_slots == 256)
-                solo_plain<4>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane, rec, rc);
+                solo_plain<4>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
             else
-                solo_plain<8>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane, rec, rc);
+                solo_plain<8>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
         }
     } else if (fast) {
         if (wv == 0) {
@@ -1892,9 +1949,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                 for (int g = wv; g < ngroups; g += nw) {
                     const int f0 = g * K;
                     const int nt = ntiles - f0 < K ? ntiles - f0 : K;
-                    run_group<8, 8>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
-                                 vlist, nv_list, c2s, solo ? rcache + colour * ntiles : nullptr, lane,
-                                 rec, rc, ho, hh, err);
+                    if (K == 4)
+                        run_group<4, 8>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, false,
+                                        vlist, nv_list, c2s, solo ? rcache + colour * ntiles : nullptr,
+                                        lane, rec, rc, ho, hh, err);
+                    else
+                        run_group<8, 8>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
+                                        vlist, nv_list, c2s, solo ? rcache + colour * ntiles : nullptr,
+                                        lane, rec, rc, ho, hh, err);
                 }
                 // per-lane counts of segment leaders to the workgroup totals
                 if (ho) atomicAdd(&hop_tot[0], (unsigned long long)ho);

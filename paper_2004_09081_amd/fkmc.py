@@ -69,7 +69,7 @@ class Stats(C.Structure):
                 ("sum_r", (C.c_int64 * 3) * 3), ("sum_rr", (C.c_int64 * 6) * 3),
                 ("msd", C.c_double * 3), ("D", C.c_double * 3),
                 ("drift", (C.c_double * 3) * 3), ("Dtensor", (C.c_double * 6) * 3),
-                ("busy_ms", C.c_double), ("lds_resident", C.c_uint32), ("reserved", C.c_uint32)]
+                ("busy_ms", C.c_double), ("lds_resident", C.c_uint32), ("tile_group", C.c_uint32)]
 
     def to_dict(self) -> dict:
         return {
@@ -82,6 +82,7 @@ class Stats(C.Structure):
             "drift": np.array([r[:] for r in self.drift]),
             "Dtensor": np.array([r[:] for r in self.Dtensor]),
             "busy_ms": self.busy_ms, "lds_resident": bool(self.lds_resident),
+            "tile_group": int(self.tile_group),
         }
 
 

@@ -309,7 +309,8 @@ GROUP_CASES = SCHED_CASES + [FRAG_CASES["dense_vac"]]
 
 
 @pytest.mark.parametrize("schedule,group", [("lockstep", 8), ("lockstep", 4), ("lockstep", 2),
-                                            ("lockstep", 1), ("persistent", 8), ("persistent", 1)])
+                                            ("lockstep", 1), ("persistent", 8), ("persistent", 4),
+                                            ("persistent", 1)])
 def test_tile_groups_match_oracle(schedule, group):
     """Every tile-group size (tiles per wavefront), including tiles whose
     vacancies overflow their segment's slots and run on the whole
@@ -324,6 +325,10 @@ def test_tile_groups_match_oracle(schedule, group):
     g.set_group(group)
     g.advance(ts, max_cycles=3)
     stats = g.read_stats()
+    if schedule == "persistent":
+        # every member ran the requested group, the HBM-staged one included
+        assert [s["tile_group"] for s in stats] == [group] * len(stats)
+        assert not stats[0]["lds_resident"] and stats[1]["lds_resident"]
     for i, lat in enumerate(lats):
         assert stats[i]["cycles"] == lat.cycles and stats[i]["t"] == lat.t
         assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops]
