@@ -217,7 +217,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg4", choices=["cfg4", "cfg3", "cfg2"])
     ap.add_argument("--lattices", type=int, default=512, help="cfg4 ensemble size")
     ap.add_argument("--hops", type=int, default=1_000_000, help="cfg4 hops per lattice per step")

@@ -316,6 +316,11 @@ struct fkmc_lattice {
     bool plain_lds = true;         // plain lattices that fit run in LDS in the persistent kernel
     std::vector<int32_t> launch_ids;       // this call's persistent-kernel lattices
     std::vector<int32_t> slow_plain_ids;   // this call's plain lattices kept in HBM
+    // launch-order cost of each lattice: the least device time over the
+    // persistent calls of one shape (0: not measured); the least is the
+    // run with the least interference from the workgroup sharing its CU
+    std::vector<uint64_t> cost_ticks;
+    uint64_t cost_shape[2] = {0, 0};       // (max_cycles, min_hops) of those calls
 };
 
 static constexpr int kGraphCycles = 8;
@@ -899,17 +904,22 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         if (plain_lds_fits(L, (uint32_t)i)) ids.push_back(i);
         else slow.push_back(i);
     }
-    // Order of the persistent launch (results do not depend on it): after a
-    // call in which every lattice ran it, the heaviest half by that call's
-    // device time goes first, heaviest first, then the rest lightest first,
-    // so that workgroups dispatched half a launch apart (which share a
-    // compute unit when every workgroup is resident) pair heavy with light.
+    // Order of the persistent launch (results do not depend on it): once
+    // every lattice has a cost from earlier calls of this shape, the heaviest
+    // half goes first, heaviest first, then the rest lightest first, so that
+    // workgroups dispatched half a launch apart (which share a compute unit
+    // when every workgroup is resident) pair heavy with light.
+    if (L->cost_ticks.size() != L->n || L->cost_shape[0] != max_cycles || L->cost_shape[1] != min_hops) {
+        L->cost_ticks.assign(L->n, 0);
+        L->cost_shape[0] = max_cycles;
+        L->cost_shape[1] = min_hops;
+    }
     {
         bool timed = ids.size() >= 2;
-        for (int32_t i : ids) timed = timed && L->h_state[i].busy_ticks > 0;
+        for (int32_t i : ids) timed = timed && L->cost_ticks[i] > 0;
         if (timed) {
             std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
-                return L->h_state[a].busy_ticks > L->h_state[b].busy_ticks;
+                return L->cost_ticks[a] > L->cost_ticks[b];
             });
             std::reverse(ids.begin() + (ids.size() + 1) / 2, ids.end());
         }
@@ -990,6 +1000,10 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
     }
     s = read_states(L);
     if (s) return s;
+    for (int32_t i : ids) {
+        const uint64_t b = L->h_state[i].busy_ticks;
+        if (b > 0) L->cost_ticks[i] = L->cost_ticks[i] ? std::min(L->cost_ticks[i], b) : b;
+    }
     for (uint32_t i = 0; i < L->n; i++) {
         if (L->desc[i].plain) continue;
         const uint64_t nc = L->h_state[i].cycles - L->cycles_host[i];
