@@ -153,6 +153,45 @@ def test_plain_matches_oracle(name, lds):
     assert_same_state(g, 0, lat, name + " horizon")
 
 
+# plain-mode degenerate cases: one vacancy, none, no ion to hop onto (no
+# event at all), and a call ended by the horizon rather than the hop count
+PLAIN_EDGE_CASES = {
+    "one_vacancy": (Case((5, 4, 6), seed=5, nv=1, nh=10, T=650.0, Ea_O=0.6, Ea_H=0.45), 0.0),
+    "no_vacancy": (Case((4, 4, 4), seed=4, nv=0, nh=5), 0.0),
+    "no_ion": (Case((2, 2, 2), seed=3, nv=24, nh=0), 0.0),
+    # 1,000 hops take 1.42e-8 s from this state in the oracle; the horizon
+    # ends the second call part way
+    "horizon": (Case((6, 5, 7), seed=9, lattice_id=3, nv=20, nh=50, T=650.0, Ea_O=0.6, Ea_H=0.45),
+                0.6e-8),
+}
+
+
+@pytest.mark.parametrize("lds", [True, False], ids=["lds", "hbm"])
+@pytest.mark.parametrize("name", list(PLAIN_EDGE_CASES))
+def test_plain_edge_cases_match_oracle(name, lds):
+    """Plain BKL with one vacancy, with none, with no event possible, and
+    stopped by the horizon t_sync (the clock then takes t + t_sync and the
+    draw is spent): draws, clock, hops and state equal the oracle's."""
+    c, horizon = PLAIN_EDGE_CASES[name]
+    say("plain edge parity", name, "lds" if lds else "hbm")
+    lat = c.oracle()
+    g = gpu_set([c])
+    g.set_plain_lds(lds)
+    for n_hops, h in ((500, 0.0), (10**6 if horizon else 1500, horizon)):
+        lat.advance_plain(n_hops, h)
+        g.advance([h], 0, n_hops)
+        st = g.read_stats()[0]
+        assert st["lds_resident"] == (1 if lds else 0)
+        assert st["draws"] == lat.draws
+        assert st["t"] == lat.t
+        assert st["hops"].tolist() == [int(x) for x in lat.hops]
+        assert_same_state(g, 0, lat, name)
+    if name == "horizon":
+        assert 0 < int(lat.hops.sum()) - 500 < 1000
+    if name in ("no_vacancy", "no_ion"):
+        assert lat.draws == 0 and int(lat.hops.sum()) == 0
+
+
 def test_plain_lds_in_ensemble_launch():
     """Plain lattices held in LDS share the persistent launch with fragment
     lattices (hop targets: exact for plain, per cycle for fragments)."""
