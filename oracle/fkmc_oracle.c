@@ -50,6 +50,7 @@
 #define TAG_INIT 1u
 #define TAG_BKL 2u
 #define TAG_PLAIN 3u
+#define TAG_ATOM 4u
 
 /* Boltzmann constant in eV/K: k_B/e from the exact SI values
  * k_B = 1.380649e-23 J/K and e = 1.602176634e-19 C, rounded to nearest
@@ -678,6 +679,116 @@ int or_advance_plain(const or_geom* g, const double k12[12], int8_t* occ, int32_
         done++;
     }
     free(slots);
+    return 0;
+}
+
+/* Atom-selection fragment kMC with null events (Sec. "Atomic-based fragment
+ * kMC method", Eqs. AtomP and TimeStepFrg), over the whole lattice.
+ *
+ * Readings of the paper (it leaves these open):
+ *  - an "atom" I is a vacancy: every event of this model is a vacancy hop,
+ *    so R_I is the sum of the rates of a vacancy's 8 hops, and R^max the
+ *    largest R_I at the start of the stage;
+ *  - a stage selects N^frg atoms, each uniformly and independently (with
+ *    replacement) among the vacancies, slot a = floor(x0 * n / 2^32);
+ *  - each selected atom takes its event i with probability k_i / R^max,
+ *    else a null event: the first event whose cumulative rate exceeds
+ *    u * R^max, none when u * R^max >= R_I;
+ *  - every selection is decided on the rates at the start of the stage; the
+ *    non-null events are then applied in selection order, and one whose
+ *    vacancy or target site an earlier applied event of the stage touched
+ *    becomes null (this covers an atom selected twice);
+ *  - t advances by N^updated * (-ln r') / sum_i k_i with one r' per stage
+ *    and the total rate at the stage start (Eq. TimeStepFrg).
+ * Slots are the vacancies in ascending canonical index at the start of the
+ * call, each following its vacancy.  Stage number n (a persistent counter)
+ * draws selection j from Philox counter (n_lo, n_hi, j, TAG_ATOM) (x0: the
+ * atom, x2 x3: u in [0,1)) and r' from (n_lo, n_hi, 0xFFFFFFFF, TAG_ATOM)
+ * (x2 x3: u in (0,1]).  Runs n_stages stages, fewer when no event is
+ * possible. */
+int or_advance_atomic(const or_geom* g, const double k12[12], int8_t* occ, int32_t* disp,
+                      uint64_t* stages, double* t, uint32_t n_frg, uint64_t n_stages,
+                      uint64_t hops[2])
+{
+    int64_t N = n_sites(g), s;
+    int n_slots = 0, j, a, d;
+    int64_t *slots, *touched;
+    double *k, *RI;
+    int *sel_slot, *sel_ev;
+    step_ctx S;
+    uint32_t key[2], ctr[4], x[4];
+    uint64_t st;
+    or_hops();
+    for (s = 0; s < N; s++) n_slots += (occ[s] == SP_V);
+    slots = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_slots > 0 ? n_slots : 1));
+    k = (double*)malloc(sizeof(double) * (size_t)(n_slots > 0 ? 8 * n_slots : 1));
+    RI = (double*)malloc(sizeof(double) * (size_t)(n_slots > 0 ? n_slots : 1));
+    sel_slot = (int*)malloc(sizeof(int) * (size_t)(n_frg > 0 ? n_frg : 1));
+    sel_ev = (int*)malloc(sizeof(int) * (size_t)(n_frg > 0 ? n_frg : 1));
+    touched = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * (n_frg > 0 ? n_frg : 1)));
+    n_slots = 0;
+    for (s = 0; s < N; s++)
+        if (occ[s] == SP_V) slots[n_slots++] = s;
+    S.g = g; S.k12 = k12; S.occ = occ; S.disp = disp;
+    S.slot_site = slots; S.n_slots = n_slots; S.lo = NULL; S.hi = NULL;
+    key[0] = g->seed; key[1] = g->lattice_id;
+    hops[0] = hops[1] = 0;
+    for (st = 0; st < n_stages; st++) {
+        double Rmax = 0.0, K = 0.0, u, dt;
+        int n_touched = 0, n_upd = 0;
+        /* rates at the start of the stage: R_I, R^max and sum_i k_i */
+        for (a = 0; a < n_slots; a++) {
+            RI[a] = 0.0;
+            for (d = 0; d < 8; d++) {
+                k[a * 8 + d] = event_rate(&S, slots[a], d);
+                RI[a] = RI[a] + k[a * 8 + d];
+            }
+            if (RI[a] > Rmax) Rmax = RI[a];
+            K = K + RI[a];
+        }
+        if (K == 0.0) break;
+        /* N^frg atoms, each with an event of probability k_i / R^max or null */
+        for (j = 0; j < (int)n_frg; j++) {
+            double y, C = 0.0;
+            ctr[0] = (uint32_t)*stages; ctr[1] = (uint32_t)(*stages >> 32);
+            ctr[2] = (uint32_t)j; ctr[3] = TAG_ATOM;
+            or_philox4x32_10(ctr, key, x);
+            a = (int)(((uint64_t)x[0] * (uint64_t)n_slots) >> 32);
+            y = u53_open1(x[2], x[3]) * Rmax;
+            sel_slot[j] = a;
+            sel_ev[j] = -1;
+            for (d = 0; d < 8; d++) {
+                C = C + k[a * 8 + d];
+                if (C > y) { sel_ev[j] = d; break; }
+            }
+        }
+        /* apply in selection order; a hop onto or from a site an earlier
+         * hop of this stage touched is null */
+        for (j = 0; j < (int)n_frg; j++) {
+            int c[3], tt, tc[3], tq, m, clash = 0;
+            int64_t src, tgt;
+            if (sel_ev[j] < 0) continue;
+            src = slots[sel_slot[j]];
+            site_coords(g, src, c, &tt);
+            tgt = hop_target(g, c, tt, sel_ev[j], tc, &tq);
+            for (m = 0; m < n_touched; m++)
+                if (touched[m] == src || touched[m] == tgt) clash = 1;
+            if (clash) continue;
+            apply_event(&S, sel_slot[j] * 8 + sel_ev[j], hops);
+            touched[n_touched++] = src;
+            touched[n_touched++] = tgt;
+            n_upd++;
+        }
+        /* Eq. TimeStepFrg */
+        ctr[0] = (uint32_t)*stages; ctr[1] = (uint32_t)(*stages >> 32);
+        ctr[2] = 0xFFFFFFFFu; ctr[3] = TAG_ATOM;
+        or_philox4x32_10(ctr, key, x);
+        u = u53_open0(x[2], x[3]);
+        dt = -or_ln(u) / K;
+        *t = *t + dt * (double)n_upd;
+        *stages = *stages + 1;
+    }
+    free(slots); free(k); free(RI); free(sel_slot); free(sel_ev); free(touched);
     return 0;
 }
 

@@ -72,6 +72,9 @@ def lib():
         _lib.or_advance_plain.argtypes = [P(_Geom), P(C.c_double), C.c_void_p, C.c_void_p,
                                           P(C.c_uint64), P(C.c_double), C.c_double, C.c_uint64,
                                           P(C.c_uint64)]
+        _lib.or_advance_atomic.argtypes = [P(_Geom), P(C.c_double), C.c_void_p, C.c_void_p,
+                                           P(C.c_uint64), P(C.c_double), C.c_uint32, C.c_uint64,
+                                           P(C.c_uint64)]
         _lib.or_num_fragments.argtypes = [P(_Geom)]
         _lib.or_footprint_sites.argtypes = [P(_Geom), C.c_int, C.c_int, P(C.c_int64), C.c_int64]
         _lib.or_edge_active.argtypes = [P(_Geom), C.c_int64, C.c_int, C.c_int, C.c_int]
@@ -283,6 +286,21 @@ class Lattice:
         lib().or_advance_plain(C.byref(self._gc), _dp(self.k12), self.occ.ctypes.data,
                                self.disp.ctypes.data, C.byref(d), C.byref(t), float(t_horizon),
                                int(n_hops), h)
+        self.draws = d.value
+        self.t = t.value
+        self.hops += np.array([h[0], h[1]], dtype=np.uint64)
+        return (h[0], h[1])
+
+    def advance_atomic(self, n_frg: int, n_stages: int):
+        """Atom-selection fragment kMC with null events (Eqs. AtomP and
+        TimeStepFrg): n_stages stages of n_frg selected vacancies each.  The
+        stage counter is the plain draw counter `draws`."""
+        h = (C.c_uint64 * 2)()
+        d = C.c_uint64(self.draws)
+        t = C.c_double(self.t)
+        lib().or_advance_atomic(C.byref(self._gc), _dp(self.k12), self.occ.ctypes.data,
+                                self.disp.ctypes.data, C.byref(d), C.byref(t), int(n_frg),
+                                int(n_stages), h)
         self.draws = d.value
         self.t = t.value
         self.hops += np.array([h[0], h[1]], dtype=np.uint64)
