@@ -199,6 +199,28 @@ fkmc_status fkmc_max_domain_sites(const fkmc_geometry* g, uint64_t* out);
 fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_cycles,
                          uint64_t min_hops);
 
+/* Atom-selection fragment kMC with null events (Sec. "Atomic-based fragment
+ * kMC method", Eqs. AtomP and TimeStepFrg), for sets whose lattices are all
+ * plain (fragment edge 0) and fit in LDS (at most 512 vacancies, occupancy
+ * at 2 bits per site plus the rate table within 64 KB).  Runs n_stages
+ * stages on every lattice (fewer when no event is possible), one wavefront
+ * per lattice.  An atom is a vacancy, its events its 8 hops.  A stage takes
+ * the rates at its start (K = sum of all rates, R^max = largest vacancy
+ * total), then n_frg (1..64) selections: selection j picks vacancy slot
+ * floor(x0 * n_vac / 2^32) and its first hop whose cumulative rate exceeds
+ * u * R^max, or a null event (Philox counter (n_lo, n_hi, j, 4) at stage n;
+ * u from words 2 and 3, in [0,1)).  The hops are taken in selection order,
+ * and one whose vacancy or target site an earlier taken hop of the stage
+ * touched becomes null.  The clock moves by N_updated * (-ln r') / K with r'
+ * from counter (n_lo, n_hi, 0xFFFFFFFF, 4).  Slots are the vacancies in
+ * canonical order at the call start, each following its vacancy; the stage
+ * counter is the lattice's draw counter (fkmc_stats.draws).  With n_frg = 1
+ * the trajectory is an exact kMC trajectory; with more, simultaneous
+ * selections make it the paper's parallel approximation.  Synchronous.
+ * FKMC_E_UNSUPPORTED for a fragment lattice or one that does not fit;
+ * FKMC_E_STATE when rates are not set. */
+fkmc_status fkmc_advance_atomic(fkmc_lattice* lat, uint32_t n_frg, uint64_t n_stages);
+
 /* Scheduling of fragment lattices (results are identical under every
  * schedule):
  *  FKMC_SCHEDULE_LOCKSTEP: one kernel launch per phase covering every tile

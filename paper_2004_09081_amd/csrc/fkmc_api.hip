@@ -1146,6 +1146,42 @@ fkmc_status fkmc_set_graph(fkmc_lattice* L, int32_t enable)
     return FKMC_OK;
 }
 
+fkmc_status fkmc_advance_atomic(fkmc_lattice* L, uint32_t n_frg, uint64_t n_stages)
+{
+    if (!L) return fail(FKMC_E_INVALID, "null handle");
+    if (n_frg < 1 || n_frg > 64) return fail(FKMC_E_INVALID, "n_frg = %u: must be 1..64", n_frg);
+    int64_t lds = 0;
+    for (uint32_t i = 0; i < L->n; i++) {
+        if (!L->rates_ok[i]) return fail(FKMC_E_STATE, "lattice %u: rates not set", i);
+        const fkmc_geometry& g = L->geo[i];
+        if (!L->desc[i].plain)
+            return fail(FKMC_E_UNSUPPORTED, "lattice %u: the atom-selection scheme runs unfragmented lattices", i);
+        const int64_t b = plain_lds_bytes(L, i);
+        if (L->n_vac[i] > (uint64_t)kPlainLdsSlots || g.L[0] > 1023 || g.L[1] > 1023 || g.L[2] > 512 ||
+            b > 65536 - 256)
+            return fail(FKMC_E_UNSUPPORTED,
+                        "lattice %u: the atom-selection scheme needs the lattice in LDS (at most %d "
+                        "vacancies, %lld bytes here)",
+                        i, kPlainLdsSlots, (long long)b);
+        lds = std::max(lds, b);
+        L->desc[i].n_vac = (int32_t)L->n_vac[i];
+        L->desc[i].resident = 1;
+    }
+    if (L->n == 0 || n_stages == 0) return FKMC_OK;
+    fkmc_status s = upload_desc(L);
+    if (s) return s;
+    // every lattice is plain: the plain-id buffer holds them all
+    if (L->slow_plain_ids != L->plain_ids) {
+        L->slow_plain_ids = L->plain_ids;
+        HIP_OK(hipMemcpyAsync(L->d_plain_ids, L->plain_ids.data(), L->plain_ids.size() * 4,
+                              hipMemcpyHostToDevice, L->stream));
+    }
+    L->last_persistent = false;
+    LAUNCH_OK(launch_atomic(L->P, L->d_plain_ids, (int)L->plain_ids.size(), (size_t)((lds + 15) & ~15),
+                            n_frg, n_stages, L->stream));
+    return read_states(L);
+}
+
 fkmc_status fkmc_set_plain_lds(fkmc_lattice* L, int32_t enable)
 {
     if (!L) return fail(FKMC_E_INVALID, "null handle");

@@ -221,6 +221,19 @@ __device__ __forceinline__ double wave_scan_dpp(double v)
     return v;
 }
 
+// Inclusive wavefront prefix maximum of non-negative binary64 values (the
+// same DPP moves as the prefix sum; lanes moved in from outside read 0).
+__device__ __forceinline__ double wave_max_dpp(double v)
+{
+    v = fmax(v, dpp_shifted<0x111, 0xF>(v));
+    v = fmax(v, dpp_shifted<0x112, 0xF>(v));
+    v = fmax(v, dpp_shifted<0x114, 0xF>(v));
+    v = fmax(v, dpp_shifted<0x118, 0xF>(v));
+    v = fmax(v, dpp_shifted<0x142, 0xA>(v));
+    v = fmax(v, dpp_shifted<0x143, 0xC>(v));
+    return v;
+}
+
 __device__ __forceinline__ double lane_value(double v, int lane)
 {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -1584,31 +1597,57 @@ __device__ __forceinline__ double plain_slot_rates(const RateCtx& C, const uint3
     return lane_value(seg_scan<8>(k, lane & 7), 7);
 }
 
-// Runs the call: exactly min_hops hops, stopping early when the next event
-// would land after t + t_sync (t_sync > 0; the clock then takes that value
-// and the draw is spent) or no event is possible.  Draw d uses Philox
-// counter (d_lo, d_hi, 0xFFFFFFFF, 3); draws are computed 64 ahead, one per
-// lane.  vlist holds the nv vacancies (i | j << 10 | k << 20 | t << 30) and
-// is rewritten here as the packed doubled coordinates of each slot.
-//
-// The 8P events of lane l's slots are entries l*8P .. l*8P+8P-1 of the rate
-// table, in event order.  Each lane keeps the total of its block and the
-// inclusive prefix of the block totals over the lanes, so a selection is
-// one ballot over the prefixes (the block), one read of the block's rates
-// into lanes 0 .. 8P-1, their prefix sum and a second ballot (the event).
-template <int P>
-__device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint32_t* vlist, int nv,
-                                           double* krate, unsigned char* kspec, const RateCtx& C, int4* disp,
-                                           LatState* St, const LatCall* Cl, int lane)
+// Load a plain lattice's occupancy into LDS at 2 bits per site in canonical
+// order (16 sites per word) and list its vacancies (i | j << 10 | k << 20 |
+// t << 30, in no particular order) up to `cap` of them; every thread of the
+// workgroup takes part.
+__device__ __forceinline__ void plain_pack_load(const LatDesc& D, const int8_t* occ_lat, uint32_t* pslab,
+                                                uint32_t* vlist, int* vlist_n, int cap)
 {
-    constexpr int NE = 8 * P;  // events per block
-    // descriptor fields in registers: the loop stores to global memory, so
-    // fields read through D would be loaded again (and waited for) each step
-    const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
-    const int64_t disp_off = D.disp_off;
-    const uint32_t seed = D.seed, lid = D.lattice_id;
-    // slot = canonical rank at call start: vacancy lane + 64 q is ranked,
-    // then written to vlist[rank] as packed doubled coordinates
+    const int64_t nbytes = D.n_sites;
+    const int n_words = (int)((nbytes + 15) >> 4);
+    for (int w = threadIdx.x; w < n_words; w += blockDim.x) {
+        uint32_t word = 0;
+        for (int b = 0; b < 16; b++) {
+            const int64_t c = 16 * (int64_t)w + b;
+            if (c >= nbytes) break;
+            const int t = (int)(c % 3);
+            const int64_t cell = c / 3;
+            const int i = (int)(cell % D.L[0]);
+            const int j = (int)((cell / D.L[0]) % D.L[1]);
+            const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
+            const uint32_t sp = (uint32_t)occ_lat[plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)] & 3u;
+            word |= sp << (2 * b);
+            if (sp == (uint32_t)kSpV) {
+                const int v = atomicAdd(vlist_n, 1);
+                if (v < cap)
+                    vlist[v] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20) | ((uint32_t)t << 30);
+            }
+        }
+        pslab[w] = word;
+    }
+}
+
+// Write a packed plain lattice back to its storage; every thread takes part.
+__device__ __forceinline__ void plain_pack_store(const LatDesc& D, int8_t* occ_lat, const uint32_t* pslab)
+{
+    const int64_t nbytes = D.n_sites;
+    for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
+        const int t = (int)(c % 3);
+        const int64_t cell = c / 3;
+        const int i = (int)(cell % D.L[0]);
+        const int j = (int)((cell / D.L[0]) % D.L[1]);
+        const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
+        occ_lat[plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)] = (int8_t)pk_get(pslab, (int)c);
+    }
+}
+
+// Slots of a plain lattice held in LDS: vlist (nv entries, i | j << 10 |
+// k << 20 | t << 30) is rewritten in ascending canonical index as packed
+// doubled coordinates, so slot s is the vacancy of rank s.  One wave.
+template <int P>
+__device__ __forceinline__ void plain_rank_slots(uint32_t* vlist, int nv, int L0, int L1, int lane)
+{
     uint32_t pv[P];
     int key[P], rank[P];
 #pragma unroll
@@ -1638,6 +1677,33 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
     for (int q = 0; q < P; q++)
         if (lane + 64 * q < nv) vlist[rank[q]] = pv[q];
     wave_lds_fence();
+}
+
+// Runs the call: exactly min_hops hops, stopping early when the next event
+// would land after t + t_sync (t_sync > 0; the clock then takes that value
+// and the draw is spent) or no event is possible.  Draw d uses Philox
+// counter (d_lo, d_hi, 0xFFFFFFFF, 3); draws are computed 64 ahead, one per
+// lane.  vlist holds the nv vacancies (i | j << 10 | k << 20 | t << 30) and
+// is rewritten here as the packed doubled coordinates of each slot.
+//
+// The 8P events of lane l's slots are entries l*8P .. l*8P+8P-1 of the rate
+// table, in event order.  Each lane keeps the total of its block and the
+// inclusive prefix of the block totals over the lanes, so a selection is
+// one ballot over the prefixes (the block), one read of the block's rates
+// into lanes 0 .. 8P-1, their prefix sum and a second ballot (the event).
+template <int P>
+__device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint32_t* vlist, int nv,
+                                           double* krate, unsigned char* kspec, const RateCtx& C, int4* disp,
+                                           LatState* St, const LatCall* Cl, int lane)
+{
+    constexpr int NE = 8 * P;  // events per block
+    // descriptor fields in registers: the loop stores to global memory, so
+    // fields read through D would be loaded again (and waited for) each step
+    const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
+    const int64_t disp_off = D.disp_off;
+    const uint32_t seed = D.seed, lid = D.lattice_id;
+    // slot = canonical rank at call start
+    plain_rank_slots<P>(vlist, nv, L0, L1, lane);
     // the rates of every slot (zero past the last vacancy: a block read
     // covers whole blocks) and the block totals
     double bsum = 0.0;
@@ -1789,6 +1855,187 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
     }
 }
 
+// ----------------------------------------------------------------------------
+// Atom-selection fragment kMC with null events (Sec. "Atomic-based fragment
+// kMC method", Eqs. AtomP and TimeStepFrg) on a plain lattice held in LDS,
+// one wave.  An atom is a vacancy (its 8 hops are its events).  A stage:
+//  - every slot's 8 rates at the start of the stage into the rate table;
+//    the total K = sum_i k_i and R^max = max over slots of the slot total;
+//  - lane j < n_frg selects slot a = floor(x0 nv / 2^32) from Philox counter
+//    (stage_lo, stage_hi, j, 4), and its first event whose cumulative rate
+//    exceeds u R^max (u from x2, x3, in [0,1)), or a null event;
+//  - the events are taken in selection order; one whose vacancy or target
+//    site an earlier taken event of the stage touched becomes null;
+//  - the clock moves by N_updated (-ln r') / K, r' from counter
+//    (stage_lo, stage_hi, 0xFFFFFFFF, 4), u in (0,1].
+// Slots are the vacancies in canonical order at the call start, following
+// their vacancies; the stage counter is the lattice's draw counter.  Runs
+// n_stages stages, fewer when no event is possible.
+template <int P>
+__device__ __forceinline__ void atomic_stages(const LatDesc& D, uint32_t* ps, uint32_t* vlist, int nv,
+                                              double* krate, unsigned char* kspec, const RateCtx& C,
+                                              int4* disp, LatState* St, uint32_t n_frg, uint64_t n_stages,
+                                              int lane)
+{
+    const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
+    const int64_t disp_off = D.disp_off;
+    const uint32_t seed = D.seed, lid = D.lattice_id;
+    plain_rank_slots<P>(vlist, nv, L0, L1, lane);
+    PlainRec pr;
+    pr.cur = -1;
+    pr.orig = 0;
+    pr.ax = pr.ay = pr.az = 0;
+    pr.n = 0;
+    pr.pending = false;
+    double t = St->t;
+    uint64_t stage = St->draws;
+    unsigned long long ho = 0, hh = 0;
+    for (uint64_t k = 0; k < n_stages; k++) {
+        // rates at the start of the stage (zero for slots past the last vacancy)
+        double lsum = 0.0, lmax = 0.0;
+#pragma nounroll
+        for (int q = 0; q < P; q++) {
+            const int sidx = lane * P + q;
+            const bool v = sidx < nv;
+            const uint32_t p = v ? vlist[sidx] : 0u;
+            double ri = 0.0;
+#pragma nounroll
+            for (int d = 0; d < 8; d++) {
+                double kd = 0.0;
+                int sp = kSpV;
+                if (v) {
+                    uint32_t np;
+                    int col;
+                    kd = plain_rate_of(C, ps, plain_nb(C, p, d, np, col), col, sp);
+                }
+                krate[sidx * 8 + d] = kd;
+                kspec[sidx * 8 + d] = (unsigned char)sp;
+                ri += kd;
+            }
+            lsum += ri;
+            lmax = fmax(lmax, ri);
+        }
+        const double K = lane_value(wave_scan_dpp(lsum), 63);
+        const double Rmax = lane_value(wave_max_dpp(lmax), 63);
+        if (K == 0.0) break;
+        wave_lds_order();
+        // selection j in lane j: an atom, then its event or a null event
+        int a = 0, e = -1;
+        if ((uint32_t)lane < n_frg) {
+            uint32_t x0, x1, x2, x3;
+            philox10((uint32_t)stage, (uint32_t)(stage >> 32), (uint32_t)lane, 4u, seed, lid, x0, x1, x2,
+                     x3);
+            a = (int)(((uint64_t)x0 * (uint64_t)(uint32_t)nv) >> 32);
+            const double y = u53_lo(x2, x3) * Rmax;
+            double cum = 0.0;
+#pragma unroll
+            for (int d = 0; d < 8; d++) {
+                cum += krate[a * 8 + d];
+                if (e < 0 && cum > y) e = d;
+            }
+        }
+        const bool ev = e >= 0;
+        uint32_t tx = 0;
+        int cs = -1, ct = -1, sp = kSpO, hx = 0, hy = 0, hz = 0;
+        if (ev) {
+            const uint32_t sx = vlist[a];
+            int col;
+            ct = plain_nb(C, sx, e, tx, col, hx, hy, hz);
+            cs = canon_dbl(L0, L1, sx & 2047, (sx >> 11) & 2047, sx >> 22);
+            sp = kspec[a * 8 + e];
+        }
+        // conflicts, in selection order
+        bool taken = false;
+        uint64_t evm = __ballot(ev);
+        while (evm) {
+            const int j = __ffsll((unsigned long long)evm) - 1;
+            evm &= evm - 1;
+            const int sj = __builtin_amdgcn_readlane(cs, j), tj = __builtin_amdgcn_readlane(ct, j);
+            const bool hit = __ballot(taken && (cs == sj || cs == tj || ct == sj || ct == tj)) != 0;
+            if (!hit && lane == j) taken = true;
+        }
+        wave_lds_order();
+        if (taken) {
+            pk_set(ps, cs, sp);
+            pk_set(ps, ct, kSpV);
+            vlist[a] = tx;
+        }
+        uint64_t tm = __ballot(taken);
+        const int n_upd = __popcll(tm);
+        const int n_o = __popcll(__ballot(taken && sp == kSpO));
+        ho += (unsigned long long)n_o;
+        hh += (unsigned long long)(n_upd - n_o);
+        while (tm) {
+            const int j = __ffsll((unsigned long long)tm) - 1;
+            tm &= tm - 1;
+            prec_hop(pr, disp, disp_off, L0, L1, L2, lane, __builtin_amdgcn_readlane(cs, j),
+                     __builtin_amdgcn_readlane(ct, j), __builtin_amdgcn_readlane(hx, j),
+                     __builtin_amdgcn_readlane(hy, j), __builtin_amdgcn_readlane(hz, j));
+        }
+        // Eq. TimeStepFrg
+        {
+            uint32_t x0, x1, x2, x3;
+            philox10((uint32_t)stage, (uint32_t)(stage >> 32), 0xFFFFFFFFu, 4u, seed, lid, x0, x1, x2, x3);
+            const double dt = -clock_ln(u53_hi(x2, x3)) / K;
+            t = t + dt * (double)n_upd;
+        }
+        stage++;
+        wave_lds_order();
+    }
+    prec_flush(pr, disp, disp_off, L0, L1, L2);
+    if (lane == 0) {
+        St->t = t;
+        St->draws = stage;
+        St->hops[0] += ho;
+        St->hops[1] += hh;
+    }
+}
+
+// One workgroup per plain lattice of `ids`: the occupancy is packed into LDS
+// by every thread, wave 0 runs the stages, and every thread writes it back.
+__global__ __launch_bounds__(256) void k_atomic(DevPtrs P, const int32_t* ids, uint32_t n_frg,
+                                                uint64_t n_stages)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int vlist_n;
+    __shared__ double k12[12];
+    const int lane = threadIdx.x & 63;
+    const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
+    const int lat = ids[blockIdx.x];
+    const LatDesc& D = P.desc[lat];
+    LatState* St = P.state + lat;
+    int8_t* occ_lat = P.occ + D.occ_off;
+    const int n_words = (int)((D.n_sites + 15) >> 4);
+    uint32_t* pslab = (uint32_t*)smem;
+    uint32_t* vlist = (uint32_t*)(smem + ((4 * n_words + 15) & ~15));
+    const int slots = D.n_vac <= 64 ? 64 : (D.n_vac <= 128 ? 128 : (D.n_vac <= 256 ? 256 : 512));
+    double* krate = (double*)(vlist + ((D.n_vac + 3) & ~3));
+    unsigned char* kspec = (unsigned char*)(krate + 8 * slots);
+    if (threadIdx.x == 0) vlist_n = 0;
+    if (threadIdx.x < 12) k12[threadIdx.x] = D.k12[threadIdx.x];
+    __syncthreads();
+    plain_pack_load(D, occ_lat, pslab, vlist, &vlist_n, D.n_vac);
+    __syncthreads();
+    const int nv = vlist_n < D.n_vac ? vlist_n : D.n_vac;
+    if (threadIdx.x < 64) {
+        const RateCtx C = {D.L[0], D.L[1], D.L[2], D.gb_period, D.gb_mask, k12};
+        if (slots == 64)
+            atomic_stages<1>(D, pslab, vlist, nv, krate, kspec, C, P.disp, St, n_frg, n_stages, lane);
+        else if (slots == 128)
+            atomic_stages<2>(D, pslab, vlist, nv, krate, kspec, C, P.disp, St, n_frg, n_stages, lane);
+        else if (slots == 256)
+            atomic_stages<4>(D, pslab, vlist, nv, krate, kspec, C, P.disp, St, n_frg, n_stages, lane);
+        else
+            atomic_stages<8>(D, pslab, vlist, nv, krate, kspec, C, P.disp, St, n_frg, n_stages, lane);
+    }
+    __syncthreads();
+    plain_pack_store(D, occ_lat, pslab);
+    if (threadIdx.x == 0) {
+        if (vlist_n != D.n_vac) atomicOr(&St->err, 1u);
+        St->busy_ticks = __builtin_amdgcn_s_memrealtime() - t_begin;
+    }
+}
+
 // Persistent batched kernel: one workgroup per lattice runs the whole call
 // (cycles of 8 phases, workgroup barrier between phases), so every lattice
 // advances at its own pace.  A lattice that fits is kept in LDS for the
@@ -1834,26 +2081,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     __syncthreads();
     if (packed) {
-        for (int w = threadIdx.x; w < n_words; w += blockDim.x) {
-            uint32_t word = 0;
-            for (int b = 0; b < 16; b++) {
-                const int64_t c = 16 * (int64_t)w + b;
-                if (c >= nbytes) break;
-                const int t = (int)(c % 3);
-                const int64_t cell = c / 3;
-                const int i = (int)(cell % D.L[0]);
-                const int j = (int)((cell / D.L[0]) % D.L[1]);
-                const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-                const uint32_t sp = (uint32_t)occ_lat[plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)] & 3u;
-                word |= sp << (2 * b);
-                if (sp == (uint32_t)kSpV) {
-                    const int v = atomicAdd(&vlist_n, 1);
-                    if (v < D.n_vac)
-                        vlist[v] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20) | ((uint32_t)t << 30);
-                }
-            }
-            pslab[w] = word;
-        }
+        plain_pack_load(D, occ_lat, pslab, vlist, &vlist_n, D.n_vac);
     } else if (resident && fast) {
         // canonical order
         for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
@@ -1978,14 +2206,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     rec_flush(rec, rc, P.disp);
     __syncthreads();
     if (packed) {
-        for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
-            const int t = (int)(c % 3);
-            const int64_t cell = c / 3;
-            const int i = (int)(cell % D.L[0]);
-            const int j = (int)((cell / D.L[0]) % D.L[1]);
-            const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-            occ_lat[plain_offset(D.L[0], D.L[1], D.L[2], i, j, k, t)] = (int8_t)pk_get(pslab, (int)c);
-        }
+        plain_pack_store(D, occ_lat, pslab);
     } else if (resident && fast) {
         for (int64_t c = threadIdx.x; c < nbytes; c += blockDim.x) {
             const int t = (int)(c % 3);
@@ -2461,6 +2682,17 @@ int launch_phase(const DevPtrs& P, int colour, int group, void* stream)
     const int blocks = (P.n_groups + wpb - 1) / wpb;
     hipLaunchKernelGGL(phase_fn(group), dim3(blocks), dim3(64 * wpb), lds, (hipStream_t)stream, P,
                        colour);
+    return (int)hipGetLastError();
+}
+
+int launch_atomic(const DevPtrs& P, const int32_t* d_ids, int n, size_t lds, uint32_t n_frg,
+                  uint64_t n_stages, void* stream)
+{
+    if (n == 0) return 0;
+    hipError_t e = hipFuncSetAttribute((const void*)k_atomic, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k_atomic, dim3(n), dim3(256), lds, (hipStream_t)stream, P, d_ids, n_frg, n_stages);
     return (int)hipGetLastError();
 }
 

@@ -127,6 +127,8 @@ int launch_gather(const DevPtrs& P, int lat, int64_t n_sites, int8_t* d_occ_cano
 int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_occ_canon,
                    void* stream);
 int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream);
+int launch_atomic(const DevPtrs& P, const int32_t* d_ids, int n, size_t lds, uint32_t n_frg,
+                  uint64_t n_stages, void* stream);
 int build_cycle_graph(const DevPtrs& P, int group, int cycles, hipGraphExec_t* out);
 int launch_scatter_disp(const DevPtrs& P, int lat, int64_t n_sites, const int32_t* d_disp_canon,
                         void* stream);

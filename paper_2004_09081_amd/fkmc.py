@@ -110,6 +110,7 @@ _SIGS = {
     "fkmc_set_schedule": [C.c_void_p, C.c_int32, C.c_int32],
     "fkmc_set_graph": [C.c_void_p, C.c_int32],
     "fkmc_set_group": [C.c_void_p, C.c_int32],
+    "fkmc_advance_atomic": [C.c_void_p, C.c_uint32, C.c_uint64],
     "fkmc_set_plain_lds": [C.c_void_p, C.c_int32],
     "fkmc_checkpoint_size": [C.c_void_p, C.c_uint32, _P(C.c_size_t)],
     "fkmc_checkpoint": [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t],
@@ -268,6 +269,12 @@ class LatticeSet:
 
     def set_graph(self, on: bool):
         _check(lib().fkmc_set_graph(self._h, 1 if on else 0))
+
+    def advance_atomic(self, n_frg: int, n_stages: int):
+        """Atom-selection fragment kMC with null events (Eqs. AtomP and
+        TimeStepFrg) on a set of plain lattices held in LDS: n_stages stages
+        of n_frg selected vacancies each."""
+        _check(lib().fkmc_advance_atomic(self._h, int(n_frg), int(n_stages)))
 
     def set_group(self, group: int = 0):
         """Tiles per wavefront (0 automatic; 1, 2, 4 or 8)."""

@@ -192,6 +192,64 @@ def test_plain_edge_cases_match_oracle(name, lds):
         assert lat.draws == 0 and int(lat.hops.sum()) == 0
 
 
+# atom-selection scheme (Eqs. AtomP and TimeStepFrg): plain lattices in LDS
+# with 0 to 512 vacancies, H, field, boundary planes, and no ion to hop onto
+ATOMIC_CASES = [
+    Case((5, 4, 6), seed=5, lattice_id=0, nv=1, nh=10, T=650.0, Ea_O=0.6, Ea_H=0.45),
+    Case((8, 8, 8), seed=0, lattice_id=1, nv=15, nh=0, T=600.0, Ea_O=0.6),
+    Case((6, 5, 7), seed=9, lattice_id=3, nv=20, nh=50, T=650.0, Ea_O=0.6, Ea_H=0.45),
+    Case((6, 6, 6), seed=10, lattice_id=4, nv=8, nh=0, T=500.0, Ea_O=0.5, E_z=2e8, gb_period=3,
+         gb_dE=0.1),
+    Case((4, 4, 4), seed=12, lattice_id=5, nv=64, nh=40, T=700.0, Ea_O=0.6, Ea_H=0.5),
+    Case((5, 4, 4), seed=13, lattice_id=6, nv=65, nh=10, T=700.0, Ea_O=0.6, Ea_H=0.5),
+    Case((8, 7, 6), seed=18, lattice_id=7, nv=256, nh=100, T=600.0, Ea_O=0.6, Ea_H=0.45,
+         gb_period=3, gb_dE=0.05),
+    Case((10, 9, 8), seed=20, lattice_id=8, nv=512, nh=200, T=620.0, Ea_O=0.6, Ea_H=0.45, E_z=5e7),
+    Case((4, 4, 4), seed=4, lattice_id=9, nv=0, nh=5),
+    Case((2, 2, 2), seed=3, lattice_id=10, nv=24, nh=0),
+]
+
+
+@pytest.mark.parametrize("n_frg", [1, 7, 64])
+def test_atomic_matches_oracle(n_frg):
+    """The atom-selection scheme with null events on the GPU equals the
+    oracle's bit for bit: stage counter, clock, hops and state, over calls
+    of different lengths, and a plain BKL call in between (the two share
+    the draw counter)."""
+    say("atom-selection parity", n_frg)
+    lats = [c.oracle() for c in ATOMIC_CASES]
+    g = gpu_set(ATOMIC_CASES)
+    for n_st, plain in ((40, 0), (90, 300), (25, 0)):
+        for lat in lats:
+            lat.advance_atomic(n_frg, n_st)
+        g.advance_atomic(n_frg, n_st)
+        if plain:
+            for lat in lats:
+                lat.advance_plain(plain)
+            g.advance([0.0] * len(lats), 0, plain)
+        stats = g.read_stats()
+        for i, lat in enumerate(lats):
+            assert stats[i]["draws"] == lat.draws, (i, n_st)
+            assert stats[i]["t"] == lat.t, (i, n_st)
+            assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops], (i, n_st)
+            assert_same_state(g, i, lat, "atom-selection member %d" % i)
+    assert lats[0].draws == 155 + 300 and lats[8].draws == 0 and lats[9].draws == 0
+
+
+def test_atomic_rejects_what_it_cannot_run():
+    from paper_2004_09081_amd import fkmc as F
+    g = gpu_set(ATOMIC_CASES[:2])
+    for bad in (0, 65):
+        with pytest.raises(F.FkmcError):
+            g.advance_atomic(bad, 1)
+    g = gpu_set([ATOMIC_CASES[0], Case((6, 6, 6), (3, 3, 3), seed=1, nv=4)])
+    with pytest.raises(F.FkmcError):
+        g.advance_atomic(1, 1)
+    g = gpu_set([PLAIN_CASES["hbm_513"]])
+    with pytest.raises(F.FkmcError):
+        g.advance_atomic(1, 1)
+
+
 def test_plain_lds_in_ensemble_launch():
     """Plain lattices held in LDS share the persistent launch with fragment
     lattices (hop targets: exact for plain, per cycle for fragments)."""

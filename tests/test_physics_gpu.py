@@ -84,3 +84,28 @@ def test_biased_drift_closed_form():
     say("  v %.5g ref %.5g (%.2f sigma)" % (v_est, v_ref, (v_est - v_ref) / se))
     assert abs(v_est - v_ref) < 4 * se
     assert se / v_ref < 0.05
+
+
+@pytest.mark.parametrize("n_frg", [1, 8])
+def test_atom_selection_single_vacancy_closed_form(n_frg):
+    """The atom-selection scheme (Eqs. AtomP and TimeStepFrg) on one
+    vacancy: never null, one hop per stage, D = Gamma_tot d^2 / 6."""
+    T, Ea, R, n = 600.0, 0.6, 2048, 300
+    k = 1e13 * math.exp(-Ea / (KB * T))
+    gam = 8 * k
+    cases = [Case((4, 4, 4), seed=79, lattice_id=i, nv=1, nh=0, T=T, Ea_O=Ea) for i in range(R)]
+    say("one-vacancy atom selection", n_frg)
+    g = gpu_set(cases)
+    g.advance_atomic(n_frg, n)
+    st = g.read_stats()
+    assert all(int(s["hops"].sum()) == n for s in st)
+    t = np.array([s["t"] for s in st])
+    r2 = (_displacements(g, R) ** 2).sum(axis=1) * (A / 2) ** 2
+    D_est = r2.mean() / (6 * t.mean())
+    se = r2.std(ddof=1) / math.sqrt(R) / (6 * t.mean())
+    D_ref = gam * (A / math.sqrt(2)) ** 2 / 6
+    say("  D %.5g ref %.5g (%.2f sigma)" % (D_est, D_ref, (D_est - D_ref) / se))
+    assert abs(t.mean() - n / gam) < 4 * t.std(ddof=1) / math.sqrt(R)
+    assert abs(D_est - D_ref) < 4 * se + 0.01 * D_ref
+    assert se / D_ref < 0.05
+
