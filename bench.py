@@ -11,8 +11,10 @@ Printed: one JSON line with whole-job hops/s; the roofline of the dominant
 kernel of the timed region (HIP events around its launches); the fragment
 sweep's roofline on the 600^3 biased lattice (lockstep phase kernel, HIP
 events); the plain (unfragmented) kMC path and the fragment path run one
-lattice per launch on a sample of the same lattices; the surrogate report;
-and the CPU oracle's rate on a bounded sample.
+lattice per launch on a sample of the same lattices; the paper's
+atom-selection scheme with null events on the lattices held in LDS, against
+BKL on the same lattices; the surrogate report; and the CPU oracle's rate on
+a bounded sample.
 
 Other workloads (--workload): cfg3 (600^3 biased lattice), cfg2 (48^3, five
 temperatures as one set).
@@ -213,6 +215,78 @@ def one_per_launch(F, specs, idx, hop_target):
     return ph, pt
 
 
+def atomic_leg(F, specs, n_frg, stages):
+    """The paper's atom-selection scheme with null events (Eqs. AtomP and
+    TimeStepFrg) on every ensemble lattice that fits in LDS unfragmented,
+    all in one launch, against BKL on the same lattices from the same
+    initial states: hops/s of both, and the ratio of the vacancy tracer D
+    for n_frg selections per stage (the paper's parallel approximation) and
+    for one (an exact kMC, so its ratio checks the estimator)."""
+    import torch
+    from paper_2004_09081_amd.autotune import plain_if_sparse
+    sel = []
+    for sp in specs:
+        if plain_if_sparse(sp) == 0:
+            q = copy.copy(sp)
+            q.frag = (0, 0, 0)
+            q.t_sync = 0.0
+            sel.append(q)
+    n = len(sel)
+
+    def run(fn):
+        s = build_set(sel, F)
+        try:
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            fn(s)
+            torch.cuda.synchronize()
+            return time.perf_counter() - a, s.read_stats()
+        finally:
+            s.close()
+
+    t_at, st_a = run(lambda s: s.advance_atomic(n_frg, stages))
+    t_1, st_1 = run(lambda s: s.advance_atomic(1, stages))
+    hops_a, hops_1 = hops_of(st_a), hops_of(st_1)
+
+    def d_ratio(st):
+        """Vacancy tracer D against BKL run to the same simulated time on
+        each lattice (MSD/6t carries a short-time offset from local
+        flicker, so equal times matter): the ratio of the summed estimates
+        (a mean of per-lattice ratios of two noisy estimates is biased
+        upwards), its error by the paired delta method."""
+        horizon = [x["t"] for x in st]
+        cap = 10 * int(hops_of(st).max()) + 100_000  # the horizon ends each run well before this
+        tb, sb = run(lambda s: s.advance(horizon, 0, cap))
+        assert all(y["t"] == h for y, h in zip(sb, horizon))
+        da = np.array([x["D"][2] for x in st])
+        db = np.array([y["D"][2] for y in sb])
+        r = float(da.sum() / db.sum())
+        return ({"value": r, "stderr": float(np.std(da - r * db, ddof=1) / np.sqrt(n) / db.mean())},
+                float(hops_of(sb).sum() / tb))
+
+    ra, bkl_rate = d_ratio(st_a)
+    r1, _ = d_ratio(st_1)
+    target = int(hops_a.mean())
+    rep = {"value": float(hops_a.sum() / t_at), "unit": "hops/s", "lattices": n, "n_frg": n_frg,
+           "stages": stages, "hops_per_stage": float(hops_a.sum() / (n * stages)),
+           "kernel_ms": max(x["busy_ms"] for x in st_a),
+           "bkl_same_lattices": {"value": bkl_rate, "unit": "hops/s",
+                                 "mean_hops_per_lattice": target},
+           "D_vacancy_ratio_to_bkl": ra,
+           "one_selection": {"value": float(hops_1.sum() / t_1), "unit": "hops/s",
+                             "hops_per_stage": float(hops_1.sum() / (n * stages)),
+                             "D_vacancy_ratio_to_bkl": r1},
+           "estimator": "D ratio = sum over lattices of D_V / the same sum for BKL run to the same "
+                        "simulated time on each lattice",
+           "sample": "%d of %d ensemble lattices (those held in LDS unfragmented), %d stages of %d "
+                     "selections (and of 1), each against BKL to the same times" % (n, len(specs), stages, n_frg)}
+    log("atom selection (N_frg %d): %.4g hops/s on %d lattices, %.2f hops per stage, D_V ratio to BKL "
+        "%.4f +- %.4f; N_frg 1: %.4g hops/s, D_V ratio %.4f +- %.4f; BKL on the same lattices %.4g hops/s"
+        % (n_frg, rep["value"], n, rep["hops_per_stage"], ra["value"], ra["stderr"],
+           rep["one_selection"]["value"], r1["value"], r1["stderr"], rep["bkl_same_lattices"]["value"]))
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +306,9 @@ def main():
     ap.add_argument("--frag", default="auto",
                     help="cfg4 fragment edge: cells, 'half' (ceil(L/2)) or 'auto' (autotuned per lattice)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup of the persistent kernel")
+    ap.add_argument("--atomic-stages", type=int, default=20000,
+                    help="stages of the atom-selection leg (0: skip)")
+    ap.add_argument("--atomic-frg", type=int, default=64, help="selections per stage of that leg")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-train", type=int, default=4096)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -412,6 +489,9 @@ def main():
                       % (len(idx), len(specs), hop_target),
             "batched_over_one_per_launch": value / frag_rate}
         log("fragment kMC one-per-launch: %.4g hops/s (batched/one = %.1f)" % (frag_rate, value / frag_rate))
+
+    if args.workload == "cfg4" and args.atomic_stages > 0:
+        out["atom_selection"] = atomic_leg(F, specs, args.atomic_frg, args.atomic_stages)
 
     if args.workload == "cfg4" and not args.no_surrogate:
         from paper_2004_09081_amd import surrogate
