@@ -49,7 +49,9 @@
  *    t_sync is discarded), and the sub-blocks of one colour never share a
  *    site.  The lattice clock then advances by t_sync per cycle.
  *  - Plain mode (frag all 0): one BKL domain over the whole lattice with a
- *    continuous clock (the conventional kMC of the paper).
+ *    continuous clock (the conventional kMC of the paper).  Plain lattices
+ *    can also run the paper's atom-selection scheme with null events
+ *    (fkmc_advance_atomic).
  *  - Random numbers: Philox4x32-10 with key (seed, lattice_id).
  */
 #ifndef FKMC_H
@@ -124,10 +126,12 @@ typedef struct {
     double D[3];           /* tracer diffusion coefficient MSD/(6t), A^2/s */
     double drift[3][3];    /* mean velocity, Angstrom/s */
     double Dtensor[3][6];  /* (<r_a r_b> - <r_a><r_b>)/(2t), A^2/s */
-    double busy_ms;        /* persistent schedule: device time this lattice's
-                              workgroup took in the last fkmc_advance (ms) */
+    double busy_ms;        /* persistent schedule or fkmc_advance_atomic:
+                              device time this lattice's workgroup took in
+                              the last such call (ms) */
     uint32_t lds_resident; /* 1 if the last fkmc_advance ran the persistent
-                              schedule with this lattice held in LDS */
+                              schedule with this lattice held in LDS (or the
+                              last call was fkmc_advance_atomic) */
     uint32_t tile_group;   /* tiles a wavefront ran at once in the last
                               fkmc_advance on the persistent schedule (8, 4
                               or 1; 0 for other runs and plain lattices) */
