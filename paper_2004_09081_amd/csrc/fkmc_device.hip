@@ -832,7 +832,7 @@ struct GroupCall {
 // allows), each caching the rates of 8/G consecutive events; K = 1 with
 // n > 64 recomputes the rates from LDS at every step.  After a hop only the
 // events whose vacancy moved or whose target changed are recomputed.
-template <int K, int E>
+template <int K, int E, bool TR>
 __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, unsigned char* occl,
                                           uint32_t* sxyz, int n, uint32_t f, const GroupCall& X,
                                           int lane, Rec& rec, RecCtl& rc, uint32_t& ho, uint32_t& hh)
@@ -871,6 +871,12 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         }
     };
     if (ev_valid) refresh();
+    // with TR, when lanes cache several events: after a hop, the moved
+    // vacancy's 8 rates are computed by 8 lanes at once and pulled by the
+    // lanes that cache them, instead of each of those lanes computing its
+    // events in turn (the same values; more registers, so the lockstep
+    // kernel, whose tiles mostly cache one event per lane, leaves it off)
+    const bool wide = TR && __ballot(ev_valid && epl > 1) != 0;
 
     double tau = 0.0;
     uint32_t step = 0;
@@ -1015,7 +1021,33 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         }
         step += go ? 1u : 0u;
         wave_lds_order();
-        if (ev_valid && go) {
+        if (wide) {
+            const bool mover = ev_valid && go && my_slot == pslot;
+            if (mover) my_xyz = tx;
+            // the moved vacancy's 8 rates, one per lane of the segment's
+            // first 8, pulled by the lanes that cache them
+            if (__ballot(mover)) {
+                double nk = 0.0;
+                if (go && sl < 8) nk = tile_rate(G, occl, C, tx, sl);
+#pragma unroll
+                for (int j = 0; j < E; j++) {
+                    const double v = lane_pull(nk, sb + ((my_d0 + j) & 7));
+                    if (mover && j < epl) kk[j] = v;
+                    __builtin_amdgcn_sched_barrier(0);  // one pull in flight: few live registers
+                }
+            }
+            // another vacancy next to either site (rare): all its cached events
+            const bool nbr = ev_valid && go && !mover && (nn_site(my_xyz, sx) || nn_site(my_xyz, tx));
+            if (__ballot(nbr)) {
+                if (nbr) refresh();
+            }
+            if (mover) {
+                ls = 0.0;
+#pragma unroll
+                for (int j = 0; j < E; j++)
+                    if (j < epl) ls += kk[j];
+            }
+        } else if (ev_valid && go) {
             if (my_slot == pslot) my_xyz = tx;
             if (my_slot == pslot || nn_site(my_xyz, sx) || nn_site(my_xyz, tx)) refresh();
         }
@@ -1031,7 +1063,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
 // (E1 cached events per lane there).
 // With `single`, every tile runs on the whole wave, one after another, and
 // a streamed lattice stages one footprint at a time.
-template <int K, int E1>
+template <int K, int E1, bool TR>
 __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, int f0, int nt, int colour,
                                           const GroupCall& X, const WaveLds& W, unsigned char* lds0,
                                           int fp, int fps, bool resident, bool single, uint32_t* vlist,
@@ -1080,7 +1112,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
         if (n_seg <= FIT && sl < n_seg) sort_list(W, seg * S, n_seg, sl);
         wave_lds_fence();
         const int n_run = n_seg <= FIT ? n_seg : 0;
-        group_bkl<K, 4>(G, C, lds0, W.xyz + seg * S, n_run, (uint32_t)(f0 + seg), X, lane, rec, rc, ho,
+        group_bkl<K, 4, TR>(G, C, lds0, W.xyz + seg * S, n_run, (uint32_t)(f0 + seg), X, lane, rec, rc, ho,
                         hh);
         wave_lds_fence();
         if (resident && sl < n_run) list_update(W, G, D, vlist, seg * S, sl);
@@ -1117,7 +1149,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
         }
         for (int l = lane; l < n1; l += 64) sort_list(W, 0, n1, l);
         wave_lds_fence();
-        group_bkl<1, E1>(T, C, lds0, W.xyz, n1, (uint32_t)(f0 + q), X, lane, rec, rc, ho, hh);
+        group_bkl<1, E1, TR>(T, C, lds0, W.xyz, n1, (uint32_t)(f0 + q), X, lane, rec, rc, ho, hh);
         wave_lds_fence();
         if (resident)
             for (int l = lane; l < n1; l += 64) list_update(W, T, D, vlist, 0, l);
@@ -1163,7 +1195,7 @@ __global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colou
     uint32_t ho = 0, hh = 0;
     bool err = false;
     if (lane < 12) W.k12[lane] = D.k12[lane];
-    run_group<KG, 4>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratch, P.fp_stride,
+    run_group<KG, 4, false>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratch, P.fp_stride,
                   false, K == 1, nullptr, 0, nullptr, nullptr, lane, rec, rc, ho, hh, err);
     rec_flush(rec, rc, P.disp);
     constexpr int S = K == 1 ? 64 : 64 / K;
@@ -2178,11 +2210,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                     const int f0 = g * K;
                     const int nt = ntiles - f0 < K ? ntiles - f0 : K;
                     if (K == 4)
-                        run_group<4, 8>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, false,
+                        run_group<4, 8, true>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, false,
                                         vlist, nv_list, c2s, solo ? rcache + colour * ntiles : nullptr,
                                         lane, rec, rc, ho, hh, err);
                     else
-                        run_group<8, 8>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
+                        run_group<8, 8, true>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
                                         vlist, nv_list, c2s, solo ? rcache + colour * ntiles : nullptr,
                                         lane, rec, rc, ho, hh, err);
                 }
