@@ -72,3 +72,85 @@ def test_full_size_biased_lattice_init_and_phase():
     assert disp1.astype(np.int64).sum(axis=0).tolist() == [0, 0, 0]
     st = g.read_stats()[0]
     assert int(st["hops"].sum()) > 0 and st["count"][2] == sp.n_vac
+
+
+def _oracle_of(sp):
+    og = O.Geometry(L=sp.L, frag=sp.frag, a_angstrom=sp.a, seed=sp.seed, lattice_id=sp.lattice_id,
+                    gb_period_cells=sp.gb_period, gb_axes_mask=sp.gb_mask)
+    lat = O.Lattice(og)
+    lat.init_random(sp.n_vac, sp.n_h)
+    lat.set_rates(O.RateParams(T=sp.T, Ea_O=sp.Ea_O, Ea_H=sp.Ea_H, E_z=sp.E_z, q=sp.q,
+                               gb_period_cells=sp.gb_period, gb_axes_mask=sp.gb_mask,
+                               gb_dE=sp.gb_dE))
+    return lat
+
+
+def test_full_ensemble_sampled_lattices_match_oracle():
+    """The 512-lattice ensemble at full size in the launch the benchmark
+    times (one persistent launch per call, 4 wavefronts per workgroup, plain
+    lattices held in LDS in the same launch, the launch order from the first
+    call's device times), with a fixed mix of decompositions that covers the
+    kernel's paths (unfragmented in LDS; fragments of 6-16 cells, held in LDS
+    or staged from HBM, in tile groups of 8, 4 or 1).  Two calls of 1e5 hops
+    per lattice (the benchmark's step is 1e6): four sampled lattices (plain,
+    resident, HBM-staged, crowded) equal the oracle's bit for bit, and every
+    lattice conserves its species and a zero displacement sum."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_09081_amd import fkmc as F
+    from paper_2004_09081_amd import workloads as W
+    from paper_2004_09081_amd.autotune import plain_if_sparse
+    specs = W.cfg4(n=512, hops=10**6, frag=8)
+    edges = (6, 8, 10, 12, 16)
+    for i, sp in enumerate(specs):
+        if plain_if_sparse(sp) == 0 and i % 3 == 0:
+            sp.frag = (0, 0, 0)
+            sp.t_sync = 0.0
+        else:
+            sp.frag = (edges[i % len(edges)],) * 3
+    # samples: the smallest plain lattice, a resident fragment lattice, a
+    # staged one, and a crowded one (most vacancies per footprint)
+    plain = [i for i, sp in enumerate(specs) if sp.frag[0] == 0]
+    frag = [i for i, sp in enumerate(specs) if sp.frag[0] > 0]
+    i_plain = min(plain, key=lambda i: specs[i].n_vac * specs[i].L[0])
+    i_res = next(i for i in frag if specs[i].L[0] <= 20)
+    i_stream = next(i for i in frag if 30 <= specs[i].L[0] <= 34 and specs[i].n_vac < 400)
+    i_dense = max((i for i in frag if specs[i].L[0] <= 30),
+                  key=lambda i: specs[i].extra["x_v"] * specs[i].frag[0] ** 3)
+    sample = [i_plain, i_res, i_stream, i_dense]
+    say("full ensemble: 512 lattices, samples", sample)
+    geoms, rates = W.to_gpu(specs, F)
+    g = F.LatticeSet(geoms)
+    g.init_random([sp.n_vac for sp in specs], [sp.n_h for sp in specs])
+    g.set_rates(rates)
+    g.set_schedule("auto", 4)
+    ts = [sp.t_sync for sp in specs]
+    H = 100_000
+    for call in range(2):
+        g.advance(ts, max_cycles=10**9, min_hops=H)
+    st = g.read_stats()
+    assert any(s["lds_resident"] and specs[i].frag[0] == 0 for i, s in enumerate(st))
+    assert any(not s["lds_resident"] for s in st)
+    groups = {s["tile_group"] for i, s in enumerate(st) if specs[i].frag[0] > 0}
+    assert groups >= {1, 8}, groups
+    for i, s in enumerate(st):
+        sp = specs[i]
+        assert s["count"].tolist() == [3 * sp.L[0] ** 3 - sp.n_vac - sp.n_h, sp.n_h, sp.n_vac]
+        assert s["sum_r"].sum(axis=0).tolist() == [0, 0, 0]
+        assert int(s["hops"].sum()) >= 2 * H
+    for i in sample:
+        sp = specs[i]
+        say("  oracle for lattice", i, sp.L, sp.frag, sp.n_vac)
+        lat = _oracle_of(sp)
+        for call in range(2):
+            if sp.frag[0] == 0:
+                lat.advance_plain(H)
+            else:
+                lat.advance(sp.t_sync, max_cycles=10**9, min_hops=H)
+        s = st[i]
+        assert s["cycles"] == lat.cycles and s["t"] == lat.t, i
+        assert s["hops"].tolist() == [int(x) for x in lat.hops], i
+        occ, disp = g.read_state(i)
+        assert np.array_equal(occ, lat.occ), "lattice %d occupancy" % i
+        assert np.array_equal(disp, lat.disp), "lattice %d displacement" % i
