@@ -1033,7 +1033,6 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
                 for (int j = 0; j < E; j++) {
                     const double v = lane_pull(nk, sb + ((my_d0 + j) & 7));
                     if (mover && j < epl) kk[j] = v;
-                    __builtin_amdgcn_sched_barrier(0);  // one pull in flight: few live registers
                 }
             }
             // another vacancy next to either site (rare): all its cached events
@@ -1477,12 +1476,19 @@ __device__ __forceinline__ int pk_get(const uint32_t* ps, int c)
 }
 
 // Set the 2-bit species of site c: two LDS atomics without return (clear,
-// then set), so nothing waits for a read of the word.
+// then set), so nothing waits for a read of the word.  The word address
+// carries a zero from a register the compiler cannot see into, so it is
+// not known to be uniform and the atomics are issued as written (a
+// uniform-address atomic gets a wavefront-combining wrapper, five more
+// instructions each, even when only one lane is active).
 __device__ __forceinline__ void pk_set(uint32_t* ps, int c, int v)
 {
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    uint32_t* w = ps + ((c >> 4) + z);
     const int sh = (c & 15) << 1;
-    atomicAnd(&ps[c >> 4], ~(3u << sh));
-    atomicOr(&ps[c >> 4], (uint32_t)v << sh);
+    atomicAnd(w, ~(3u << sh));
+    atomicOr(w, (uint32_t)v << sh);
 }
 
 // Neighbour d of the site at packed doubled coordinates p: its canonical
