@@ -732,9 +732,9 @@ static fkmc_status prepare_lockstep(fkmc_lattice* L)
     // the shared steps save (measured on the 600^3 sweep)
     int g = 4;
     for (int32_t i : L->batch_ids)
-        g = std::min(g, pick_group(mean_footprint_vacancies(L, i), L->fp_stride, 32768 - kWaveScratch, true));
+        g = std::min(g, pick_group(mean_footprint_vacancies(L, i), L->fp_stride, 32768 - kWaveScratchStaged, true));
     if (L->group_override) g = L->group_override;
-    while (g > 1 && kWaveScratch + g * L->fp_stride > 65536) g /= 2;
+    while (g > 1 && kWaveScratchStaged + g * L->fp_stride > 65536) g /= 2;
     std::vector<int2> groups;
     for (int32_t i : L->batch_ids) {
         const LatDesc& D = L->desc[i];
@@ -746,7 +746,7 @@ static fkmc_status prepare_lockstep(fkmc_lattice* L)
                               hipMemcpyHostToDevice, L->stream));
     HIP_OK(hipStreamSynchronize(L->stream));
     L->P.n_groups = (int32_t)groups.size();
-    L->P.lds_wave_bytes = kWaveScratch + g * L->fp_stride;
+    L->P.lds_wave_bytes = kWaveScratchStaged + g * L->fp_stride;
     if (L->graph) {
         (void)hipGraphExecDestroy(L->graph);
         L->graph = nullptr;

@@ -535,6 +535,8 @@ constexpr int kLdsEnd = kLdsIdx + 256;
 static_assert(sizeof(TileRec) == 48, "tile record layout");
 static_assert(kLdsK12 % 8 == 0 && kLdsRawKey % 8 == 0, "scratch alignment");
 static_assert(kLdsEnd <= kWaveScratch && kWaveScratch % 16 == 0, "wave scratch size");
+static_assert(kLdsRawIdx == kWaveScratchStaged && kLdsIdx > kLdsRawIdx,
+              "the staged-tile scratch ends where the index arrays begin");
 
 __device__ __forceinline__ WaveLds wave_lds(unsigned char* b)
 {
@@ -623,7 +625,8 @@ __device__ __forceinline__ void seg_site(const TileGeo& G, int k, int li, int& l
 }
 
 // Append a vacancy at local cell (lx,ly,lz), type t of tile G to slot list
-// `list` (entries [list*cap, list*cap + cap), counter cnt[ci]).
+// `list` (entries [list*cap, list*cap + cap), counter cnt[ci]); vidx is its
+// vacancy-list index, or < 0 for a staged tile (no index kept).
 __device__ __forceinline__ void put_slot(const WaveLds& W, const TileGeo& G, int L0, int L1, int L2,
                                          int ci, int first, int cap, int lx, int ly, int lz, int t,
                                          int vidx)
@@ -637,7 +640,7 @@ __device__ __forceinline__ void put_slot(const WaveLds& W, const TileGeo& G, int
     if (s < cap) {
         W.raw_key[first + s] = key;
         W.raw_xyz[first + s] = pack_xyz(2 * lx + (t != 0), 2 * ly + (t != 1), 2 * lz + (t != 2));
-        W.raw_idx[first + s] = (uint16_t)vidx;
+        if (vidx >= 0) W.raw_idx[first + s] = (uint16_t)vidx;
     }
 }
 
@@ -672,7 +675,7 @@ __device__ __forceinline__ void scan_staged(const WaveLds& W, const TileGeo& G, 
             if (li < 0 || li >= len) continue;
             int lx, ly, lz, t;
             seg_site(G, k, li, lx, ly, lz, t);
-            put_slot(W, G, L0, L1, L2, ci, first, cap, lx, ly, lz, t, 0);
+            put_slot(W, G, L0, L1, L2, ci, first, cap, lx, ly, lz, t, -1);
         }
     }
 }
@@ -746,14 +749,15 @@ __device__ __forceinline__ void collect_list(const WaveLds& W, const TileRec* R,
     }
 }
 
-// Order n slots of list [first, first+n) by canonical key (keys distinct).
-__device__ __forceinline__ void sort_list(const WaveLds& W, int first, int n, int l)
+// Order n slots of list [first, first+n) by canonical key (keys distinct);
+// the vacancy-list indices follow for a resident lattice.
+__device__ __forceinline__ void sort_list(const WaveLds& W, int first, int n, int l, bool with_idx)
 {
     const uint64_t key = W.raw_key[first + l];
     int rank = 0;
     for (int j = 0; j < n; j++) rank += W.raw_key[first + j] < key;
     W.xyz[first + rank] = W.raw_xyz[first + l];
-    W.idx[first + rank] = W.raw_idx[first + l];
+    if (with_idx) W.idx[first + rank] = W.raw_idx[first + l];
 }
 
 // Resident lattice: final position of slot l of list `first` back to the list.
@@ -1108,7 +1112,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
         if (resident) tile_lds_resident(G);
         else tile_lds_at(G, fp + seg * fps);
         n_seg = seg < nt ? W.cnt[seg] : 0;
-        if (n_seg <= FIT && sl < n_seg) sort_list(W, seg * S, n_seg, sl);
+        if (n_seg <= FIT && sl < n_seg) sort_list(W, seg * S, n_seg, sl, resident);
         wave_lds_fence();
         const int n_run = n_seg <= FIT ? n_seg : 0;
         group_bkl<K, 4, TR>(G, C, lds0, W.xyz + seg * S, n_run, (uint32_t)(f0 + seg), X, lane, rec, rc, ho,
@@ -1146,7 +1150,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
             err = true;
             continue;
         }
-        for (int l = lane; l < n1; l += 64) sort_list(W, 0, n1, l);
+        for (int l = lane; l < n1; l += 64) sort_list(W, 0, n1, l, resident);
         wave_lds_fence();
         group_bkl<1, E1, TR>(T, C, lds0, W.xyz, n1, (uint32_t)(f0 + q), X, lane, rec, rc, ho, hh);
         wave_lds_fence();
@@ -1194,7 +1198,7 @@ __global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colou
     uint32_t ho = 0, hh = 0;
     bool err = false;
     if (lane < 12) W.k12[lane] = D.k12[lane];
-    run_group<KG, 4, false>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratch, P.fp_stride,
+    run_group<KG, 4, false>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratchStaged, P.fp_stride,
                   false, K == 1, nullptr, 0, nullptr, nullptr, lane, rec, rc, ho, hh, err);
     rec_flush(rec, rc, P.disp);
     constexpr int S = K == 1 ? 64 : 64 / K;

@@ -112,6 +112,9 @@ struct DevPtrs {
 // Per-wave LDS scratch of both fragment kernels (slot lists, tile records,
 // rate table); staged footprints come after it.
 constexpr int kWaveScratch = 3104;
+// lockstep kernel: the same scratch without its last two arrays (the slots'
+// vacancy-list indices, which only LDS-resident lattices use)
+constexpr int kWaveScratchStaged = 2592;
 constexpr int kPhaseWaves = 2;     // waves per lockstep workgroup
 constexpr int kRecCache = 8 * 8 * 48;  // persistent kernel: tile records of a one-group lattice
 
