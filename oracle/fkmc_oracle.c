@@ -31,12 +31,17 @@
  *    after another).  The paper leaves the boundary rule unstated (Sec.
  *    "Atomic-based fragment kMC method": the event lists are gathered and
  *    updated); this edge splitting is the reading used here.
+ *  - The paper's own atom-selection scheme with null events (Eqs. AtomP and
+ *    TimeStepFrg) over a whole lattice, with its open points read as
+ *    written at or_advance_atomic.
  *
  * Parity status: Philox is pinned against an independent library
  * implementation; ln against libm / mpmath; the BKL step and clock against
  * the exact master equation on a 2x2x2 lattice; the phase splitting against
  * the exact product of phase propagators on a 4x4x4 lattice; the single
- * vacancy diffusion coefficient and the biased drift against closed forms.
+ * vacancy diffusion coefficient and the biased drift against closed forms;
+ * the atom-selection scheme with one selection per stage against the exact
+ * master equation, and its single-vacancy diffusion against the closed form.
  */
 #include <stdint.h>
 #include <stdlib.h>
