@@ -199,7 +199,13 @@ fkmc_status fkmc_max_domain_sites(const fkmc_geometry* g, uint64_t* out);
  * event would land after t_start + t_sync[i] (t_sync[i] > 0; the clock is then
  * set to that time) or no event is possible.  Draw d uses Philox counter
  * (d_lo, d_hi, 0xFFFFFFFF, 3).  max_cycles is ignored.
- * t_sync may be NULL for plain-only sets (no horizon). */
+ * t_sync may be NULL for plain-only sets (no horizon).
+ * FKMC_E_RANGE when a BKL domain (a fragment lattice's sub-block plus its
+ * three +faces) holds more than 128 vacancies, or a plain lattice on the
+ * HBM kernel more than 4096; such a domain makes no hop in that phase, so
+ * the trajectory no longer follows the method.  The error stays set: every
+ * later advance, sync or read of the set reports it until fkmc_init_random
+ * or fkmc_set_occupancy initialises that lattice again. */
 fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_cycles,
                          uint64_t min_hops);
 

@@ -369,6 +369,39 @@ def test_no_vacancy_and_errors():
         g.set_occupancy(0, np.full(g.geoms[0].n_sites, 3, np.int8))
 
 
+@pytest.mark.parametrize("schedule", ["lockstep", "persistent"])
+def test_crowded_domain_reports_range_error(schedule):
+    """A BKL domain over the 128-vacancy cap is caught by the kernel's own
+    bounds check and reported as FKMC_E_RANGE; reads keep reporting it
+    until the lattice is initialised again, after which the set runs and
+    matches the oracle."""
+    say("crowded domain error", schedule)
+    from paper_2004_09081_amd import fkmc as F
+    # a fragment of edge 8 has 240-site domains: 1,100 vacancies put about
+    # 170 in each
+    cases = [Case((8, 8, 8), (8, 8, 8), seed=3, lattice_id=0, nv=1100),
+             Case((8, 8, 8), (4, 4, 4), seed=3, lattice_id=1, nv=20)]
+    g = gpu_set(cases)
+    g.set_schedule(schedule, 4)
+    with pytest.raises(F.FkmcError) as e:
+        g.advance([1e-9, 1e-9], max_cycles=2)
+    assert e.value.code == -4 and "lattice 0" in str(e.value)
+    with pytest.raises(F.FkmcError):
+        g.read_stats()
+    cases[0].nv = 60
+    g.init_random([c.nv for c in cases], [c.nh for c in cases])
+    g.set_rates([c.gpu_rates() for c in cases])
+    lats = [c.oracle() for c in cases]
+    ts = [1.0 / (8.0 * l.k12[0]) for l in lats]
+    for lat, t in zip(lats, ts):
+        lat.advance(t, max_cycles=2)
+    g.advance(ts, max_cycles=2)
+    stats = g.read_stats()
+    for i, lat in enumerate(lats):
+        assert stats[i]["cycles"] == 2 and stats[i]["hops"].tolist() == [int(x) for x in lat.hops]
+        assert_same_state(g, i, lat, "after re-initialisation %d" % i)
+
+
 SCHED_CASES = [
     Case((30, 30, 28), (6, 6, 7), seed=21, lattice_id=0, nv=150, nh=600, T=700.0, Ea_O=0.6,
          Ea_H=0.45),                                    # 75,600 sites: not LDS-resident
@@ -552,3 +585,60 @@ def test_checkpoint_resume_is_bit_exact(name):
         lat.advance(t_sync, max_cycles=3)
     assert_same_state(b, 0, lat, "resumed " + name)
     assert sb["t"] == lat.t
+
+
+def _random_cases(seed, n):
+    """n seeded random small configurations: non-cubic lattices of 2-12
+    cells per axis, fragment edges from 0 (plain) up to the lattice,
+    vacancy fractions from one vacancy to crowded, H, field, boundary
+    planes on random axes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        L = tuple(int(x) for x in rng.integers(2, 13, size=3))
+        sites = 3 * L[0] * L[1] * L[2]
+        if rng.random() < 0.3:
+            fr = (0, 0, 0)
+        else:
+            e = int(rng.integers(2, max(L) + 2))
+            fr = (e, e, e)
+        nv = int(min(sites // 3, max(1, round(sites * 10 ** rng.uniform(-2.5, -0.7)))))
+        if fr[0]:
+            # a BKL domain holds at most 128 vacancies: keep the mean per
+            # domain at 40 or below, so none comes near the cap
+            dom = O.max_domain_sites(O.Geometry(L=L, frag=fr))
+            nv = max(1, min(nv, 128, 40 * sites // dom))
+        nh = int(rng.integers(0, (sites - nv) // 4 + 1))
+        gb = int(rng.integers(0, 5)) if rng.random() < 0.4 else 0
+        out.append(Case(L, fr, seed=int(rng.integers(0, 1 << 30)), lattice_id=i, nv=nv, nh=nh,
+                        T=float(rng.uniform(450, 800)), Ea_O=float(rng.uniform(0.5, 0.7)),
+                        Ea_H=float(rng.uniform(0.35, 0.55)), E_z=float(rng.choice([0.0, 1e8, -2e8])),
+                        gb_period=gb, gb_mask=int(rng.integers(1, 8)), gb_dE=0.07 if gb else 0.0))
+    return out
+
+
+@pytest.mark.parametrize("schedule", ["lockstep", "persistent"])
+@pytest.mark.parametrize("seed", [20260, 7])
+def test_random_configurations_match_oracle(schedule, seed):
+    """96 seeded random configurations in one set, two calls (a cycle
+    count, then a hop target), every lattice against the oracle bit for
+    bit."""
+    cases = _random_cases(seed, 96)
+    say("random configurations", schedule, seed)
+    lats = [c.oracle() for c in cases]
+    ts = [0.0 if c.frag[0] == 0 else 1.2 / (8.0 * l.k12[0]) for c, l in zip(cases, lats)]
+    g = gpu_set(cases)
+    g.set_schedule(schedule, 4)
+    for max_cycles, min_hops in ((3, 0), (10**6, 400)):
+        for c, lat, t in zip(cases, lats, ts):
+            if c.frag[0] == 0:
+                lat.advance_plain(min_hops)  # plain: exactly min_hops hops
+            else:
+                lat.advance(t, max_cycles=max_cycles, min_hops=min_hops)
+        g.advance(ts, max_cycles=max_cycles, min_hops=min_hops)
+        stats = g.read_stats()
+        for i, lat in enumerate(lats):
+            assert stats[i]["cycles"] == lat.cycles and stats[i]["t"] == lat.t, (i, cases[i].L, cases[i].frag)
+            assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops], (i, cases[i].L, cases[i].frag)
+            assert_same_state(g, i, lat, "random member %d %s %s" % (i, cases[i].L, cases[i].frag))
+
