@@ -211,10 +211,13 @@ fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_c
 
 /* Atom-selection fragment kMC with null events (Sec. "Atomic-based fragment
  * kMC method", Eqs. AtomP and TimeStepFrg), for sets whose lattices are all
- * plain (fragment edge 0) and fit in LDS (at most 512 vacancies, occupancy
- * at 2 bits per site plus the rate table within 64 KB).  Runs n_stages
- * stages on every lattice (fewer when no event is possible), one wavefront
- * per lattice.  An atom is a vacancy, its events its 8 hops.  A stage takes
+ * plain (fragment edge 0) with at most 4096 vacancies.  Runs n_stages
+ * stages on every lattice (fewer when no event is possible), one workgroup
+ * per lattice: a lattice that fits in LDS (at most 512 vacancies, occupancy
+ * at 2 bits per site plus the rate table within 64 KB) runs there on one
+ * wavefront unless fkmc_set_plain_lds turned that off; any other keeps its
+ * occupancy in HBM and its vacancy slots in LDS.  Results are identical
+ * either way.  An atom is a vacancy, its events its 8 hops.  A stage takes
  * the rates at its start (K = sum of all rates, R^max = largest vacancy
  * total), then n_frg (1..64) selections: selection j picks vacancy slot
  * floor(x0 * n_vac / 2^32) and its first hop whose cumulative rate exceeds
@@ -227,8 +230,8 @@ fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_c
  * counter is the lattice's draw counter (fkmc_stats.draws).  With n_frg = 1
  * the trajectory is an exact kMC trajectory; with more, simultaneous
  * selections make it the paper's parallel approximation.  Synchronous.
- * FKMC_E_UNSUPPORTED for a fragment lattice or one that does not fit;
- * FKMC_E_STATE when rates are not set. */
+ * FKMC_E_UNSUPPORTED for a fragment lattice or one of more than 4096
+ * vacancies; FKMC_E_STATE when rates are not set. */
 fkmc_status fkmc_advance_atomic(fkmc_lattice* lat, uint32_t n_frg, uint64_t n_stages);
 
 /* Scheduling of fragment lattices (results are identical under every
@@ -266,7 +269,8 @@ fkmc_status fkmc_set_group(fkmc_lattice* lat, int32_t group);
  * 512) runs there on one wavefront, in the same launch as the fragment
  * lattices when those use the persistent schedule; every other plain lattice
  * runs the HBM-resident plain kernel.  enable = 0 sends every plain lattice
- * to the HBM kernel.  Results are identical either way. */
+ * to the HBM kernel, in fkmc_advance_atomic too.  Results are identical
+ * either way. */
 fkmc_status fkmc_set_plain_lds(fkmc_lattice* lat, int32_t enable);
 
 /* Lockstep schedule: replay batches of 8 cycles from a prebuilt HIP graph

@@ -1151,34 +1151,46 @@ fkmc_status fkmc_advance_atomic(fkmc_lattice* L, uint32_t n_frg, uint64_t n_stag
     if (!L) return fail(FKMC_E_INVALID, "null handle");
     if (n_frg < 1 || n_frg > 64) return fail(FKMC_E_INVALID, "n_frg = %u: must be 1..64", n_frg);
     int64_t lds = 0;
+    std::vector<int32_t> in_lds, in_hbm;
     for (uint32_t i = 0; i < L->n; i++) {
         if (!L->rates_ok[i]) return fail(FKMC_E_STATE, "lattice %u: rates not set", i);
         const fkmc_geometry& g = L->geo[i];
         if (!L->desc[i].plain)
             return fail(FKMC_E_UNSUPPORTED, "lattice %u: the atom-selection scheme runs unfragmented lattices", i);
         const int64_t b = plain_lds_bytes(L, i);
-        if (L->n_vac[i] > (uint64_t)kPlainLdsSlots || g.L[0] > 1023 || g.L[1] > 1023 || g.L[2] > 512 ||
-            b > 65536 - 256)
+        const bool fits = L->n_vac[i] <= (uint64_t)kPlainLdsSlots && g.L[0] <= 1023 && g.L[1] <= 1023 &&
+                          g.L[2] <= 512 && b <= 65536 - 256;
+        if (fits && L->plain_lds) {
+            lds = std::max(lds, b);
+            L->desc[i].n_vac = (int32_t)L->n_vac[i];
+            L->desc[i].resident = 1;
+            in_lds.push_back((int32_t)i);
+        } else if (L->n_vac[i] <= (uint64_t)kMaxPlainSlots) {
+            L->desc[i].resident = 0;
+            in_hbm.push_back((int32_t)i);
+        } else {
             return fail(FKMC_E_UNSUPPORTED,
-                        "lattice %u: the atom-selection scheme needs the lattice in LDS (at most %d "
-                        "vacancies, %lld bytes here)",
-                        i, kPlainLdsSlots, (long long)b);
-        lds = std::max(lds, b);
-        L->desc[i].n_vac = (int32_t)L->n_vac[i];
-        L->desc[i].resident = 1;
+                        "lattice %u: %llu vacancies; the atom-selection scheme runs at most %d",
+                        i, (unsigned long long)L->n_vac[i], kMaxPlainSlots);
+        }
     }
     if (L->n == 0 || n_stages == 0) return FKMC_OK;
     fkmc_status s = upload_desc(L);
     if (s) return s;
-    // every lattice is plain: the plain-id buffer holds them all
-    if (L->slow_plain_ids != L->plain_ids) {
-        L->slow_plain_ids = L->plain_ids;
-        HIP_OK(hipMemcpyAsync(L->d_plain_ids, L->plain_ids.data(), L->plain_ids.size() * 4,
-                              hipMemcpyHostToDevice, L->stream));
+    // every lattice is plain: the plain-id buffer holds them all, those held
+    // in LDS first
+    std::vector<int32_t> ord = in_lds;
+    ord.insert(ord.end(), in_hbm.begin(), in_hbm.end());
+    if (L->slow_plain_ids != ord) {
+        L->slow_plain_ids = ord;
+        HIP_OK(hipMemcpyAsync(L->d_plain_ids, ord.data(), ord.size() * 4, hipMemcpyHostToDevice,
+                              L->stream));
     }
     L->last_persistent = false;
-    LAUNCH_OK(launch_atomic(L->P, L->d_plain_ids, (int)L->plain_ids.size(), (size_t)((lds + 15) & ~15),
-                            n_frg, n_stages, L->stream));
+    LAUNCH_OK(launch_atomic(L->P, L->d_plain_ids, (int)in_lds.size(), (size_t)((lds + 15) & ~15), n_frg,
+                            n_stages, L->stream));
+    LAUNCH_OK(launch_atomic_hbm(L->P, L->d_plain_ids + in_lds.size(), (int)in_hbm.size(), n_frg, n_stages,
+                                L->stream));
     return read_states(L);
 }
 

@@ -2371,6 +2371,50 @@ __device__ __forceinline__ bool plain_adjacent(const LatDesc& D, uint64_t a, uin
 // slot is kept in LDS, so a step sums m <= 16 totals per thread, scans the
 // workgroup, evaluates the 8 rates of the selected slot only, and after the
 // hop re-evaluates just the slots next to its two sites.
+// Vacancy slots of a plain lattice in ascending canonical index, as packed
+// cell/type positions (at most kMaxPlainSlots are stored); every thread of
+// the workgroup calls it and gets the vacancy count.
+__device__ int plain_collect_slots(const LatDesc& D, const DevPtrs& P, uint64_t* slots, int* wcount,
+                                   int* n_sh, int tid)
+{
+    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = kPlainThreads / 64;
+    if (tid == 0) *n_sh = 0;
+    __syncthreads();
+    const int64_t N = D.n_sites;
+    for (int64_t base = 0; base < N; base += kPlainThreads) {
+        const int64_t nidx = base + tid;
+        bool v = false;
+        uint64_t pk = 0;
+        if (nidx < N) {
+            const int t = (int)(nidx % 3);
+            const int64_t cell = nidx / 3;
+            const int i = (int)(cell % D.L[0]);
+            const int j = (int)((cell / D.L[0]) % D.L[1]);
+            const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
+            v = P.occ[D.occ_off + plain_store(D, i, j, k, t)] == kSpV;
+            pk = (uint64_t)i | ((uint64_t)j << 16) | ((uint64_t)k << 32) | ((uint64_t)t << 48);
+        }
+        const uint64_t mk = __ballot(v);
+        if (lane == 0) wcount[wv] = __popcll(mk);
+        __syncthreads();
+        int before = *n_sh;
+        for (int w = 0; w < wv; w++) before += wcount[w];
+        if (v) {
+            const int r = before + __popcll(mk & ((1ull << lane) - 1ull));
+            if (r < kMaxPlainSlots) slots[r] = pk;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int tot = 0;
+            for (int w = 0; w < NW; w++) tot += wcount[w];
+            *n_sh += tot;
+        }
+        __syncthreads();
+    }
+    return *n_sh;
+}
+
 __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_t* ids)
 {
     extern __shared__ __align__(16) unsigned char psm[];
@@ -2392,41 +2436,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     constexpr int NW = kPlainThreads / 64;
 
-    // vacancy slots in ascending canonical index
-    if (tid == 0) n_sh = 0;
-    __syncthreads();
-    const int64_t N = D.n_sites;
-    for (int64_t base = 0; base < N; base += kPlainThreads) {
-        const int64_t nidx = base + tid;
-        bool v = false;
-        uint64_t pk = 0;
-        if (nidx < N) {
-            const int t = (int)(nidx % 3);
-            const int64_t cell = nidx / 3;
-            const int i = (int)(cell % D.L[0]);
-            const int j = (int)((cell / D.L[0]) % D.L[1]);
-            const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-            v = P.occ[D.occ_off + plain_store(D, i, j, k, t)] == kSpV;
-            pk = (uint64_t)i | ((uint64_t)j << 16) | ((uint64_t)k << 32) | ((uint64_t)t << 48);
-        }
-        const uint64_t mk = __ballot(v);
-        if (lane == 0) wcount[wv] = __popcll(mk);
-        __syncthreads();
-        int before = n_sh;
-        for (int w = 0; w < wv; w++) before += wcount[w];
-        if (v) {
-            const int r = before + __popcll(mk & ((1ull << lane) - 1ull));
-            if (r < kMaxPlainSlots) slots[r] = pk;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int tot = 0;
-            for (int w = 0; w < NW; w++) tot += wcount[w];
-            n_sh += tot;
-        }
-        __syncthreads();
-    }
-    const int n = n_sh;
+    const int n = plain_collect_slots(D, P, slots, wcount, &n_sh, tid);
     if (n > kMaxPlainSlots) {
         if (tid == 0) atomicOr(&S->err, 1u);
         return;
@@ -2563,6 +2573,155 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
     if (tid == 0) {
         S->t = t;
         S->draws = draws;
+        S->hops[0] += ho;
+        S->hops[1] += hh;
+        S->busy_ticks = __builtin_amdgcn_s_memrealtime() - t_begin;
+    }
+}
+
+// Atom-selection stages (Sec. "Atomic-based fragment kMC method", Eqs. AtomP
+// and TimeStepFrg) on a plain lattice whose occupancy stays in HBM: one
+// workgroup per lattice, its vacancy slots in LDS in ascending canonical
+// index at the call start, each following its vacancy.  Every stage
+// recomputes the slot totals R_I from the occupancy (K = their sum, R^max
+// their maximum); wave 0 then draws the selections, one per lane, resolves
+// the conflicts in selection order and makes the taken hops in place.
+__global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const int32_t* ids,
+                                                              uint32_t n_frg, uint64_t n_stages)
+{
+    extern __shared__ __align__(16) unsigned char psm[];
+    uint64_t* slots = (uint64_t*)psm;  // [kMaxPlainSlots]
+    __shared__ int wcount[kPlainThreads / 64];
+    __shared__ double wsum[kPlainThreads / 64];
+    __shared__ double wmax[kPlainThreads / 64];
+    __shared__ int n_sh;
+    const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
+    const int lat = ids[blockIdx.x];
+    const LatDesc& D = P.desc[lat];
+    LatState* S = P.state + lat;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = kPlainThreads / 64;
+    const int n = plain_collect_slots(D, P, slots, wcount, &n_sh, tid);
+    if (n > kMaxPlainSlots) {
+        if (tid == 0) atomicOr(&S->err, 1u);
+        return;
+    }
+    const int m = (n + kPlainThreads - 1) / kPlainThreads;
+    const int s0 = tid * m < n ? tid * m : n;
+    const int s1 = s0 + m < n ? s0 + m : n;
+    int8_t* occ = P.occ + D.occ_off;
+    double t = S->t;
+    uint64_t stage = S->draws;
+    unsigned long long ho = 0, hh = 0;
+    for (uint64_t st = 0; st < n_stages; st++) {
+        // rates at the start of the stage
+        double ls = 0.0, lm = 0.0;
+        for (int sidx = s0; sidx < s1; sidx++) {
+            double r = 0.0;
+            for (int d = 0; d < 8; d++) {
+                int64_t ts;
+                r += plain_rate(D, P, slots[sidx], d, ts);
+            }
+            ls += r;
+            lm = fmax(lm, r);
+        }
+        ls = lane_value(wave_scan_dpp(ls), 63);
+        lm = lane_value(wave_max_dpp(lm), 63);
+        if (lane == 0) {
+            wsum[wv] = ls;
+            wmax[wv] = lm;
+        }
+        __syncthreads();
+        double K = 0.0, Rmax = 0.0;
+        for (int w = 0; w < NW; w++) {
+            K += wsum[w];
+            Rmax = fmax(Rmax, wmax[w]);
+        }
+        if (K == 0.0) break;
+        if (wv == 0) {
+            // selection j in lane j: an atom, then its event or a null event
+            int a = 0, e = -1;
+            int64_t cs = -1, ct = -1;
+            uint64_t pk = 0;
+            if ((uint32_t)lane < n_frg) {
+                uint32_t x0, x1, x2, x3;
+                philox10((uint32_t)stage, (uint32_t)(stage >> 32), (uint32_t)lane, 4u, D.seed,
+                         D.lattice_id, x0, x1, x2, x3);
+                a = (int)(((uint64_t)x0 * (uint64_t)(uint32_t)n) >> 32);
+                pk = slots[a];
+                const double y = u53_lo(x2, x3) * Rmax;
+                double cum = 0.0;
+                for (int d = 0; d < 8; d++) {
+                    int64_t ts;
+                    cum += plain_rate(D, P, pk, d, ts);
+                    if (e < 0 && cum > y) {
+                        e = d;
+                        ct = ts;
+                    }
+                }
+            }
+            const bool ev = e >= 0;
+            int sp = kSpO;
+            if (ev) {
+                cs = plain_store(D, (int)(pk & 0xffff), (int)((pk >> 16) & 0xffff),
+                                 (int)((pk >> 32) & 0xffff), (int)(pk >> 48));
+                sp = occ[ct];
+            }
+            // conflicts, in selection order
+            bool taken = false;
+            uint64_t evm = __ballot(ev);
+            while (evm) {
+                const int j = __ffsll((unsigned long long)evm) - 1;
+                evm &= evm - 1;
+                const int64_t sj = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(cs >> 32), j) << 32) |
+                                             (uint32_t)__builtin_amdgcn_readlane((int)cs, j));
+                const int64_t tj = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(ct >> 32), j) << 32) |
+                                             (uint32_t)__builtin_amdgcn_readlane((int)ct, j));
+                const bool hit = __ballot(taken && (cs == sj || cs == tj || ct == sj || ct == tj)) != 0;
+                if (!hit && lane == j) taken = true;
+            }
+            if (taken) {
+                // the taken hops touch disjoint sites: each lane swaps its own pair
+                const int i = (int)(pk & 0xffff), jj = (int)((pk >> 16) & 0xffff),
+                          k = (int)((pk >> 32) & 0xffff), tp = (int)(pk >> 48);
+                int hx, hy, hz;
+                hop_vec(tp, e, hx, hy, hz);
+                occ[cs] = (int8_t)sp;
+                occ[ct] = (int8_t)kSpV;
+                int4* dsrc = P.disp + (D.disp_off + cs);
+                int4* dtgt = P.disp + (D.disp_off + ct);
+                const int4 dv = *dsrc;
+                const int4 di = *dtgt;
+                *dtgt = make_int4(dv.x + hx, dv.y + hy, dv.z + hz, 0);
+                *dsrc = make_int4(di.x - hx, di.y - hy, di.z - hz, 0);
+                int X = 2 * i + (tp != 0) + hx, Y = 2 * jj + (tp != 1) + hy, Z = 2 * k + (tp != 2) + hz;
+                if (X < 0) X += 2 * D.L[0];
+                if (X >= 2 * D.L[0]) X -= 2 * D.L[0];
+                if (Y < 0) Y += 2 * D.L[1];
+                if (Y >= 2 * D.L[1]) Y -= 2 * D.L[1];
+                if (Z < 0) Z += 2 * D.L[2];
+                if (Z >= 2 * D.L[2]) Z -= 2 * D.L[2];
+                slots[a] = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) | ((uint64_t)(Z >> 1) << 32) |
+                           ((uint64_t)site_type(X, Y) << 48);
+            }
+            const int n_upd = __popcll(__ballot(taken));
+            const int n_o = __popcll(__ballot(taken && sp == kSpO));
+            ho += (unsigned long long)n_o;
+            hh += (unsigned long long)(n_upd - n_o);
+            // Eq. TimeStepFrg
+            uint32_t x0, x1, x2, x3;
+            philox10((uint32_t)stage, (uint32_t)(stage >> 32), 0xFFFFFFFFu, 4u, D.seed, D.lattice_id, x0,
+                     x1, x2, x3);
+            const double dt = -clock_ln(u53_hi(x2, x3)) / K;
+            t = t + dt * (double)n_upd;
+            __threadfence();  // the hops are visible to every wave's rates of the next stage
+        }
+        stage++;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        S->t = t;
+        S->draws = stage;
         S->hops[0] += ho;
         S->hops[1] += hh;
         S->busy_ticks = __builtin_amdgcn_s_memrealtime() - t_begin;
@@ -2816,6 +2975,15 @@ int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(k_plain, dim3(n_plain), dim3(kPlainThreads), lds, (hipStream_t)stream, P,
                        d_plain_ids);
+    return (int)hipGetLastError();
+}
+
+int launch_atomic_hbm(const DevPtrs& P, const int32_t* d_ids, int n, uint32_t n_frg, uint64_t n_stages,
+                      void* stream)
+{
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_atomic_hbm, dim3(n), dim3(kPlainThreads), (size_t)8 * kMaxPlainSlots,
+                       (hipStream_t)stream, P, d_ids, n_frg, n_stages);
     return (int)hipGetLastError();
 }
 

@@ -124,6 +124,8 @@ int launch_phase(const DevPtrs& P, int colour, int group, void* stream);
 int launch_cycle_begin(const DevPtrs& P, void* stream);
 int launch_cycle_end(const DevPtrs& P, void* stream);
 int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void* stream);
+int launch_atomic_hbm(const DevPtrs& P, const int32_t* d_ids, int n, uint32_t n_frg, uint64_t n_stages,
+                      void* stream);
 int launch_stats(const DevPtrs& P, int lat, int64_t n_sites, void* stream);
 int launch_gather(const DevPtrs& P, int lat, int64_t n_sites, int8_t* d_occ_canon,
                   int32_t* d_disp_canon, void* stream);

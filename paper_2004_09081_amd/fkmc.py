@@ -272,8 +272,8 @@ class LatticeSet:
 
     def advance_atomic(self, n_frg: int, n_stages: int):
         """Atom-selection fragment kMC with null events (Eqs. AtomP and
-        TimeStepFrg) on a set of plain lattices held in LDS: n_stages stages
-        of n_frg selected vacancies each."""
+        TimeStepFrg) on a set of plain lattices of at most 4096 vacancies:
+        n_stages stages of n_frg selected vacancies each."""
         _check(lib().fkmc_advance_atomic(self._h, int(n_frg), int(n_stages)))
 
     def set_group(self, group: int = 0):

@@ -207,18 +207,25 @@ ATOMIC_CASES = [
     Case((10, 9, 8), seed=20, lattice_id=8, nv=512, nh=200, T=620.0, Ea_O=0.6, Ea_H=0.45, E_z=5e7),
     Case((4, 4, 4), seed=4, lattice_id=9, nv=0, nh=5),
     Case((2, 2, 2), seed=3, lattice_id=10, nv=24, nh=0),
+    # past the LDS kernel: slots in LDS, occupancy in HBM
+    Case((10, 9, 8), seed=21, lattice_id=11, nv=513, nh=50, T=620.0, Ea_O=0.6, Ea_H=0.45),
+    Case((40, 30, 20), seed=23, lattice_id=12, nv=1200, nh=3000, T=650.0, Ea_O=0.6, Ea_H=0.45,
+         E_z=1e8, gb_period=7, gb_dE=0.08),
+    Case((16, 16, 16), seed=24, lattice_id=13, nv=4096, nh=0, T=600.0, Ea_O=0.6),
 ]
 
 
+@pytest.mark.parametrize("lds", [True, False])
 @pytest.mark.parametrize("n_frg", [1, 7, 64])
-def test_atomic_matches_oracle(n_frg):
+def test_atomic_matches_oracle(n_frg, lds):
     """The atom-selection scheme with null events on the GPU equals the
     oracle's bit for bit: stage counter, clock, hops and state, over calls
     of different lengths, and a plain BKL call in between (the two share
-    the draw counter)."""
-    say("atom-selection parity", n_frg)
+    the draw counter).  With lds off every lattice runs the HBM kernel."""
+    say("atom-selection parity", n_frg, "lds" if lds else "hbm")
     lats = [c.oracle() for c in ATOMIC_CASES]
     g = gpu_set(ATOMIC_CASES)
+    g.set_plain_lds(lds)
     for n_st, plain in ((40, 0), (90, 300), (25, 0)):
         for lat in lats:
             lat.advance_atomic(n_frg, n_st)
@@ -245,9 +252,10 @@ def test_atomic_rejects_what_it_cannot_run():
     g = gpu_set([ATOMIC_CASES[0], Case((6, 6, 6), (3, 3, 3), seed=1, nv=4)])
     with pytest.raises(F.FkmcError):
         g.advance_atomic(1, 1)
-    g = gpu_set([PLAIN_CASES["hbm_513"]])
-    with pytest.raises(F.FkmcError):
+    g = gpu_set([Case((16, 16, 17), seed=2, nv=4097)])
+    with pytest.raises(F.FkmcError) as e:
         g.advance_atomic(1, 1)
+    assert e.value.code == -6
 
 
 def test_plain_lds_in_ensemble_launch():
