@@ -287,6 +287,54 @@ def atomic_leg(F, specs, n_frg, stages):
     return rep
 
 
+def atomic_hbm_leg(F, specs, n_frg, stages):
+    """The atom-selection scheme on the ensemble lattices past the LDS
+    kernel (513 to 4096 vacancies, occupancy in HBM), all in one launch,
+    against plain BKL (also HBM-resident, one workgroup per lattice) making
+    the same mean number of hops from the same initial states."""
+    import torch
+    from paper_2004_09081_amd.autotune import plain_if_sparse
+    sel = []
+    for sp in specs:
+        if plain_if_sparse(sp) != 0 and sp.n_vac <= 4096:
+            q = copy.copy(sp)
+            q.frag = (0, 0, 0)
+            q.t_sync = 0.0
+            sel.append(q)
+    if not sel:
+        return None
+
+    def run(fn):
+        s = build_set(sel, F)
+        try:
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            fn(s)
+            torch.cuda.synchronize()
+            return time.perf_counter() - a, s.read_stats()
+        finally:
+            s.close()
+
+    t_at, st_a = run(lambda s: s.advance_atomic(n_frg, stages))
+    hops_a = hops_of(st_a)
+    target = int(hops_a.mean())
+    t_b, st_b = run(lambda s: s.advance([0.0] * len(sel), 0, target))
+    hops_b = hops_of(st_b)
+    rep = {"value": float(hops_a.sum() / t_at), "unit": "hops/s", "lattices": len(sel), "n_frg": n_frg,
+           "stages": stages, "hops_per_stage": float(hops_a.sum() / (len(sel) * stages)),
+           "kernel_ms": max(x["busy_ms"] for x in st_a),
+           "us_per_stage": 1e3 * max(x["busy_ms"] for x in st_a) / stages,
+           "bkl_same_lattices": {"value": float(hops_b.sum() / t_b), "unit": "hops/s",
+                                 "hops_per_lattice": target},
+           "sample": "%d of %d ensemble lattices (513 to 4096 vacancies, unfragmented), %d stages of "
+                     "%d selections; BKL the same mean hop count" % (len(sel), len(specs), stages, n_frg)}
+    log("atom selection on HBM lattices (N_frg %d): %.4g hops/s on %d lattices, %.2f hops per stage, "
+        "%.1f us per stage; BKL on the same lattices %.4g hops/s"
+        % (n_frg, rep["value"], len(sel), rep["hops_per_stage"], rep["us_per_stage"],
+           rep["bkl_same_lattices"]["value"]))
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +357,8 @@ def main():
     ap.add_argument("--atomic-stages", type=int, default=20000,
                     help="stages of the atom-selection leg (0: skip)")
     ap.add_argument("--atomic-frg", type=int, default=64, help="selections per stage of that leg")
+    ap.add_argument("--atomic-hbm-stages", type=int, default=2000,
+                    help="stages of the atom-selection leg on lattices past the LDS kernel (0: skip)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-train", type=int, default=4096)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -492,6 +542,8 @@ def main():
 
     if args.workload == "cfg4" and args.atomic_stages > 0:
         out["atom_selection"] = atomic_leg(F, specs, args.atomic_frg, args.atomic_stages)
+        if args.atomic_hbm_stages > 0:
+            out["atom_selection_hbm"] = atomic_hbm_leg(F, specs, args.atomic_frg, args.atomic_hbm_stages)
 
     if args.workload == "cfg4" and not args.no_surrogate:
         from paper_2004_09081_amd import surrogate

@@ -2556,8 +2556,9 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
             hop_s = pk;
             hop_t = npk;
             ev_sh = sp;
-            __threadfence();  // the occupancy change is visible to the rate updates
         }
+        // the barrier's workgroup-scope fence makes the hop's HBM writes
+        // visible to every wave of this workgroup, the only readers
         __syncthreads();
         if (ev_sh == kSpO) ho++;
         else hh++;
@@ -2579,18 +2580,57 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
     }
 }
 
+// Cells whose slots need new totals after a stage: a hashed bitmap of
+// 2^kMarkBits bits per stage (collisions only cost recomputations).
+constexpr int kMarkBits = 14;
+constexpr int kMarkWords = 1 << (kMarkBits - 5);
+static_assert(kMaxPlainSlots <= 65536, "slot indices of the refresh list are 16-bit");
+
+__device__ __forceinline__ uint32_t cell_mark_bit(int i, int j, int k)
+{
+    return ((uint32_t)i * 0x9E3779B1u ^ (uint32_t)j * 0x85EBCA77u ^ (uint32_t)k * 0xC2B2AE3Du) >>
+           (32 - kMarkBits);
+}
+
+// Mark the 27 cells around cell (i, j, k), periodic: every site next to a
+// site of that cell lies in one of them.
+__device__ __forceinline__ void mark_cells_around(uint32_t* marks, const LatDesc& D, int i, int j, int k)
+{
+    for (int dz = -1; dz <= 1; dz++) {
+        int c = k + dz;
+        c = c < 0 ? c + D.L[2] : (c >= D.L[2] ? c - D.L[2] : c);
+        for (int dy = -1; dy <= 1; dy++) {
+            int b = j + dy;
+            b = b < 0 ? b + D.L[1] : (b >= D.L[1] ? b - D.L[1] : b);
+            for (int dx = -1; dx <= 1; dx++) {
+                int a = i + dx;
+                a = a < 0 ? a + D.L[0] : (a >= D.L[0] ? a - D.L[0] : a);
+                const uint32_t h = cell_mark_bit(a, b, c);
+                atomicOr(marks + (h >> 5), 1u << (h & 31));
+            }
+        }
+    }
+}
+
 // Atom-selection stages (Sec. "Atomic-based fragment kMC method", Eqs. AtomP
 // and TimeStepFrg) on a plain lattice whose occupancy stays in HBM: one
-// workgroup per lattice, its vacancy slots in LDS in ascending canonical
-// index at the call start, each following its vacancy.  Every stage
-// recomputes the slot totals R_I from the occupancy (K = their sum, R^max
-// their maximum); wave 0 then draws the selections, one per lane, resolves
-// the conflicts in selection order and makes the taken hops in place.
+// workgroup per lattice, its vacancy slots and their totals R_I in LDS, the
+// slots in ascending canonical index at the call start, each following its
+// vacancy.  Each stage reduces the totals to K (sum) and R^max (maximum);
+// wave 0 draws the selections, one per lane, resolves the conflicts in
+// selection order, makes the taken hops in place and marks the cells around
+// their sites; the next stage recomputes the totals of the slots in marked
+// cells only.  Two mark bitmaps alternate, so that one is cleared while the
+// other is written.
 __global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const int32_t* ids,
                                                               uint32_t n_frg, uint64_t n_stages)
 {
     extern __shared__ __align__(16) unsigned char psm[];
-    uint64_t* slots = (uint64_t*)psm;  // [kMaxPlainSlots]
+    uint64_t* slots = (uint64_t*)psm;                         // [kMaxPlainSlots]
+    double* stot = (double*)(psm + 8 * kMaxPlainSlots);       // [kMaxPlainSlots]
+    uint32_t* marks = (uint32_t*)(psm + 16 * kMaxPlainSlots); // [2][kMarkWords]
+    uint16_t* fresh = (uint16_t*)(marks + 2 * kMarkWords);   // [kMaxPlainSlots] slots to recompute
+    __shared__ int n_fresh;
     __shared__ int wcount[kPlainThreads / 64];
     __shared__ double wsum[kPlainThreads / 64];
     __shared__ double wmax[kPlainThreads / 64];
@@ -2610,18 +2650,40 @@ __global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const i
     const int s0 = tid * m < n ? tid * m : n;
     const int s1 = s0 + m < n ? s0 + m : n;
     int8_t* occ = P.occ + D.occ_off;
+    auto slot_total = [&](int sidx) {
+        double r = 0.0;
+        for (int d = 0; d < 8; d++) {
+            int64_t ts;
+            r += plain_rate(D, P, slots[sidx], d, ts);
+        }
+        return r;
+    };
+    for (int w = tid; w < 2 * kMarkWords; w += kPlainThreads) marks[w] = 0u;
+    if (tid == 0) n_fresh = 0;
+    for (int sidx = s0; sidx < s1; sidx++) stot[sidx] = slot_total(sidx);
+    __syncthreads();
     double t = S->t;
     uint64_t stage = S->draws;
     unsigned long long ho = 0, hh = 0;
     for (uint64_t st = 0; st < n_stages; st++) {
-        // rates at the start of the stage
+        // rates at the start of the stage: new totals for the slots in cells
+        // the last stage marked, listed first and then shared out evenly
+        if (st > 0) {
+            const uint32_t* seen = marks + ((st + 1) & 1) * kMarkWords;
+            for (int sidx = s0; sidx < s1; sidx++) {
+                const uint64_t pk = slots[sidx];
+                const uint32_t h = cell_mark_bit((int)(pk & 0xffff), (int)((pk >> 16) & 0xffff),
+                                                 (int)((pk >> 32) & 0xffff));
+                if ((seen[h >> 5] >> (h & 31)) & 1u) fresh[atomicAdd(&n_fresh, 1)] = (uint16_t)sidx;
+            }
+            __syncthreads();
+            const int nf = n_fresh;
+            for (int x = tid; x < nf; x += kPlainThreads) stot[fresh[x]] = slot_total(fresh[x]);
+            __syncthreads();
+        }
         double ls = 0.0, lm = 0.0;
         for (int sidx = s0; sidx < s1; sidx++) {
-            double r = 0.0;
-            for (int d = 0; d < 8; d++) {
-                int64_t ts;
-                r += plain_rate(D, P, slots[sidx], d, ts);
-            }
+            const double r = stot[sidx];
             ls += r;
             lm = fmax(lm, r);
         }
@@ -2638,7 +2700,11 @@ __global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const i
             Rmax = fmax(Rmax, wmax[w]);
         }
         if (K == 0.0) break;
+        // nobody reads the last stage's marks or list any more: clear them
+        for (int w = tid; w < kMarkWords; w += kPlainThreads) marks[((st + 1) & 1) * kMarkWords + w] = 0u;
+        if (tid == 0) n_fresh = 0;
         if (wv == 0) {
+            uint32_t* mark = marks + (st & 1) * kMarkWords;
             // selection j in lane j: an atom, then its event or a null event
             int a = 0, e = -1;
             int64_t cs = -1, ct = -1;
@@ -2703,6 +2769,8 @@ __global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const i
                 if (Z >= 2 * D.L[2]) Z -= 2 * D.L[2];
                 slots[a] = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) | ((uint64_t)(Z >> 1) << 32) |
                            ((uint64_t)site_type(X, Y) << 48);
+                mark_cells_around(mark, D, i, jj, k);
+                mark_cells_around(mark, D, X >> 1, Y >> 1, Z >> 1);
             }
             const int n_upd = __popcll(__ballot(taken));
             const int n_o = __popcll(__ballot(taken && sp == kSpO));
@@ -2714,9 +2782,10 @@ __global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const i
                      x1, x2, x3);
             const double dt = -clock_ln(u53_hi(x2, x3)) / K;
             t = t + dt * (double)n_upd;
-            __threadfence();  // the hops are visible to every wave's rates of the next stage
         }
         stage++;
+        // the barrier's workgroup-scope fence makes the hops' HBM writes
+        // visible to every wave of this workgroup, the only readers
         __syncthreads();
     }
     if (tid == 0) {
@@ -2982,8 +3051,12 @@ int launch_atomic_hbm(const DevPtrs& P, const int32_t* d_ids, int n, uint32_t n_
                       void* stream)
 {
     if (n == 0) return 0;
-    hipLaunchKernelGGL(k_atomic_hbm, dim3(n), dim3(kPlainThreads), (size_t)8 * kMaxPlainSlots,
-                       (hipStream_t)stream, P, d_ids, n_frg, n_stages);
+    const size_t lds = (size_t)18 * kMaxPlainSlots + (size_t)8 * kMarkWords;
+    hipError_t e = hipFuncSetAttribute((const void*)k_atomic_hbm, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k_atomic_hbm, dim3(n), dim3(kPlainThreads), lds, (hipStream_t)stream, P, d_ids,
+                       n_frg, n_stages);
     return (int)hipGetLastError();
 }
 

@@ -243,6 +243,53 @@ def test_atomic_matches_oracle(n_frg, lds):
     assert lats[0].draws == 155 + 300 and lats[8].draws == 0 and lats[9].draws == 0
 
 
+def _random_plain_cases(seed, n):
+    """n seeded random plain lattices of 2-16 cells per axis with 1 to 4096
+    vacancies (from one vacancy to a third of the sites), H, field and
+    boundary planes on random axes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        L = tuple(int(x) for x in rng.integers(2, 17, size=3))
+        sites = 3 * L[0] * L[1] * L[2]
+        nv = int(min(4096, sites // 3, max(1, round(sites * 10 ** rng.uniform(-2.5, -0.4)))))
+        if i % 6 == 0:  # one in six past the LDS kernel's 512 vacancies
+            L = tuple(int(x) for x in rng.integers(12, 17, size=3))
+            sites = 3 * L[0] * L[1] * L[2]
+            nv = int(min(4096, sites // 3, rng.integers(513, 4097)))
+        nh = int(rng.integers(0, (sites - nv) // 4 + 1))
+        gb = int(rng.integers(2, 6)) if rng.random() < 0.4 else 0
+        out.append(Case(L, seed=int(rng.integers(0, 1 << 30)), lattice_id=i, nv=nv, nh=nh,
+                        T=float(rng.uniform(450, 800)), Ea_O=float(rng.uniform(0.5, 0.7)),
+                        Ea_H=float(rng.uniform(0.35, 0.55)), E_z=float(rng.choice([0.0, 1e8, -2e8])),
+                        gb_period=gb, gb_mask=int(rng.integers(1, 8)), gb_dE=0.07 if gb else 0.0))
+    return out
+
+
+@pytest.mark.parametrize("lds", [True, False])
+def test_atomic_random_configurations_match_oracle(lds):
+    """64 seeded random plain lattices (LDS and HBM kernels mixed, or all on
+    the HBM kernel), three calls with random selection counts and stage
+    counts, each against the oracle bit for bit."""
+    cases = _random_plain_cases(911, 64)
+    say("atom-selection random configurations", "lds" if lds else "hbm")
+    rng = np.random.default_rng(912)
+    lats = [c.oracle() for c in cases]
+    g = gpu_set(cases)
+    g.set_plain_lds(lds)
+    for call in range(3):
+        n_frg, n_st = int(rng.integers(1, 65)), int(rng.integers(20, 120))
+        for lat in lats:
+            lat.advance_atomic(n_frg, n_st)
+        g.advance_atomic(n_frg, n_st)
+        stats = g.read_stats()
+        for i, lat in enumerate(lats):
+            what = "member %d %s nv %d, call %d (n_frg %d)" % (i, cases[i].L, cases[i].nv, call, n_frg)
+            assert stats[i]["draws"] == lat.draws and stats[i]["t"] == lat.t, what
+            assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops], what
+            assert_same_state(g, i, lat, what)
+
+
 def test_atomic_rejects_what_it_cannot_run():
     from paper_2004_09081_amd import fkmc as F
     g = gpu_set(ATOMIC_CASES[:2])
