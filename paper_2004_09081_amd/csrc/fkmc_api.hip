@@ -1161,7 +1161,10 @@ fkmc_status fkmc_advance_atomic(fkmc_lattice* L, uint32_t n_frg, uint64_t n_stag
         const bool fits = L->n_vac[i] <= (uint64_t)kPlainLdsSlots && g.L[0] <= 1023 && g.L[1] <= 1023 &&
                           g.L[2] <= 512 && b <= 65536 - 256;
         if (fits && L->plain_lds) {
-            lds = std::max(lds, b);
+            // plus the slot totals, two cell-mark bitmaps and the refresh list
+            const int64_t nv = (int64_t)L->n_vac[i];
+            const int64_t slots = nv <= 64 ? 64 : (nv <= 128 ? 128 : (nv <= 256 ? 256 : 512));
+            lds = std::max(lds, b + 8 * slots + 8 * (int64_t)kAtomMarkWords + 2 * slots);
             L->desc[i].n_vac = (int32_t)L->n_vac[i];
             L->desc[i].resident = 1;
             in_lds.push_back((int32_t)i);

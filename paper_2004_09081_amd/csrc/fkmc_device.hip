@@ -1913,11 +1913,36 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
 // Slots are the vacancies in canonical order at the call start, following
 // their vacancies; the stage counter is the lattice's draw counter.  Runs
 // n_stages stages, fewer when no event is possible.
+// Hashed bit of cell (i, j, k) in a mark bitmap of 2^B bits.
+template <int B>
+__device__ __forceinline__ uint32_t cell_mark_bit(int i, int j, int k)
+{
+    return ((uint32_t)i * 0x9E3779B1u ^ (uint32_t)j * 0x85EBCA77u ^ (uint32_t)k * 0xC2B2AE3Du) >> (32 - B);
+}
+
+// Mark the cells that hold the neighbours of the site at doubled coordinates
+// (X, Y, Z): a neighbour differs by one in two of them, so along each axis
+// it lies in cell (X-1)/2 or (X+1)/2 (periodic), 8 cells in all.
+template <int B>
+__device__ __forceinline__ void mark_neighbour_cells(uint32_t* marks, int L0, int L1, int L2, int X, int Y,
+                                                     int Z)
+{
+    const int x0 = (X == 0 ? 2 * L0 - 1 : X - 1) >> 1, x1 = (X + 1 == 2 * L0 ? 0 : X + 1) >> 1;
+    const int y0 = (Y == 0 ? 2 * L1 - 1 : Y - 1) >> 1, y1 = (Y + 1 == 2 * L1 ? 0 : Y + 1) >> 1;
+    const int z0 = (Z == 0 ? 2 * L2 - 1 : Z - 1) >> 1, z1 = (Z + 1 == 2 * L2 ? 0 : Z + 1) >> 1;
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        const uint32_t h = cell_mark_bit<B>(c & 1 ? x1 : x0, c & 2 ? y1 : y0, c & 4 ? z1 : z0);
+        atomicOr(marks + (h >> 5), 1u << (h & 31));
+    }
+}
+
 template <int P>
 __device__ __forceinline__ void atomic_stages(const LatDesc& D, uint32_t* ps, uint32_t* vlist, int nv,
-                                              double* krate, unsigned char* kspec, const RateCtx& C,
-                                              int4* disp, LatState* St, uint32_t n_frg, uint64_t n_stages,
-                                              int lane)
+                                              double* krate, unsigned char* kspec, double* stot,
+                                              uint32_t* marks, uint16_t* fresh, const RateCtx& C,
+                                              int4* disp, LatState* St,
+                                              uint32_t n_frg, uint64_t n_stages, int lane)
 {
     const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
     const int64_t disp_off = D.disp_off;
@@ -1932,34 +1957,68 @@ __device__ __forceinline__ void atomic_stages(const LatDesc& D, uint32_t* ps, ui
     double t = St->t;
     uint64_t stage = St->draws;
     unsigned long long ho = 0, hh = 0;
+    // the 8 rates and the total of slot sidx (zero past the last vacancy)
+    auto slot_rates = [&](int sidx) {
+        const bool v = sidx < nv;
+        const uint32_t p = v ? vlist[sidx] : 0u;
+        double ri = 0.0;
+#pragma nounroll
+        for (int d = 0; d < 8; d++) {
+            double kd = 0.0;
+            int sp = kSpV;
+            if (v) {
+                uint32_t np;
+                int col;
+                kd = plain_rate_of(C, ps, plain_nb(C, p, d, np, col), col, sp);
+            }
+            krate[sidx * 8 + d] = kd;
+            kspec[sidx * 8 + d] = (unsigned char)sp;
+            ri += kd;
+        }
+        stot[sidx] = ri;
+    };
+#pragma nounroll
+    for (int q = 0; q < P; q++) slot_rates(lane * P + q);
+    for (int w = lane; w < 2 * kAtomMarkWords; w += 64) marks[w] = 0u;
+    wave_lds_order();
     for (uint64_t k = 0; k < n_stages; k++) {
-        // rates at the start of the stage (zero for slots past the last vacancy)
+        // rates at the start of the stage: new ones for the slots in cells
+        // the last stage marked
+        if (k > 0) {
+            // list them (ballot prefix), then recompute the list densely
+            const uint32_t* seen = marks + ((k + 1) & 1) * kAtomMarkWords;
+            int nf = 0;
+#pragma nounroll
+            for (int q = 0; q < P; q++) {
+                const int sidx = lane * P + q;
+                bool f = false;
+                if (sidx < nv) {
+                    const uint32_t p = vlist[sidx];
+                    const uint32_t h = cell_mark_bit<kAtomMarkBits>(
+                        (int)((p & 2047) >> 1), (int)(((p >> 11) & 2047) >> 1), (int)(p >> 23));
+                    f = (seen[h >> 5] >> (h & 31)) & 1u;
+                }
+                const uint64_t fm = __ballot(f);
+                if (f) fresh[nf + __popcll(fm & ((1ull << lane) - 1ull))] = (uint16_t)sidx;
+                nf += __popcll(fm);
+            }
+            wave_lds_order();
+#pragma nounroll
+            for (int x = lane; x < nf; x += 64) slot_rates(fresh[x]);
+            wave_lds_order();
+        }
         double lsum = 0.0, lmax = 0.0;
 #pragma nounroll
         for (int q = 0; q < P; q++) {
-            const int sidx = lane * P + q;
-            const bool v = sidx < nv;
-            const uint32_t p = v ? vlist[sidx] : 0u;
-            double ri = 0.0;
-#pragma nounroll
-            for (int d = 0; d < 8; d++) {
-                double kd = 0.0;
-                int sp = kSpV;
-                if (v) {
-                    uint32_t np;
-                    int col;
-                    kd = plain_rate_of(C, ps, plain_nb(C, p, d, np, col), col, sp);
-                }
-                krate[sidx * 8 + d] = kd;
-                kspec[sidx * 8 + d] = (unsigned char)sp;
-                ri += kd;
-            }
+            const double ri = stot[lane * P + q];
             lsum += ri;
             lmax = fmax(lmax, ri);
         }
         const double K = lane_value(wave_scan_dpp(lsum), 63);
         const double Rmax = lane_value(wave_max_dpp(lmax), 63);
         if (K == 0.0) break;
+        // the last stage's marks are read: clear them for the next
+        for (int w = lane; w < kAtomMarkWords; w += 64) marks[((k + 1) & 1) * kAtomMarkWords + w] = 0u;
         wave_lds_order();
         // selection j in lane j: an atom, then its event or a null event
         int a = 0, e = -1;
@@ -2000,7 +2059,13 @@ __device__ __forceinline__ void atomic_stages(const LatDesc& D, uint32_t* ps, ui
         if (taken) {
             pk_set(ps, cs, sp);
             pk_set(ps, ct, kSpV);
+            const uint32_t sx = vlist[a];
             vlist[a] = tx;
+            uint32_t* mark = marks + (k & 1) * kAtomMarkWords;
+            mark_neighbour_cells<kAtomMarkBits>(mark, L0, L1, L2, (int)(sx & 2047), (int)((sx >> 11) & 2047),
+                                                (int)(sx >> 22));
+            mark_neighbour_cells<kAtomMarkBits>(mark, L0, L1, L2, (int)(tx & 2047), (int)((tx >> 11) & 2047),
+                                                (int)(tx >> 22));
         }
         uint64_t tm = __ballot(taken);
         const int n_upd = __popcll(tm);
@@ -2053,6 +2118,9 @@ __global__ __launch_bounds__(256) void k_atomic(DevPtrs P, const int32_t* ids, u
     const int slots = D.n_vac <= 64 ? 64 : (D.n_vac <= 128 ? 128 : (D.n_vac <= 256 ? 256 : 512));
     double* krate = (double*)(vlist + ((D.n_vac + 3) & ~3));
     unsigned char* kspec = (unsigned char*)(krate + 8 * slots);
+    double* stot = (double*)(kspec + 8 * slots);
+    uint32_t* marks = (uint32_t*)(stot + slots);
+    uint16_t* fresh = (uint16_t*)(marks + 2 * kAtomMarkWords);
     if (threadIdx.x == 0) vlist_n = 0;
     if (threadIdx.x < 12) k12[threadIdx.x] = D.k12[threadIdx.x];
     __syncthreads();
@@ -2062,13 +2130,17 @@ __global__ __launch_bounds__(256) void k_atomic(DevPtrs P, const int32_t* ids, u
     if (threadIdx.x < 64) {
         const RateCtx C = {D.L[0], D.L[1], D.L[2], D.gb_period, D.gb_mask, k12};
         if (slots == 64)
-            atomic_stages<1>(D, pslab, vlist, nv, krate, kspec, C, P.disp, St, n_frg, n_stages, lane);
+            atomic_stages<1>(D, pslab, vlist, nv, krate, kspec, stot, marks, fresh, C, P.disp, St, n_frg, n_stages,
+                             lane);
         else if (slots == 128)
-            atomic_stages<2>(D, pslab, vlist, nv, krate, kspec, C, P.disp, St, n_frg, n_stages, lane);
+            atomic_stages<2>(D, pslab, vlist, nv, krate, kspec, stot, marks, fresh, C, P.disp, St, n_frg, n_stages,
+                             lane);
         else if (slots == 256)
-            atomic_stages<4>(D, pslab, vlist, nv, krate, kspec, C, P.disp, St, n_frg, n_stages, lane);
+            atomic_stages<4>(D, pslab, vlist, nv, krate, kspec, stot, marks, fresh, C, P.disp, St, n_frg, n_stages,
+                             lane);
         else
-            atomic_stages<8>(D, pslab, vlist, nv, krate, kspec, C, P.disp, St, n_frg, n_stages, lane);
+            atomic_stages<8>(D, pslab, vlist, nv, krate, kspec, stot, marks, fresh, C, P.disp, St, n_frg, n_stages,
+                             lane);
     }
     __syncthreads();
     plain_pack_store(D, occ_lat, pslab);
@@ -2585,33 +2657,6 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
 constexpr int kMarkBits = 14;
 constexpr int kMarkWords = 1 << (kMarkBits - 5);
 static_assert(kMaxPlainSlots <= 65536, "slot indices of the refresh list are 16-bit");
-
-__device__ __forceinline__ uint32_t cell_mark_bit(int i, int j, int k)
-{
-    return ((uint32_t)i * 0x9E3779B1u ^ (uint32_t)j * 0x85EBCA77u ^ (uint32_t)k * 0xC2B2AE3Du) >>
-           (32 - kMarkBits);
-}
-
-// Mark the 27 cells around cell (i, j, k), periodic: every site next to a
-// site of that cell lies in one of them.
-__device__ __forceinline__ void mark_cells_around(uint32_t* marks, const LatDesc& D, int i, int j, int k)
-{
-    for (int dz = -1; dz <= 1; dz++) {
-        int c = k + dz;
-        c = c < 0 ? c + D.L[2] : (c >= D.L[2] ? c - D.L[2] : c);
-        for (int dy = -1; dy <= 1; dy++) {
-            int b = j + dy;
-            b = b < 0 ? b + D.L[1] : (b >= D.L[1] ? b - D.L[1] : b);
-            for (int dx = -1; dx <= 1; dx++) {
-                int a = i + dx;
-                a = a < 0 ? a + D.L[0] : (a >= D.L[0] ? a - D.L[0] : a);
-                const uint32_t h = cell_mark_bit(a, b, c);
-                atomicOr(marks + (h >> 5), 1u << (h & 31));
-            }
-        }
-    }
-}
-
 // Atom-selection stages (Sec. "Atomic-based fragment kMC method", Eqs. AtomP
 // and TimeStepFrg) on a plain lattice whose occupancy stays in HBM: one
 // workgroup per lattice, its vacancy slots and their totals R_I in LDS, the
@@ -2672,8 +2717,8 @@ __global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const i
             const uint32_t* seen = marks + ((st + 1) & 1) * kMarkWords;
             for (int sidx = s0; sidx < s1; sidx++) {
                 const uint64_t pk = slots[sidx];
-                const uint32_t h = cell_mark_bit((int)(pk & 0xffff), (int)((pk >> 16) & 0xffff),
-                                                 (int)((pk >> 32) & 0xffff));
+                const uint32_t h = cell_mark_bit<kMarkBits>((int)(pk & 0xffff), (int)((pk >> 16) & 0xffff),
+                                                            (int)((pk >> 32) & 0xffff));
                 if ((seen[h >> 5] >> (h & 31)) & 1u) fresh[atomicAdd(&n_fresh, 1)] = (uint16_t)sidx;
             }
             __syncthreads();
@@ -2769,8 +2814,9 @@ __global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const i
                 if (Z >= 2 * D.L[2]) Z -= 2 * D.L[2];
                 slots[a] = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) | ((uint64_t)(Z >> 1) << 32) |
                            ((uint64_t)site_type(X, Y) << 48);
-                mark_cells_around(mark, D, i, jj, k);
-                mark_cells_around(mark, D, X >> 1, Y >> 1, Z >> 1);
+                mark_neighbour_cells<kMarkBits>(mark, D.L[0], D.L[1], D.L[2], 2 * i + (tp != 0),
+                                                2 * jj + (tp != 1), 2 * k + (tp != 2));
+                mark_neighbour_cells<kMarkBits>(mark, D.L[0], D.L[1], D.L[2], X, Y, Z);
             }
             const int n_upd = __popcll(__ballot(taken));
             const int n_o = __popcll(__ballot(taken && sp == kSpO));

@@ -26,7 +26,9 @@ constexpr int kMaxWidth = 100;      // largest sub-block edge (cells)
 constexpr int kMaxLdsPerBlock = 65536;  // dynamic LDS of one phase workgroup
 constexpr int kMaxSlots = 128;      // vacancies per fragment-mode footprint
 constexpr int kMaxPlainSlots = 4096;  // vacancies per plain-mode lattice
-constexpr int kPlainLdsSlots = 512;   // vacancies per plain lattice held in LDS
+constexpr int kPlainLdsSlots = 512;
+constexpr int kAtomMarkBits = 13;     // hashed cell bitmap of the LDS atom-selection kernel
+constexpr int kAtomMarkWords = 1 << (kAtomMarkBits - 5);   // vacancies per plain lattice held in LDS
 constexpr int kHopBuckets = 256;    // spread of the per-lattice hop counters
 constexpr int kStatFields = 10;     // count, r(3), rr(6)
 
