@@ -288,10 +288,12 @@ def atomic_leg(F, specs, n_frg, stages):
 
 
 def atomic_hbm_leg(F, specs, n_frg, stages):
-    """The atom-selection scheme on the ensemble lattices past the LDS
-    kernel (513 to 4096 vacancies, occupancy in HBM), all in one launch,
-    against plain BKL (also HBM-resident, one workgroup per lattice) making
-    the same mean number of hops from the same initial states."""
+    """The atom-selection scheme on the ensemble lattices of at most 4096
+    vacancies that the persistent kernel does not hold in LDS (more than
+    512 vacancies, or an occupancy too large for its LDS share), all in one
+    call, against plain BKL making the same mean number of hops from the
+    same initial states.  Those that fit the LDS atom-selection kernel's
+    own limit run there, the rest keep their occupancy in HBM."""
     import torch
     from paper_2004_09081_amd.autotune import plain_if_sparse
     sel = []
@@ -326,9 +328,10 @@ def atomic_hbm_leg(F, specs, n_frg, stages):
            "us_per_stage": 1e3 * max(x["busy_ms"] for x in st_a) / stages,
            "bkl_same_lattices": {"value": float(hops_b.sum() / t_b), "unit": "hops/s",
                                  "hops_per_lattice": target},
-           "sample": "%d of %d ensemble lattices (513 to 4096 vacancies, unfragmented), %d stages of "
-                     "%d selections; BKL the same mean hop count" % (len(sel), len(specs), stages, n_frg)}
-    log("atom selection on HBM lattices (N_frg %d): %.4g hops/s on %d lattices, %.2f hops per stage, "
+           "sample": "%d of %d ensemble lattices (at most 4096 vacancies, not held in LDS by the "
+                     "persistent kernel; unfragmented), %d stages of %d selections; BKL the same mean "
+                     "hop count" % (len(sel), len(specs), stages, n_frg)}
+    log("atom selection on lattices past the persistent kernel's LDS (N_frg %d): %.4g hops/s on %d lattices, %.2f hops per stage, "
         "%.1f us per stage; BKL on the same lattices %.4g hops/s"
         % (n_frg, rep["value"], len(sel), rep["hops_per_stage"], rep["us_per_stage"],
            rep["bkl_same_lattices"]["value"]))
