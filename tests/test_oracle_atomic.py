@@ -122,3 +122,31 @@ def test_crowded_stages_touch_disjoint_sites():
         assert np.bincount(lat.occ, minlength=3).tolist() == counts0.tolist()
         assert lat.disp.sum(axis=0).tolist() == [0, 0, 0]
     assert total > 300  # several hops per stage on average
+
+
+@pytest.mark.parametrize("nv", [0, 24])
+def test_no_possible_event_takes_no_stage(nv):
+    """With no vacancy, or with every anion site of a 2x2x2 lattice vacant,
+    K = 0: no stage runs, so the stage counter and the clock stay at zero
+    and nothing moves."""
+    lat = O.Lattice(O.Geometry(L=(2, 2, 2), seed=5, lattice_id=1))
+    lat.init_random(nv, 0)
+    lat.set_rates(O.RateParams(nu=1e13, T=600.0, Ea_O=0.6))
+    occ0 = lat.occ.copy()
+    h = lat.advance_atomic(8, 10)
+    assert sum(h) == 0 and lat.draws == 0 and lat.t == 0.0
+    assert np.array_equal(lat.occ, occ0)
+
+
+def test_more_selections_than_vacancies():
+    """64 selections per stage on 3 vacancies: at most 3 hops a stage (one
+    per vacancy), and a stage with a taken hop always moves the clock."""
+    lat = O.Lattice(O.Geometry(L=(4, 4, 4), seed=8, lattice_id=2))
+    lat.init_random(3, 20)
+    lat.set_rates(O.RateParams(nu=1e13, T=650.0, Ea_O=0.6, Ea_H=0.45))
+    for _ in range(200):
+        t0 = lat.t
+        h = lat.advance_atomic(64, 1)
+        n = int(sum(h))
+        assert n <= 3
+        assert (lat.t > t0) == (n > 0)
