@@ -39,7 +39,7 @@ def plain_if_sparse(spec) -> int:
     return 0 if spec.n_vac <= PLAIN_LDS_VACANCIES and fits else 16
 
 
-DEFAULT_CANDIDATES = (4, 6, 8, 10, 12, 16, 20, 24, whole_if_sparse, plain_if_sparse)
+DEFAULT_CANDIDATES = (4, 6, 8, 10, 12, 14, 16, 18, 20, 24, whole_if_sparse, plain_if_sparse)
 
 
 def trial(specs, F, cycles: int, waves: int, plain_hops: int = 20_000):
