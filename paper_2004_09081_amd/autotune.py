@@ -72,7 +72,7 @@ def trial(specs, F, cycles: int, waves: int, plain_hops: int = 20_000):
     return ms, hops
 
 
-def tune(make_specs, hop_target: int, candidates=DEFAULT_CANDIDATES, cycles: int = 64,
+def tune(make_specs, hop_target: int, candidates=DEFAULT_CANDIDATES, cycles: int = 128,
          waves: int = 4, log=None):
     """make_specs(frag) -> list of LatticeSpec with fragment edge `frag`
     (cells).  A candidate is an edge, or a function of a lattice's spec
