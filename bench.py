@@ -37,9 +37,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "hops/s on 1 MI355X, batched fragment vs plain kMC; surrogate log10 D MAE"
 HBM_PEAK_GBS = 8000.0
-# Per hop: two occupancy bytes written, and the displacement records (int32x4)
-# of the two particles that swap read and written.
-HOP_BYTES = 2 + 4 * 16
+# Algorithmic bytes of one hop, what the method itself must move: the 9
+# occupancy bytes around the moved vacancy read (its site and 8 neighbours),
+# 2 written, and the int32x3 displacements of the two particles that swap
+# read and written (2 x 12 B each way).
+ALG_HOP_BYTES = 9 + 2 + 2 * 2 * 12
+# Bytes a hop moves in this implementation's records: two occupancy bytes
+# written, and the int32x4 displacement records of both particles read and
+# written.
+IMPL_HOP_BYTES = 2 + 4 * 16
 # Sources (kernels and their launch set-up) whose change invalidates stored
 # HBM traffic counts.
 # The counter traffic belongs to these sources: the kernels, the host plan,
@@ -124,47 +130,147 @@ def hops_of(stats) -> np.ndarray:
     return np.array([int(st["hops"][0]) + int(st["hops"][1]) for st in stats], dtype=np.int64)
 
 
-def roofline_obj(kernel, bytes_per_launch, avg_ms, launches, workload, note):
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+def roofline_obj(kernel, hops_per_launch, staging_per_launch, avg_ms, launches, workload, note):
+    """Roofline of one kernel.  achieved/frac: the method's algorithmic bytes
+    (ALG_HOP_BYTES per hop) per launch over the mean launch time.  The
+    staging figures count what this design moves on purpose besides: each
+    streamed lattice's footprints once per phase (HBM -> LDS), a resident
+    lattice's occupancy in and out once per launch, and the displacement
+    records of its hops."""
+    sec = avg_ms * 1e-3
+    alg = hops_per_launch * ALG_HOP_BYTES
+    achieved = alg / sec / 1e9 if avg_ms > 0 else 0.0
+    stg = staging_per_launch + hops_per_launch * IMPL_HOP_BYTES
+    st_gbs = stg / sec / 1e9 if avg_ms > 0 else 0.0
+    traffic = stored_traffic(kernel, workload)
     return {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 6),
-            "traffic": stored_traffic(kernel, workload),
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": traffic,
             "kernel": kernel, "avg_launch_ms": avg_ms, "launches_timed": launches,
-            "algorithmic_bytes_per_launch": int(bytes_per_launch), "note": note}
+            "hops_per_launch": float(hops_per_launch),
+            "algorithmic_bytes_per_hop": ALG_HOP_BYTES,
+            "algorithmic_bytes_per_launch": int(alg),
+            "staging": {"bytes_per_launch": int(stg), "achieved": round(st_gbs, 3),
+                        "frac": round(st_gbs / HBM_PEAK_GBS, 6)},
+            "traffic_frac": (round(traffic / sec / 1e9 / HBM_PEAK_GBS, 6)
+                             if traffic and avg_ms > 0 else None),
+            "note": note}
 
 
-def cpu_baseline(specs, budget_s: float, hop_target: int):
-    """The oracle, unchanged, on the first lattices of the workload (one
-    host thread), cycle by cycle until each reaches its hop target or the
-    time budget runs out."""
+def _oracle_lattice(sp):
     from oracle import oracle as O
-    done_hops = 0
-    t_used = 0.0
-    n_lat = 0
-    partial = False
-    for sp in specs:
-        g = O.Geometry(L=sp.L, frag=sp.frag, a_angstrom=sp.a, seed=sp.seed,
-                       lattice_id=sp.lattice_id, gb_period_cells=sp.gb_period,
-                       gb_axes_mask=sp.gb_mask)
-        lat = O.Lattice(g)
-        lat.init_random(sp.n_vac, sp.n_h)
-        lat.set_rates(O.RateParams(T=sp.T, Ea_O=sp.Ea_O, Ea_H=sp.Ea_H, E_z=sp.E_z, q=sp.q,
-                                   gb_period_cells=sp.gb_period, gb_axes_mask=sp.gb_mask,
-                                   gb_dE=sp.gb_dE))
-        n_lat += 1
-        h0 = 0
-        t0 = time.perf_counter()
-        while h0 < hop_target:
+    g = O.Geometry(L=sp.L, frag=sp.frag, a_angstrom=sp.a, seed=sp.seed, lattice_id=sp.lattice_id,
+                   gb_period_cells=sp.gb_period, gb_axes_mask=sp.gb_mask)
+    lat = O.Lattice(g)
+    lat.init_random(sp.n_vac, sp.n_h)
+    lat.set_rates(O.RateParams(T=sp.T, Ea_O=sp.Ea_O, Ea_H=sp.Ea_H, E_z=sp.E_z, q=sp.q,
+                               gb_period_cells=sp.gb_period, gb_axes_mask=sp.gb_mask,
+                               gb_dE=sp.gb_dE))
+    return lat
+
+
+def _oracle_run(sp, hop_target: int, budget_s: float):
+    """The oracle, unchanged, on one lattice in the decomposition the GPU
+    ran (plain BKL for edge 0, else fragment cycles), until the hop target
+    or the time budget: (hops, seconds, finished)."""
+    lat = _oracle_lattice(sp)
+    h = 0
+    t0 = time.perf_counter()
+    while h < hop_target:
+        if sp.frag[0] == 0:
+            lat.advance_plain(min(20_000, hop_target - h))
+        else:
             lat.advance(sp.t_sync, max_cycles=1)
-            h0 = int(lat.hops.sum())
-            if t_used + time.perf_counter() - t0 > budget_s:
-                partial = True
-                break
-        t_used += time.perf_counter() - t0
-        done_hops += h0
-        if t_used > budget_s:
+        h = int(lat.hops.sum())
+        if time.perf_counter() - t0 > budget_s:
+            return h, time.perf_counter() - t0, False
+    return h, time.perf_counter() - t0, True
+
+
+def _oracle_worker(args):
+    sp, hop_target, budget_s = args
+    return _oracle_run(sp, hop_target, budget_s)
+
+
+def cpu_model() -> str:
+    """The host CPU's model name and its online and usable CPU counts."""
+    name = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    if not name:
+        import platform
+        name = platform.processor() or "unknown"
+    return "%s (%d CPUs online, %d usable by this process)" % (name, os.cpu_count() or 0,
+                                                               len(os.sched_getaffinity(0)))
+
+
+def cpu_baseline(specs, budget_s: float, hop_target: int, workers: int):
+    """The oracle as it stands on the workload's first lattices: on one host
+    thread, lattice after lattice until the budget runs out; then on
+    `workers` processes at once, one lattice each (independent lattices, so
+    the all-core rate is the sum of the per-process rates)."""
+    import multiprocessing as mp
+    done, used, n_lat, partial = 0, 0.0, 0, False
+    for sp in specs:
+        h, t, fin = _oracle_run(sp, hop_target, budget_s - used)
+        done += h
+        used += t
+        n_lat += 1
+        if not fin or used >= budget_s:
+            partial = not fin
             break
-    return done_hops, t_used, n_lat, partial
+    one = {"value": done / used, "hops": done, "seconds": used, "lattices": n_lat, "partial": partial}
+    jobs = [(sp, hop_target, budget_s) for sp in specs[:workers]]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(jobs)) as pool:
+        res = pool.map(_oracle_worker, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    allc = {"value": float(sum(h / t for h, t, _ in res)), "processes": len(jobs),
+            "hops": int(sum(h for h, _, _ in res)), "wall_s": wall,
+            "finished": int(sum(1 for _, _, f in res if f))}
+    return one, allc
+
+
+def cpu_leg(args):
+    """The cpu_baseline record of the workload bench.py times, from the
+    oracle on the host's cores (cfg4: the stored autotuner decomposition when
+    it matches, else 8-cell fragments)."""
+    from paper_2004_09081_amd import workloads as W
+    if args.workload == "cfg4":
+        from paper_2004_09081_amd import autotune
+        specs = W.cfg4(n=args.lattices, hops=args.hops, frag=8)
+        edges = autotune.load_edges(autotune.ENSEMBLE_EDGES, specs)
+        if edges is not None and args.frag in ("auto", "tune"):
+            for sp, e in zip(specs, edges):
+                sp.frag = (int(e),) * 3
+        elif args.frag not in ("auto", "tune"):
+            specs = W.cfg4(n=args.lattices, hops=args.hops,
+                           frag=(lambda L: (L + 1) // 2) if args.frag == "half" else int(args.frag))
+        hop_target = args.hops
+    elif args.workload == "cfg3":
+        specs, hop_target = [W.cfg3()], 10**18
+    else:
+        specs, hop_target = [W.cfg2(T) for T in W.CFG2_TEMPERATURES], 10_000_000
+    workers = max(1, min(args.cpu_workers, len(os.sched_getaffinity(0))))
+    one, allc = cpu_baseline(specs, args.cpu_budget, hop_target, workers)
+    model = cpu_model()
+    log("cpu oracle (%s): %.4g hops/s on 1 thread, %.4g hops/s on %d processes"
+        % (model, one["value"], allc["value"], allc["processes"]))
+    return {"value": one["value"], "unit": "hops/s", "cores": 1, "kind": "oracle", "cpu": model,
+            "sample": "first %d lattice(s) of the workload in the decomposition the GPU runs (plain "
+                      "BKL for unfragmented ones), %d hops in %.1f s on one thread%s"
+                      % (one["lattices"], one["hops"], one["seconds"],
+                         " (last one partial)" if one["partial"] else ""),
+            "all_cores": {"value": allc["value"], "unit": "hops/s", "cores": allc["processes"],
+                          "sample": "first %d lattices, one process each, up to %.0f s each (%d "
+                                    "reached the hop target); rate = sum of per-process rates"
+                                    % (allc["processes"], args.cpu_budget, allc["finished"])}}
 
 
 def sweep_leg(F, W, cycles: int, warm: int):
@@ -189,15 +295,16 @@ def sweep_leg(F, W, cycles: int, warm: int):
     del S
     torch.cuda.empty_cache()
     fp = footprint_bytes(spec)
-    bpl = fp / 8.0 + hops * HOP_BYTES / (8.0 * cycles)
-    rf = roofline_obj("k_phase", bpl, avg_ms, launches, "cfg3",
-                      "fragment sweep: per launch, one colour's footprints (sub-block plus three "
-                      "+faces) read HBM->LDS, plus per-hop occupancy and displacement updates")
+    rf = roofline_obj("k_phase", hops / launches, fp / 8.0, avg_ms, launches, "cfg3",
+                      "fragment sweep, one colour of every fragment per launch; staging = that "
+                      "colour's footprints (sub-block plus three +faces) read HBM->LDS, written back")
     rf["hops_per_s"] = hops / (launches * avg_ms * 1e-3) if avg_ms > 0 else 0.0
     rf["workload"] = ("600^3 cells (6.48e8 sites), 0.1%% V, 450 K, E_z 1e7 V/m, GB z-planes every "
                       "50 cells +0.3 eV, 16^3-cell fragments, %d cycles" % cycles)
-    log("sweep: k_phase %.4f ms avg over %d launches, %.0f B/launch -> %.1f GB/s (%.2f%% of peak), "
-        "%.4g hops/s" % (avg_ms, launches, bpl, rf["achieved"], 100 * rf["frac"], rf["hops_per_s"]))
+    log("sweep: k_phase %.4f ms avg over %d launches, %.0f hops/launch -> %.1f GB/s algorithmic "
+        "(%.3f%% of peak), staging %.1f GB/s (%.2f%%), %.4g hops/s"
+        % (avg_ms, launches, hops / launches, rf["achieved"], 100 * rf["frac"],
+           rf["staging"]["achieved"], 100 * rf["staging"]["frac"], rf["hops_per_s"]))
     return rf
 
 
@@ -353,12 +460,18 @@ def main():
                     help="lattices run one per launch for the comparison legs (0: skip)")
     ap.add_argument("--plain-hops", type=int, default=20_000,
                     help="hops per lattice of the unfragmented one-per-launch leg")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="processes of the all-core oracle leg (capped by the host's CPUs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-cycles", type=int, default=4,
                     help="timed cycles of the 600^3 sweep leg (0: skip)")
     ap.add_argument("--frag", default="auto",
-                    help="cfg4 fragment edge: cells, 'half' (ceil(L/2)) or 'auto' (autotuned per lattice)")
+                    help="cfg4 fragment edge: cells, 'half' (ceil(L/2)), 'auto' (the stored autotuner "
+                         "edges when they match the ensemble, else tuned now) or 'tune' (tuned now)")
+    ap.add_argument("--tune-repeats", type=int, default=1,
+                    help="autotuner trials per candidate (median per lattice)")
+    ap.add_argument("--save-edges", default="", help="write the tuned per-lattice edges here")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup of the persistent kernel")
     ap.add_argument("--atomic-stages", type=int, default=20000,
                     help="stages of the atom-selection leg (0: skip)")
@@ -379,6 +492,12 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    # The CPU oracle leg runs first, before this process touches the GPU, so
+    # that its worker processes start from a process without GPU state.
+    cpu_rep = None
+    if not args.no_cpu_baseline and not args.calibrate_copy_mib:
+        cpu_rep = cpu_leg(args)
+
     import torch
     if args.calibrate_copy_mib:
         n = args.calibrate_copy_mib << 20
@@ -396,17 +515,28 @@ def main():
     torch.cuda.set_device(0)
     F.lib()
 
+    decomposition = None
     if args.workload == "cfg4":
         hop_target = args.hops
-        if args.frag == "auto":
+        if args.frag in ("auto", "tune"):
             from paper_2004_09081_amd import autotune
-            t_tune = time.perf_counter()
-            best, tune_report = autotune.tune(lambda fr: W.cfg4(n=args.lattices, hops=args.hops, frag=fr),
-                                              hop_target, waves=args.waves or 4, log=log)
             specs = W.cfg4(n=args.lattices, hops=args.hops, frag=8)
+            best = autotune.load_edges(autotune.ENSEMBLE_EDGES, specs) if args.frag == "auto" else None
+            if best is not None:
+                decomposition = "autotuner edges stored with the package (digest %s)" % autotune.specs_digest(specs)
+                log("decomposition: stored autotuner edges %s" % dict(zip(*[x.tolist() for x in np.unique(best, return_counts=True)])))
+            else:
+                t_tune = time.perf_counter()
+                best, tune_report = autotune.tune(lambda fr: W.cfg4(n=args.lattices, hops=args.hops, frag=fr),
+                                                  hop_target, waves=args.waves or 4, log=log,
+                                                  repeats=args.tune_repeats)
+                log("autotune %.1f s: %s" % (time.perf_counter() - t_tune, tune_report["histogram"]))
+                decomposition = "autotuned in this run (%d trial(s) per candidate)" % args.tune_repeats
+                if args.save_edges:
+                    autotune.save_edges(args.save_edges, specs, best, tune_report)
+                    log("edges saved to %s" % args.save_edges)
             for i, sp in enumerate(specs):
                 sp.frag = (int(best[i]),) * 3
-            log("autotune %.1f s: %s" % (time.perf_counter() - t_tune, tune_report["histogram"]))
         else:
             fr = (lambda L: (L + 1) // 2) if args.frag == "half" else int(args.frag)
             specs = W.cfg4(n=args.lattices, hops=args.hops, frag=fr)
@@ -451,6 +581,7 @@ def main():
     # schedule: one launch per step; lockstep: one per phase).
     S.set_timing(True)
     ev_ms, ev_n = 0.0, 0
+    step_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -458,8 +589,10 @@ def main():
         a, n = S.phase_timing()
         ev_ms += a * n
         ev_n += n
+        step_ms.append(round(a * n, 2))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log("timed steps, device ms each: %s" % step_ms)
     S.set_timing(False)
     stats = S.read_stats()
     hops_each = hops_of(stats) - h_before
@@ -488,18 +621,18 @@ def main():
         # A lattice held in LDS moves its occupancy HBM->LDS->HBM once per
         # launch; any other lattice reads its footprints every cycle.
         sweep_b = float(np.where(res, 2.0 * sites * args.steps, cyc_each * fp).sum())
-        bpl = (sweep_b + hops * HOP_BYTES) / max(ev_n, 1)
         roofline = roofline_obj(
-            "k_batch", bpl, avg_ms, ev_n, "cfg4",
+            "k_batch", hops / max(ev_n, 1), sweep_b / max(ev_n, 1), avg_ms, ev_n, "cfg4",
             "persistent kernel, one workgroup per lattice; the launch lasts as long as the "
             "slowest lattice's serial BKL chain, so it is latency-bound, not HBM-bound: "
             "%d of %d lattices held in LDS" % (int(res.sum()), len(specs)))
     else:
-        bpl = (float((cyc_each * fp).sum()) + hops * HOP_BYTES) / max(ev_n, 1)
-        roofline = roofline_obj("k_phase", bpl, avg_ms, ev_n, args.workload,
+        roofline = roofline_obj("k_phase", hops / max(ev_n, 1), float((cyc_each * fp).sum()) / max(ev_n, 1),
+                                avg_ms, ev_n, args.workload,
                                 "lockstep phase kernel, one colour of every fragment per launch")
-    log("%s: %.4f ms avg over %d launches, %.0f B/launch -> %.3f GB/s" % (
-        roofline["kernel"], avg_ms, ev_n, bpl, roofline["achieved"]))
+    log("%s: %.4f ms avg over %d launches, %.4g hops/launch -> %.3f GB/s algorithmic, %.3f GB/s staging" % (
+        roofline["kernel"], avg_ms, ev_n, roofline["hops_per_launch"], roofline["achieved"],
+        roofline["staging"]["achieved"]))
 
     out = {"metric": METRIC, "value": value, "unit": "hops/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
@@ -508,7 +641,9 @@ def main():
            "config": {"workload": desc, "lattices": len(specs),
                       "fragment_edges": ({int(k): int(v) for k, v in zip(*np.unique([sp.frag[0] for sp in specs], return_counts=True))}),
                       "sites": int(sum(s.n_sites for s in specs)),
+                      "decomposition": decomposition,
                       "hops_timed": hops},
+           "step_device_ms": step_ms,
            "roofline": roofline}
     S.close()
     del S
@@ -559,13 +694,8 @@ def main():
             "surrogate+fallback %.2f s" % (rep["mae_log10D"], rep["served_fraction"],
                                            rep["time_kmc_only_s"], rep["time_surrogate_with_fallback_s"]))
 
-    if not args.no_cpu_baseline:
-        hops_c, tc, nl, partial = cpu_baseline(specs, args.cpu_budget, hop_target or 10**18)
-        out["cpu_baseline"] = {"value": hops_c / tc, "unit": "hops/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": "first %d lattice(s) of the workload, %d hops in %.1f s%s"
-                                         % (nl, hops_c, tc, " (last one partial)" if partial else "")}
-        log("cpu oracle: %.4g hops/s" % (hops_c / tc))
+    if cpu_rep is not None:
+        out["cpu_baseline"] = cpu_rep
     print(json.dumps(out), flush=True)
 
 

@@ -109,7 +109,11 @@ typedef struct {
 typedef struct {
     void* occ;   /* int8 occupancy, library storage order (not canonical) */
     void* disp;  /* int32x4 per site (x, y, z, unused), library order */
-    void* work;  /* descriptors, counters, tables */
+    void* work;  /* descriptors, counters, tables, and a staging slice for the
+                    canonical-order transfers of fkmc_set_occupancy,
+                    fkmc_read_state and fkmc_restore (up to 2^19 sites per
+                    chunk, 13 bytes per site): the library allocates no
+                    device memory of its own */
     size_t bytes[3];
 } fkmc_buffers;
 
@@ -159,8 +163,10 @@ uint32_t fkmc_count(const fkmc_lattice* lat);
 fkmc_status fkmc_init_random(fkmc_lattice* lat, const uint64_t* n_vac, const uint64_t* n_h);
 
 /* Copy occupancy (canonical order, n bytes = 3 L0 L1 L2) into lattice i and
- * zero its displacements, clock and counters.  Values must be 0, 1 or 2.
- * Invalidates the rate tables. */
+ * zero its displacements, clock and counters.  Values must be 0, 1 or 2
+ * (checked on the host before any device work).  The data pass through the
+ * work buffer's staging slice in chunks of at most 2^19 sites.  Invalidates
+ * the rate tables. */
 fkmc_status fkmc_set_occupancy(fkmc_lattice* lat, uint32_t i, const int8_t* host, size_t n);
 
 /* Build and quantise the 12-entry rate table of every lattice from params[i]
@@ -288,7 +294,8 @@ fkmc_status fkmc_run_phase(fkmc_lattice* lat, const double* t_sync, int32_t colo
 fkmc_status fkmc_sync(fkmc_lattice* lat);
 
 /* Occupancy (n bytes) and displacements (3n int32) of lattice i in canonical
- * order; synchronises.  disp may be NULL. */
+ * order; synchronises.  disp may be NULL.  The data pass through the work
+ * buffer's staging slice in chunks of at most 2^19 sites. */
 fkmc_status fkmc_read_state(fkmc_lattice* lat, uint32_t i, int8_t* occ, int32_t* disp, size_t n);
 
 /* Statistics of every lattice (out[n]); synchronises. */

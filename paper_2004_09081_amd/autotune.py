@@ -16,7 +16,17 @@ ensemble is the slowest lattice, so the choice is made lattice by lattice.
 """
 from __future__ import annotations
 
+import hashlib
+import json
+import os
+
 import numpy as np
+
+# Per-lattice fragment edges chosen by tune() for the 512-lattice ensemble
+# (seed 0xC4), stored so that runs of that ensemble simulate the same
+# decomposition (the edge is part of the dynamics) without re-tuning.
+ENSEMBLE_EDGES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned",
+                              "ensemble_512_edges.json")
 
 PLAIN_LDS_VACANCIES = 512
 PLAIN_LDS_BYTES = 62_000
@@ -40,6 +50,36 @@ def plain_if_sparse(spec) -> int:
 
 
 DEFAULT_CANDIDATES = (4, 6, 8, 10, 12, 14, 16, 18, 20, 24, whole_if_sparse, plain_if_sparse)
+
+
+def specs_digest(specs) -> str:
+    """Digest of what identifies an ensemble's lattices (sizes, keys,
+    compositions, temperatures, fields, windows), whatever their edges."""
+    h = hashlib.sha256()
+    for sp in specs:
+        h.update(repr((tuple(sp.L), sp.seed, sp.lattice_id, sp.n_vac, sp.n_h, round(sp.T, 9),
+                       round(sp.E_z, 3), sp.Ea_O, sp.Ea_H, float.hex(float(sp.t_sync)))).encode())
+    return h.hexdigest()[:16]
+
+
+def save_edges(path: str, specs, edges, report=None) -> None:
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump({"lattices": len(specs), "digest": specs_digest(specs),
+                   "edges": [int(e) for e in edges],
+                   "histogram": {int(k): int(v) for k, v in zip(*np.unique(edges, return_counts=True))},
+                   "report": report or {}}, f, indent=0)
+
+
+def load_edges(path: str, specs):
+    """Stored per-lattice edges for exactly these lattices, else None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("lattices") != len(specs) or d.get("digest") != specs_digest(specs):
+        return None
+    return np.array(d["edges"], dtype=np.int64)
 
 
 def trial(specs, F, cycles: int, waves: int, plain_hops: int = 20_000):
@@ -73,11 +113,13 @@ def trial(specs, F, cycles: int, waves: int, plain_hops: int = 20_000):
 
 
 def tune(make_specs, hop_target: int, candidates=DEFAULT_CANDIDATES, cycles: int = 128,
-         waves: int = 4, log=None):
+         waves: int = 4, log=None, repeats: int = 1):
     """make_specs(frag) -> list of LatticeSpec with fragment edge `frag`
     (cells).  A candidate is an edge, or a function of a lattice's spec
-    giving its edge.  Returns (per-lattice edge, report); the edge is the
-    one the lattice ran with in its best trial."""
+    giving its edge.  Each candidate's trial runs `repeats` times and a
+    lattice's prediction is the median, which steadies the choice against
+    timing noise.  Returns (per-lattice edge, report); the edge is the one
+    the lattice ran with in its best trial."""
     from paper_2004_09081_amd import fkmc as F
     base = make_specs(8)
     n = len(base)
@@ -94,13 +136,16 @@ def tune(make_specs, hop_target: int, candidates=DEFAULT_CANDIDATES, cycles: int
             specs = make_specs(c)
         used = np.array([sp.frag[0] for sp in specs], dtype=np.int64)
         try:
-            ms, hops = trial(specs, F, cycles, waves)
+            preds = []
+            for _ in range(max(1, repeats)):
+                ms, hops = trial(specs, F, cycles, waves)
+                preds.append(ms * hop_target / np.maximum(hops, 1e-9))
         except F.FkmcError as e:
             report[label] = "infeasible: %s" % e
             if log:
                 log("autotune F=%s: infeasible (%s)" % (label, e))
             continue
-        pred = ms * hop_target / np.maximum(hops, 1e-9)
+        pred = np.median(np.array(preds), axis=0)
         better = pred < best_t
         best_t[better] = pred[better]
         best_f[better] = used[better]

@@ -181,6 +181,8 @@ struct Layout {
     size_t occ_bytes, disp_bytes, work_bytes;
     std::vector<int64_t> occ_off, disp_off;
     size_t o_desc, o_call, o_state, o_buckets, o_stat, o_counts, o_plain, o_batch, o_tile2lat, o_tiles, o_bounds, o_c2s, o_groups;
+    size_t o_stage;          // canonical-order transfers: stage_sites bytes, then stage_sites int32x3
+    int64_t stage_sites;
     int32_t n_tiles;
     std::vector<std::vector<int32_t>> bounds[3];
 };
@@ -190,9 +192,11 @@ Layout plan(const fkmc_geometry* g, uint32_t n)
     Layout Y;
     size_t occ = 0, disp = 0;
     int32_t tiles = 0, nb = 0, nc = 0;
+    uint64_t maxN = 1;
     for (int a = 0; a < 3; a++) Y.bounds[a].resize(n);
     for (uint32_t i = 0; i < n; i++) {
         const uint64_t N = 3ull * g[i].L[0] * g[i].L[1] * g[i].L[2];
+        maxN = std::max(maxN, N);
         Y.occ_off.push_back((int64_t)occ);
         occ = align_up(occ + N, 256);
         Y.disp_off.push_back((int64_t)disp);
@@ -225,6 +229,8 @@ Layout plan(const fkmc_geometry* g, uint32_t n)
     Y.o_bounds = take((size_t)nb * sizeof(int32_t));
     Y.o_c2s = take((size_t)nc * sizeof(int32_t));
     Y.o_groups = take((size_t)std::max(tiles, 1) * sizeof(int2));
+    Y.stage_sites = (int64_t)std::min<uint64_t>(maxN, (uint64_t)kStageSites);
+    Y.o_stage = take(align_up((size_t)Y.stage_sites, 16) + (size_t)Y.stage_sites * 12);
     Y.work_bytes = w;
     return Y;
 }
@@ -604,12 +610,17 @@ fkmc_status fkmc_set_occupancy(fkmc_lattice* L, uint32_t i, const int8_t* host, 
         nv += host[k] == kSpV;
         nh += host[k] == kSpH;
     }
-    int8_t* tmp = nullptr;
-    HIP_OK(hipMalloc((void**)&tmp, N));
-    hipError_t e = hipMemcpyAsync(tmp, host, N, hipMemcpyHostToDevice, L->stream);
-    int le = e == hipSuccess ? launch_scatter(L->P, (int)i, (int64_t)N, tmp, L->stream) : 0;
+    // chunks through the work buffer's stage slice; stream order keeps a
+    // chunk's copy behind the previous chunk's kernel
+    int8_t* stage = (int8_t*)((char*)L->buf.work + L->Y.o_stage);
+    hipError_t e = hipSuccess;
+    int le = 0;
+    for (int64_t b = 0; b < (int64_t)N && e == hipSuccess && le == 0; b += L->Y.stage_sites) {
+        const int64_t c = std::min<int64_t>(L->Y.stage_sites, (int64_t)N - b);
+        e = hipMemcpyAsync(stage, host + b, (size_t)c, hipMemcpyHostToDevice, L->stream);
+        if (e == hipSuccess) le = launch_scatter(L->P, (int)i, b, c, stage, L->stream);
+    }
     hipError_t e2 = hipStreamSynchronize(L->stream);
-    (void)hipFree(tmp);
     if (e != hipSuccess || le != 0 || e2 != hipSuccess)
         return fail(FKMC_E_DEVICE, "set_occupancy copy failed");
     fkmc_status s = reset_counters(L, i);
@@ -1107,12 +1118,15 @@ fkmc_status fkmc_restore(fkmc_lattice* L, uint32_t i, const void* host, size_t b
     fkmc_status s = fkmc_set_occupancy(L, i, occ, N);
     if (s) return s;
     // displacements: canonical int32x3 -> storage int4 via a device gather of the copy
-    int32_t* d_disp = nullptr;
-    HIP_OK(hipMalloc((void**)&d_disp, N * 12));
-    hipError_t e1 = hipMemcpyAsync(d_disp, disp.data(), N * 12, hipMemcpyHostToDevice, L->stream);
-    int le = e1 == hipSuccess ? launch_scatter_disp(L->P, (int)i, (int64_t)N, d_disp, L->stream) : 0;
+    int32_t* stage = (int32_t*)((char*)L->buf.work + L->Y.o_stage);
+    hipError_t e1 = hipSuccess;
+    int le = 0;
+    for (int64_t b = 0; b < (int64_t)N && e1 == hipSuccess && le == 0; b += L->Y.stage_sites) {
+        const int64_t c = std::min<int64_t>(L->Y.stage_sites, (int64_t)N - b);
+        e1 = hipMemcpyAsync(stage, disp.data() + 3 * b, (size_t)c * 12, hipMemcpyHostToDevice, L->stream);
+        if (e1 == hipSuccess) le = launch_scatter_disp(L->P, (int)i, b, c, stage, L->stream);
+    }
     hipError_t e2 = hipStreamSynchronize(L->stream);
-    (void)hipFree(d_disp);
     if (e1 != hipSuccess || le != 0 || e2 != hipSuccess) return fail(FKMC_E_DEVICE, "restore copy failed");
     // clock and counters
     LatState st;
@@ -1254,19 +1268,21 @@ fkmc_status fkmc_read_state(fkmc_lattice* L, uint32_t i, int8_t* occ, int32_t* d
     if (n != N) return fail(FKMC_E_INVALID, "buffer has %zu entries, lattice has %zu sites", n, N);
     fkmc_status s = read_states(L);
     if (s) return s;
-    int8_t* t_occ = nullptr;
-    int32_t* t_disp = nullptr;
-    HIP_OK(hipMalloc((void**)&t_occ, N));
-    if (disp && hipMalloc((void**)&t_disp, N * 12) != hipSuccess) {
-        (void)hipFree(t_occ);
-        return fail(FKMC_E_DEVICE, "temporary allocation failed");
+    // chunks through the work buffer's stage slice: occupancy bytes first,
+    // then the chunk's displacements
+    int8_t* t_occ = (int8_t*)((char*)L->buf.work + L->Y.o_stage);
+    int32_t* t_disp = disp ? (int32_t*)(t_occ + align_up((size_t)L->Y.stage_sites, 16)) : nullptr;
+    int le = 0;
+    hipError_t e1 = hipSuccess, e2 = hipSuccess;
+    for (int64_t b = 0; b < (int64_t)N && !le && e1 == hipSuccess && e2 == hipSuccess; b += L->Y.stage_sites) {
+        const int64_t c = std::min<int64_t>(L->Y.stage_sites, (int64_t)N - b);
+        le = launch_gather(L->P, (int)i, b, c, t_occ, t_disp, L->stream);
+        if (le) break;
+        e1 = hipMemcpyAsync(occ + b, t_occ, (size_t)c, hipMemcpyDeviceToHost, L->stream);
+        if (disp && e1 == hipSuccess)
+            e2 = hipMemcpyAsync(disp + 3 * b, t_disp, (size_t)c * 12, hipMemcpyDeviceToHost, L->stream);
     }
-    int le = launch_gather(L->P, (int)i, (int64_t)N, t_occ, t_disp, L->stream);
-    hipError_t e1 = hipMemcpyAsync(occ, t_occ, N, hipMemcpyDeviceToHost, L->stream);
-    hipError_t e2 = disp ? hipMemcpyAsync(disp, t_disp, N * 12, hipMemcpyDeviceToHost, L->stream) : hipSuccess;
     hipError_t e3 = hipStreamSynchronize(L->stream);
-    (void)hipFree(t_occ);
-    if (t_disp) (void)hipFree(t_disp);
     if (le || e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
         return fail(FKMC_E_DEVICE, "read_state failed");
     return FKMC_OK;

@@ -2916,39 +2916,40 @@ __global__ __launch_bounds__(256) void k_stats(DevPtrs P, int lat)
         }
 }
 
-// Canonical-order gather (read-out) and scatter (set occupancy).
-__global__ void k_gather(DevPtrs P, int lat, int8_t* occ_c, int32_t* disp_c)
+// Canonical-order gather (read-out) and scatter (set occupancy) over the
+// canonical sites [begin, begin + count); the canonical arrays hold only those.
+__device__ __forceinline__ int64_t canon_store(const DevPtrs& P, const LatDesc& D, int64_t n)
 {
-    const LatDesc& D = P.desc[lat];
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= D.n_sites) return;
     const int t = (int)(n % 3);
     const int64_t cell = n / 3;
     const int i = (int)(cell % D.L[0]);
     const int j = (int)((cell / D.L[0]) % D.L[1]);
     const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-    const int64_t s = store_index(D, P.bounds, P.c2s, i, j, k, t);
-    occ_c[n] = P.occ[D.occ_off + s];
+    return store_index(D, P.bounds, P.c2s, i, j, k, t);
+}
+
+__global__ void k_gather(DevPtrs P, int lat, int64_t begin, int64_t count, int8_t* occ_c, int32_t* disp_c)
+{
+    const LatDesc& D = P.desc[lat];
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= count || begin + m >= D.n_sites) return;
+    const int64_t s = canon_store(P, D, begin + m);
+    occ_c[m] = P.occ[D.occ_off + s];
     if (disp_c) {
         const int4 r = P.disp[D.disp_off + s];
-        disp_c[3 * n] = r.x;
-        disp_c[3 * n + 1] = r.y;
-        disp_c[3 * n + 2] = r.z;
+        disp_c[3 * m] = r.x;
+        disp_c[3 * m + 1] = r.y;
+        disp_c[3 * m + 2] = r.z;
     }
 }
 
-__global__ void k_scatter(DevPtrs P, int lat, const int8_t* occ_c)
+__global__ void k_scatter(DevPtrs P, int lat, int64_t begin, int64_t count, const int8_t* occ_c)
 {
     const LatDesc& D = P.desc[lat];
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= D.n_sites) return;
-    const int t = (int)(n % 3);
-    const int64_t cell = n / 3;
-    const int i = (int)(cell % D.L[0]);
-    const int j = (int)((cell / D.L[0]) % D.L[1]);
-    const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-    const int64_t s = store_index(D, P.bounds, P.c2s, i, j, k, t);
-    P.occ[D.occ_off + s] = occ_c[n];
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= count || begin + m >= D.n_sites) return;
+    const int64_t s = canon_store(P, D, begin + m);
+    P.occ[D.occ_off + s] = occ_c[m];
     P.disp[D.disp_off + s] = make_int4(0, 0, 0, 0);
 }
 
@@ -3115,44 +3116,42 @@ int launch_stats(const DevPtrs& P, int lat, int64_t n_sites, void* stream)
     return (int)hipGetLastError();
 }
 
-int launch_gather(const DevPtrs& P, int lat, int64_t n_sites, int8_t* d_occ_canon,
+int launch_gather(const DevPtrs& P, int lat, int64_t begin, int64_t count, int8_t* d_occ_canon,
                   int32_t* d_disp_canon, void* stream)
 {
-    const int64_t blocks = (n_sites + 255) / 256;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, P, lat,
-                       d_occ_canon, d_disp_canon);
+    const int64_t blocks = (count + 255) / 256;
+    if (blocks < 1) return 0;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, P, lat, begin,
+                       count, d_occ_canon, d_disp_canon);
     return (int)hipGetLastError();
 }
 
-__global__ void k_scatter_disp(DevPtrs P, int lat, const int32_t* disp_c)
+__global__ void k_scatter_disp(DevPtrs P, int lat, int64_t begin, int64_t count, const int32_t* disp_c)
 {
     const LatDesc& D = P.desc[lat];
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= D.n_sites) return;
-    const int t = (int)(n % 3);
-    const int64_t cell = n / 3;
-    const int i = (int)(cell % D.L[0]);
-    const int j = (int)((cell / D.L[0]) % D.L[1]);
-    const int k = (int)(cell / ((int64_t)D.L[0] * D.L[1]));
-    const int64_t s = store_index(D, P.bounds, P.c2s, i, j, k, t);
-    P.disp[D.disp_off + s] = make_int4(disp_c[3 * n], disp_c[3 * n + 1], disp_c[3 * n + 2], 0);
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= count || begin + m >= D.n_sites) return;
+    const int64_t s = canon_store(P, D, begin + m);
+    P.disp[D.disp_off + s] = make_int4(disp_c[3 * m], disp_c[3 * m + 1], disp_c[3 * m + 2], 0);
 }
 
-int launch_scatter_disp(const DevPtrs& P, int lat, int64_t n_sites, const int32_t* d_disp_canon,
-                        void* stream)
+int launch_scatter_disp(const DevPtrs& P, int lat, int64_t begin, int64_t count,
+                        const int32_t* d_disp_canon, void* stream)
 {
-    const int64_t blocks = (n_sites + 255) / 256;
+    const int64_t blocks = (count + 255) / 256;
+    if (blocks < 1) return 0;
     hipLaunchKernelGGL(k_scatter_disp, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, P,
-                       lat, d_disp_canon);
+                       lat, begin, count, d_disp_canon);
     return (int)hipGetLastError();
 }
 
-int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_occ_canon,
+int launch_scatter(const DevPtrs& P, int lat, int64_t begin, int64_t count, const int8_t* d_occ_canon,
                    void* stream)
 {
-    const int64_t blocks = (n_sites + 255) / 256;
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, P, lat,
-                       d_occ_canon);
+    const int64_t blocks = (count + 255) / 256;
+    if (blocks < 1) return 0;
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, P, lat, begin,
+                       count, d_occ_canon);
     return (int)hipGetLastError();
 }
 

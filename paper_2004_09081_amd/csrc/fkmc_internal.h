@@ -119,6 +119,10 @@ constexpr int kWaveScratch = 3104;
 constexpr int kWaveScratchStaged = 2592;
 constexpr int kPhaseWaves = 2;     // waves per lockstep workgroup
 constexpr int kRecCache = 8 * 8 * 48;  // persistent kernel: tile records of a one-group lattice
+// Sites per chunk of the canonical-order transfers at the ABI (occupancy and
+// displacements, 13 bytes per site), staged through a slice of the work
+// buffer so that the library allocates no device memory.
+constexpr int64_t kStageSites = 1 << 19;
 
 // Kernel launchers (fkmc_device.hip).  All return a hipError_t value.
 int launch_init(const DevPtrs& P, const uint64_t* d_counts, int n_lat, void* stream);
@@ -129,16 +133,18 @@ int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void
 int launch_atomic_hbm(const DevPtrs& P, const int32_t* d_ids, int n, uint32_t n_frg, uint64_t n_stages,
                       void* stream);
 int launch_stats(const DevPtrs& P, int lat, int64_t n_sites, void* stream);
-int launch_gather(const DevPtrs& P, int lat, int64_t n_sites, int8_t* d_occ_canon,
+// Canonical <-> storage order over canonical sites [begin, begin + count) of
+// one lattice; the canonical arrays hold exactly those sites.
+int launch_gather(const DevPtrs& P, int lat, int64_t begin, int64_t count, int8_t* d_occ_canon,
                   int32_t* d_disp_canon, void* stream);
-int launch_scatter(const DevPtrs& P, int lat, int64_t n_sites, const int8_t* d_occ_canon,
+int launch_scatter(const DevPtrs& P, int lat, int64_t begin, int64_t count, const int8_t* d_occ_canon,
                    void* stream);
 int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream);
 int launch_atomic(const DevPtrs& P, const int32_t* d_ids, int n, size_t lds, uint32_t n_frg,
                   uint64_t n_stages, void* stream);
 int build_cycle_graph(const DevPtrs& P, int group, int cycles, hipGraphExec_t* out);
-int launch_scatter_disp(const DevPtrs& P, int lat, int64_t n_sites, const int32_t* d_disp_canon,
-                        void* stream);
+int launch_scatter_disp(const DevPtrs& P, int lat, int64_t begin, int64_t count,
+                        const int32_t* d_disp_canon, void* stream);
 // LDS bytes of one staged footprint of at most max_footprint_bytes sites
 // (four 16-byte-aligned segments).
 int footprint_stride(int max_footprint_bytes);

@@ -85,41 +85,17 @@ def _oracle_of(sp):
     return lat
 
 
-def test_full_ensemble_sampled_lattices_match_oracle():
-    """The 512-lattice ensemble at full size in the launch the benchmark
-    times (one persistent launch per call, 4 wavefronts per workgroup, plain
-    lattices held in LDS in the same launch, the launch order from the first
-    call's device times), with a fixed mix of decompositions that covers the
-    kernel's paths (unfragmented in LDS; fragments of 6-16 cells, held in LDS
-    or staged from HBM, in tile groups of 8, 4 or 1).  Two calls of 1e5 hops
-    per lattice (the benchmark's step is 1e6): four sampled lattices (plain,
-    resident, HBM-staged, crowded) equal the oracle's bit for bit, and every
-    lattice conserves its species and a zero displacement sum."""
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+def _run_ensemble_and_check(specs, sample, what):
+    """The 512 lattices in the launch the benchmark times (one persistent
+    launch per call, 4 wavefronts per workgroup, plain lattices held in LDS
+    in the same launch, the second call in the launch order derived from the
+    first call's device times); two calls of 1e5 hops per lattice (the
+    benchmark's step is 1e6).  Every lattice conserves its species and a
+    zero displacement sum; the sampled lattices equal the oracle's bit for
+    bit."""
     from paper_2004_09081_amd import fkmc as F
     from paper_2004_09081_amd import workloads as W
-    from paper_2004_09081_amd.autotune import plain_if_sparse
-    specs = W.cfg4(n=512, hops=10**6, frag=8)
-    edges = (6, 8, 10, 12, 16)
-    for i, sp in enumerate(specs):
-        if plain_if_sparse(sp) == 0 and i % 3 == 0:
-            sp.frag = (0, 0, 0)
-            sp.t_sync = 0.0
-        else:
-            sp.frag = (edges[i % len(edges)],) * 3
-    # samples: the smallest plain lattice, a resident fragment lattice, a
-    # staged one, and a crowded one (most vacancies per footprint)
-    plain = [i for i, sp in enumerate(specs) if sp.frag[0] == 0]
-    frag = [i for i, sp in enumerate(specs) if sp.frag[0] > 0]
-    i_plain = min(plain, key=lambda i: specs[i].n_vac * specs[i].L[0])
-    i_res = next(i for i in frag if specs[i].L[0] <= 20)
-    i_stream = next(i for i in frag if 30 <= specs[i].L[0] <= 34 and specs[i].n_vac < 400)
-    i_dense = max((i for i in frag if specs[i].L[0] <= 30),
-                  key=lambda i: specs[i].extra["x_v"] * specs[i].frag[0] ** 3)
-    sample = [i_plain, i_res, i_stream, i_dense]
-    say("full ensemble: 512 lattices, samples", sample)
+    say(what, "samples", sample, "edges", sorted({specs[i].frag[0] for i in sample}))
     geoms, rates = W.to_gpu(specs, F)
     g = F.LatticeSet(geoms)
     g.init_random([sp.n_vac for sp in specs], [sp.n_h for sp in specs])
@@ -130,10 +106,6 @@ def test_full_ensemble_sampled_lattices_match_oracle():
     for call in range(2):
         g.advance(ts, max_cycles=10**9, min_hops=H)
     st = g.read_stats()
-    assert any(s["lds_resident"] and specs[i].frag[0] == 0 for i, s in enumerate(st))
-    assert any(not s["lds_resident"] for s in st)
-    groups = {s["tile_group"] for i, s in enumerate(st) if specs[i].frag[0] > 0}
-    assert groups >= {1, 8}, groups
     for i, s in enumerate(st):
         sp = specs[i]
         assert s["count"].tolist() == [3 * sp.L[0] ** 3 - sp.n_vac - sp.n_h, sp.n_h, sp.n_vac]
@@ -141,7 +113,7 @@ def test_full_ensemble_sampled_lattices_match_oracle():
         assert int(s["hops"].sum()) >= 2 * H
     for i in sample:
         sp = specs[i]
-        say("  oracle for lattice", i, sp.L, sp.frag, sp.n_vac)
+        say("  oracle for lattice", i, sp.L, sp.frag, sp.n_vac, sp.n_h)
         lat = _oracle_of(sp)
         for call in range(2):
             if sp.frag[0] == 0:
@@ -154,6 +126,74 @@ def test_full_ensemble_sampled_lattices_match_oracle():
         occ, disp = g.read_state(i)
         assert np.array_equal(occ, lat.occ), "lattice %d occupancy" % i
         assert np.array_equal(disp, lat.disp), "lattice %d displacement" % i
+    g.close()
+    return st
+
+
+def _one_per_edge(specs):
+    """For every fragment edge in use, its lattice with the fewest sites
+    (the oracle's cost)."""
+    best = {}
+    for i, sp in enumerate(specs):
+        e = sp.frag[0]
+        if e not in best or sp.n_sites < specs[best[e]].n_sites:
+            best[e] = i
+    return [best[e] for e in sorted(best)]
+
+
+def test_full_ensemble_every_candidate_edge_matches_oracle():
+    """Every decomposition the autotuner can choose, assigned round-robin
+    over the 512 ensemble lattices (edges 4-24 cells, the whole lattice
+    where sparse, unfragmented in LDS where it fits), with one sampled
+    lattice per edge plus a resident, an HBM-staged and a crowded one."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_09081_amd import workloads as W
+    from paper_2004_09081_amd.autotune import DEFAULT_CANDIDATES
+    specs = W.cfg4(n=512, hops=10**6, frag=8)
+    for i, sp in enumerate(specs):
+        c = DEFAULT_CANDIDATES[i % len(DEFAULT_CANDIDATES)]
+        sp.frag = (int(c(sp)) if callable(c) else int(c),) * 3
+        if sp.frag[0] == 0:
+            sp.t_sync = 0.0
+    frag = [i for i, sp in enumerate(specs) if sp.frag[0] > 0]
+    i_res = next(i for i in frag if specs[i].L[0] <= 20)
+    i_stream = next(i for i in frag if 30 <= specs[i].L[0] <= 34 and specs[i].n_vac < 400)
+    i_dense = max((i for i in frag if specs[i].L[0] <= 30),
+                  key=lambda i: specs[i].extra["x_v"] * specs[i].frag[0] ** 3)
+    sample = sorted(set(_one_per_edge(specs) + [i_res, i_stream, i_dense]))
+    edges = {sp.frag[0] for sp in specs}
+    assert edges >= {0, 4, 6, 8, 10, 12, 14, 16, 18, 20, 24}, edges
+    st = _run_ensemble_and_check(specs, sample, "full ensemble, every candidate edge:")
+    assert any(s["lds_resident"] and specs[i].frag[0] == 0 for i, s in enumerate(st))
+    assert any(not s["lds_resident"] for s in st)
+    groups = {s["tile_group"] for i, s in enumerate(st) if specs[i].frag[0] > 0}
+    assert groups >= {1, 4, 8}, groups
+
+
+def test_full_ensemble_benchmark_decomposition_matches_oracle():
+    """The decomposition the benchmark runs by default (the autotuner's
+    per-lattice edges, stored with the package), one sampled lattice per
+    edge it uses plus the largest lattice of the most common edge."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_09081_amd import autotune
+    from paper_2004_09081_amd import workloads as W
+    specs = W.cfg4(n=512, hops=10**6, frag=8)
+    edges = autotune.load_edges(autotune.ENSEMBLE_EDGES, specs)
+    if edges is None:
+        pytest.skip("no stored decomposition for this ensemble")
+    for sp, e in zip(specs, edges):
+        sp.frag = (int(e),) * 3
+        if e == 0:
+            sp.t_sync = 0.0
+    sample = _one_per_edge(specs)
+    common = max(set(edges.tolist()), key=edges.tolist().count)
+    sample.append(max((i for i in range(len(specs)) if edges[i] == common),
+                      key=lambda i: specs[i].n_sites))
+    _run_ensemble_and_check(specs, sorted(set(sample)), "full ensemble, benchmark decomposition:")
 
 
 def test_atom_selection_on_ensemble_lattices_matches_oracle():

@@ -697,3 +697,98 @@ def test_random_configurations_match_oracle(schedule, seed):
             assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops], (i, cases[i].L, cases[i].frag)
             assert_same_state(g, i, lat, "random member %d %s %s" % (i, cases[i].L, cases[i].frag))
 
+
+
+# Fragment edges of 14, 18, 20 and 24 cells (sub-blocks of 7, 9, 10 and 12
+# cells, and the odd halves 8/7, 10/9, 11/10, 13/12 of merged remainders),
+# each once small enough to be held in LDS by the persistent kernel and once
+# staged from HBM, with a ragged remainder of >= 2 cells and one of 1 cell.
+WIDE_CASES = [
+    Case((26, 25, 24), (14, 14, 14), seed=41, lattice_id=0, nv=230, nh=4000, T=650.0, Ea_O=0.6,
+         Ea_H=0.45, E_z=5e7),
+    Case((30, 29, 28), (14, 14, 14), seed=41, lattice_id=1, nv=370, nh=7000, T=620.0, Ea_O=0.6,
+         Ea_H=0.45, gb_period=7, gb_mask=7, gb_dE=0.06),
+    Case((26, 23, 19), (18, 18, 18), seed=41, lattice_id=2, nv=170, nh=3000, T=700.0, Ea_O=0.6,
+         Ea_H=0.45),
+    Case((38, 37, 36), (18, 18, 18), seed=41, lattice_id=3, nv=760, nh=9000, T=600.0, Ea_O=0.6,
+         Ea_H=0.45, E_z=1e8),
+    Case((27, 21, 22), (20, 20, 20), seed=41, lattice_id=4, nv=190, nh=0, T=650.0, Ea_O=0.55,
+         gb_period=10, gb_mask=4, gb_dE=0.1),
+    Case((43, 40, 41), (20, 20, 20), seed=41, lattice_id=5, nv=1060, nh=6000, T=680.0, Ea_O=0.6,
+         Ea_H=0.45),
+    Case((25, 26, 24), (24, 24, 24), seed=41, lattice_id=6, nv=230, nh=2500, T=640.0, Ea_O=0.6,
+         Ea_H=0.45, E_z=3e7),
+    Case((50, 49, 48), (24, 24, 24), seed=41, lattice_id=7, nv=1760, nh=18000, T=600.0, Ea_O=0.6,
+         Ea_H=0.45, gb_period=12, gb_mask=3, gb_dE=0.05),
+]
+
+
+@pytest.mark.parametrize("schedule,group", [("lockstep", 0), ("lockstep", 8), ("lockstep", 4),
+                                            ("lockstep", 2), ("lockstep", 1), ("persistent", 0),
+                                            ("persistent", 8), ("persistent", 4),
+                                            ("persistent", 1)])
+def test_wide_fragment_edges_match_oracle(schedule, group):
+    """Sub-blocks of 7 to 13 cells (the wide fragment edges the autotuner
+    can pick), held in LDS or staged, under both schedules and every tile
+    group (0 = the library's own choice): the oracle's trajectories bit for
+    bit over two calls (a cycle count, then a hop target)."""
+    say("wide fragment edges", schedule, group)
+    lats = [c.oracle() for c in WIDE_CASES]
+    ts = [1.2 / (8.0 * l.k12[0]) for l in lats]
+    g = gpu_set(WIDE_CASES)
+    g.set_schedule(schedule, 4)
+    g.set_group(group)
+    for max_cycles, min_hops in ((2, 0), (10**6, 3000)):
+        for lat, t in zip(lats, ts):
+            lat.advance(t, max_cycles=max_cycles, min_hops=min_hops)
+        g.advance(ts, max_cycles=max_cycles, min_hops=min_hops)
+        stats = g.read_stats()
+        if schedule == "persistent":
+            res = [bool(s["lds_resident"]) for s in stats]
+            assert res == [True, False] * 4, res
+        for i, lat in enumerate(lats):
+            what = "%s/%d member %d %s F=%d" % (schedule, group, i, WIDE_CASES[i].L, WIDE_CASES[i].frag[0])
+            assert stats[i]["cycles"] == lat.cycles and stats[i]["t"] == lat.t, what
+            assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops], what
+            assert_same_state(g, i, lat, what)
+
+
+def test_transfers_larger_than_one_stage_chunk():
+    """A lattice of 540,000 sites (more than the 2^19 sites one staging
+    chunk of the work buffer holds): caller occupancy in, read back
+    unchanged; two cycles equal the oracle's; a checkpoint restored into a
+    fresh set continues identically."""
+    say("chunked transfers, 540,000 sites")
+    from paper_2004_09081_amd import fkmc as F
+    c = Case((60, 60, 50), (15, 15, 10), seed=51, lattice_id=2, nv=0, nh=0, T=650.0, Ea_O=0.6,
+             Ea_H=0.45, E_z=1e8)
+    lat = c.oracle()
+    n = lat.g.n_sites
+    assert n > (1 << 19)
+    rng = np.random.default_rng(52)
+    occ = np.zeros(n, np.int8)
+    idx = rng.choice(n, 3300, replace=False)
+    occ[idx[:1100]] = 2
+    occ[idx[1100:]] = 1
+    lat.occ[:] = occ
+    lat.disp[:] = 0
+    raw = O.rate_raw(O.RateParams(**c.rp), lat.g.a_angstrom)
+    lat.k12, _, _ = O.quantise(raw, 8 * min(1100, O.max_domain_sites(lat.g)))
+    g = F.LatticeSet([c.gpu_geometry()])
+    g.set_occupancy(0, occ)
+    back, disp0 = g.read_state(0)
+    assert np.array_equal(back, occ) and not disp0.any()
+    g.set_rate_table(0, raw)
+    t_sync = 1.5 / (8 * lat.k12[0])
+    lat.advance(t_sync, max_cycles=2)
+    g.advance([t_sync], max_cycles=2)
+    assert_same_state(g, 0, lat, "chunked set_occupancy")
+    blob = g.checkpoint(0)
+    h = F.LatticeSet([c.gpu_geometry()])
+    h.init_random([0], [0])
+    h.restore(0, blob)
+    for s in (g, h):
+        s.advance([t_sync], max_cycles=1)
+    lat.advance(t_sync, max_cycles=1)
+    assert_same_state(h, 0, lat, "restored from checkpoint")
+    assert_same_state(g, 0, lat, "uninterrupted")

@@ -89,3 +89,16 @@ def test_query_sizes_and_argument_checks(F):
         F.query_sizes([F.Geometry.make((8, 8, 8), (4, 0, 4))])
     with pytest.raises(F.FkmcError):
         F.rate_table_host(F.RateParams.make(T=-1.0), 3.905, 8)
+
+
+def test_library_allocates_no_device_memory():
+    """Device memory belongs to the caller: no library source allocates or
+    frees device memory (canonical-order transfers stage through the work
+    buffer)."""
+    csrc = os.path.join(ROOT, "paper_2004_09081_amd", "csrc")
+    pat = re.compile(r"\b(hipMalloc|hipMallocAsync|hipMallocManaged|hipExtMallocWithFlags|hipFree|"
+                     r"hipFreeAsync|hipMallocPitch|hipMalloc3D|hipMallocArray)\s*\(")
+    for name in sorted(os.listdir(csrc)):
+        text = open(os.path.join(csrc, name)).read()
+        text = re.sub(r"//[^\n]*", "", re.sub(r"/\*.*?\*/", "", text, flags=re.S))
+        assert not pat.search(text), "%s allocates device memory: %s" % (name, pat.search(text).group(0))

@@ -244,3 +244,84 @@ def test_drift_with_boundary_planes_matches_projected_chain():
     se = z.std(ddof=1) / math.sqrt(R) / tend
     assert abs(v_est - v_ref) < 4 * se, (v_est, v_ref, se)
     assert se / abs(v_ref) < 0.1
+
+
+def _tilted_msd(Q, disp, pi, t, lam=1e-3):
+    """Exact E[x(t)^2] of the additive functional x (jump i -> j adds
+    disp[i, j]) of a chain with generator Q started from law pi: the second
+    derivative at 0 of pi exp(t Q(lam)) 1, where Q(lam) multiplies each
+    off-diagonal rate by exp(lam disp), by a central difference."""
+    def mgf(l):
+        M = Q * np.exp(l * disp)
+        np.fill_diagonal(M, np.diag(Q))
+        return float(pi @ brute.propagate(M, t) @ np.ones(len(pi)))
+    return (mgf(lam) - 2.0 * mgf(0.0) + mgf(-lam)) / lam**2
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_diffusion_across_boundary_planes_matches_projected_chain(axis):
+    """One vacancy, no field, boundary planes normal to x (or y) every P
+    cells.  A site lies on a plane when its coordinate along that axis is a
+    multiple of P lattice constants (positions and neighbours from real
+    space, not from the oracle's tables).  Every site of one layer (equal
+    doubled coordinate along the axis) has the same rates to each other
+    layer, which the test checks, so the layer index alone is a Markov
+    chain; from the stationary (uniform) start its exact E[dx(t)^2] must
+    match the oracle's runs.  The planes slow diffusion along the axis by
+    about 3x, far outside the statistical error."""
+    T, Ea, gbdE, P = 600.0, 0.6, 0.1, 3
+    L = [3, 3, 3]
+    L[axis] = 6
+    L = tuple(L)
+    mask = 1 << axis
+    S = brute.sites(L)
+    nb = brute.neighbours(L)
+    N = len(S)
+    pos = np.array([s[3] for s in S])
+    on_plane = np.array([abs(p[axis] - round(p[axis])) < 1e-9 and int(round(p[axis])) % P == 0
+                         for p in pos])
+    X = np.rint(2 * pos[:, axis]).astype(int) % (2 * L[axis])
+    nl = 2 * L[axis]
+    k = lambda g: brute.arrhenius(1e13, Ea, T, gb=gbdE if g else 0.0)
+    per_site = np.zeros((N, nl))
+    step = np.zeros((nl, nl))
+    for s in range(N):
+        for m, d in nb[s]:
+            per_site[s, X[m]] += k(on_plane[s] or on_plane[m])
+            step[X[s], X[m]] = round(2 * d[axis])
+    Q = np.zeros((nl, nl))
+    for Xl in range(nl):
+        rows = per_site[X == Xl]
+        assert np.allclose(rows, rows[0], rtol=1e-14, atol=0), "layer %d is not lumpable" % Xl
+        Q[Xl] = rows[0]
+    np.fill_diagonal(Q, 0.0)
+    Q -= np.diag(Q.sum(1))
+    w = np.bincount(X, minlength=nl).astype(float)
+    pi = w / w.sum()
+    tend = 150.0 / (8 * k(0))
+    msd_ref = _tilted_msd(Q, step.astype(float), pi, tend)
+    # without planes the same chain gives a clearly different value
+    Q0 = np.where(Q > 0, 0.0, Q)
+    Q0 = np.zeros_like(Q)
+    for Xl in range(nl):
+        for Ym in range(nl):
+            if step[Xl, Ym] != 0:
+                Q0[Xl, Ym] = (4 if Xl % 2 == 0 else 2) * k(0)
+    Q0 -= np.diag(Q0.sum(1))
+    msd_free = _tilted_msd(Q0, step.astype(float), pi, tend)
+    p = O.RateParams(nu=1e13, T=T, Ea_O=Ea, gb_period_cells=P, gb_axes_mask=mask, gb_dE=gbdE)
+    rng = np.random.default_rng(17 + axis)
+    R = 3000
+    x2 = np.zeros(R)
+    for r in range(R):
+        s0 = int(rng.integers(N))
+        lat = O.Lattice(O.Geometry(L=L, seed=31, lattice_id=r, gb_period_cells=P, gb_axes_mask=mask))
+        lat.occ[s0] = 2
+        lat.set_rates(p)
+        lat.advance_plain(10**9, t_horizon=tend)
+        v = np.nonzero(lat.occ == 2)[0][0]
+        x2[r] = float(lat.disp[v, axis]) ** 2
+    est = x2.mean()
+    se = x2.std(ddof=1) / math.sqrt(R)
+    assert abs(est - msd_ref) < 4 * se, (est, msd_ref, se)
+    assert abs(msd_free - msd_ref) > 10 * se, (msd_free, msd_ref, se)
