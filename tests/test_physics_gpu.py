@@ -109,3 +109,99 @@ def test_atom_selection_single_vacancy_closed_form(n_frg):
     assert abs(D_est - D_ref) < 4 * se + 0.01 * D_ref
     assert se / D_ref < 0.05
 
+
+
+def test_cfg1_msd_and_diffusion():
+    """The 8^3-cell plain lattice with 15 vacancies (no H, O barrier 0.60
+    eV, 600 K, unfragmented BKL, 1e5 hops), 1,024 seeds at once: MSD_V(t)
+    read every 1,000 hops; at 1e5 hops D_V = MSD/(6t) lies within 2 % + 3
+    sigma of Gamma_tot d^2/6 = 927.63 A^2/us (Eqs. RateCnst1, TimeStep; the
+    vacancies block one another, which lowers D by about 1 %), and the MSD
+    grows linearly: the slope over the second half gives the same D within
+    its error."""
+    R, T, Ea = 1024, 600.0, 0.6
+    cases = [Case((8, 8, 8), seed=s, lattice_id=0, nv=15, nh=0, T=T, Ea_O=Ea) for s in range(R)]
+    say("cfg1: %d seeds, 100 x 1000 hops" % R)
+    g = gpu_set(cases)
+    msd = np.zeros((100, R))
+    t = np.zeros((100, R))
+    for k in range(100):
+        g.advance([0.0] * R, 0, 1000)
+        st = g.read_stats()
+        msd[k] = [s["msd"][2] for s in st]
+        t[k] = [s["t"] for s in st]
+        assert all(int(s["hops"].sum()) == 1000 * (k + 1) for s in st)
+    k0 = 1e13 * math.exp(-Ea / (KB * T))
+    D_ref = 8 * k0 * (A / math.sqrt(2)) ** 2 / 6          # A^2/s
+    D = msd[-1] / (6 * t[-1])
+    se = D.std(ddof=1) / math.sqrt(R)
+    # slope of the mean MSD against the mean time over the second half
+    tm, mm = t.mean(axis=1), msd.mean(axis=1)
+    slope = np.polyfit(tm[50:], mm[50:], 1)[0] / 6
+    say("  MSD_V(t) [A^2] at 1e4, 5e4, 1e5 hops: %.1f %.1f %.1f (t = %.4g %.4g %.4g s)"
+        % (mm[9], mm[49], mm[99], tm[9], tm[49], tm[99]))
+    say("  D_V %.2f +- %.2f A^2/us, slope %.2f, closed form %.2f (%.2f %%)"
+        % (1e-6 * D.mean(), 1e-6 * se, 1e-6 * slope, 1e-6 * D_ref, 100 * (D.mean() / D_ref - 1)))
+    assert abs(D.mean() - D_ref) < 0.02 * D_ref + 3 * se
+    assert se < 0.01 * D_ref
+    assert abs(slope - D.mean()) < 0.03 * D_ref
+
+
+def test_cfg3_drift_and_diffusion_tensor():
+    """The 600^3 biased lattice with boundary planes (0.1 % vacancies, no
+    H, 0.75 eV, 450 K, E_z 1e7 V/m, +0.3 eV z-planes every 50 cells,
+    16^3-cell fragments, t_sync 1/(8 k_O)) advanced by at least 1e8 hops:
+    the sums obey N_V <r_V> = -N_O <r_O> exactly (every hop moves the
+    vacancy by h and an O by -h), so v_O = -(N_V/N_O) v_V; the vacancy
+    drift matches the exact drift of the single-vacancy chain projected on
+    the z layers of one 50-cell period within 3 sigma plus 3 % (the rest is
+    vacancy blocking and the one-hop-per-cycle splitting); the transverse
+    drift is zero within 4 sigma; and the D tensor is reported."""
+    from scipy.linalg import null_space
+    from paper_2004_09081_amd import fkmc as F
+    from paper_2004_09081_amd import workloads as W
+    sp = W.cfg3()
+    say("cfg3: 600^3 to 1e8 hops")
+    geoms, rates = W.to_gpu([sp], F)
+    g = F.LatticeSet(geoms)
+    g.init_random([sp.n_vac], [0])
+    g.set_rates(rates)
+    g.advance([sp.t_sync], max_cycles=10**6, min_hops=100_000_000)
+    st = g.read_stats()[0]
+    g.close()
+    nO, nV = int(st["count"][0]), int(st["count"][2])
+    assert nV == sp.n_vac and int(st["hops"].sum()) >= 100_000_000
+    assert (st["sum_r"][2] == -st["sum_r"][0]).all()
+    t = st["t"]
+    vV = st["drift"][2] * 1e-10   # m/s
+    vO = st["drift"][0] * 1e-10
+    assert abs(vO + nV / nO * vV) <= 1e-12 * abs(vV)
+    # statistical error of the mean vacancy displacement along each axis
+    n = float(nV)
+    mean = st["sum_r"][2] / n
+    var = np.array([st["sum_rr"][2][a] for a in range(3)]) / n - mean ** 2
+    se_v = np.sqrt(var / n) * (A / 2) * 1e-10 / t
+    # exact drift of one vacancy on the ring of z layers (doubled units) of one period
+    kp = lambda up, g: brute.arrhenius(1e13, sp.Ea_O, sp.T, sp.E_z, sp.q, 0.5 if up else -0.5, A,
+                                       gb=sp.gb_dE if g else 0.0)
+    nz = 2 * sp.gb_period
+    Q = np.zeros((nz, nz))
+    gb_layer = lambda Z: Z % 2 == 0 and (Z // 2) % sp.gb_period == 0
+    for Z in range(nz):
+        up, dn = (Z + 1) % nz, (Z - 1) % nz
+        if Z % 2:
+            Q[Z, up] += 2 * kp(True, gb_layer(up))
+            Q[Z, dn] += 2 * kp(False, gb_layer(dn))
+        else:
+            Q[Z, up] += 4 * kp(True, gb_layer(Z))
+            Q[Z, dn] += 4 * kp(False, gb_layer(Z))
+    Q -= np.diag(Q.sum(1))
+    pi = null_space(Q.T)[:, 0]
+    pi /= pi.sum()
+    v_ref = sum(pi[Z] * (Q[Z, (Z + 1) % nz] - Q[Z, (Z - 1) % nz]) for Z in range(nz)) * A / 2 * 1e-10
+    say("  %d hops, t = %.4g s: v_V = (%.3g, %.3g, %.5g) m/s (+- %.2g), chain %.5g m/s (%+.2f %%); "
+        "v_O z %.4g m/s" % (int(st["hops"].sum()), t, vV[0], vV[1], vV[2], se_v[2], v_ref,
+                            100 * (vV[2] / v_ref - 1), vO[2]))
+    say("  D tensor of V (A^2/s, xx yy zz xy xz yz): %s" % np.array2string(st["Dtensor"][2], precision=4))
+    assert abs(vV[2] - v_ref) < 3 * se_v[2] + 0.03 * abs(v_ref)
+    assert abs(vV[0]) < 4 * se_v[0] and abs(vV[1]) < 4 * se_v[1]
