@@ -149,6 +149,22 @@ fkmc_status fkmc_query_sizes(const fkmc_geometry* geoms, uint32_t n, size_t byte
 fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffers* buf,
                         void* hip_stream, fkmc_lattice** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * handle as fkmc_create, but the work buffer is a static array of 64 MiB per
+ * device held by the library (it stays allocated on every device the library
+ * runs on until the process ends).  The caller passes only the occupancy and
+ * displacement buffers (sizes and alignment as fkmc_query_sizes and
+ * fkmc_buffers state; the work size it reports must not exceed 64 MiB, else
+ * FKMC_E_NOMEM).  The call allocates nothing on the device or in pinned host
+ * memory.  One such handle per device at a time: a second one while the
+ * first lives returns FKMC_E_STATE (two handles on one array would race);
+ * fkmc_destroy releases it.  The array keeps the previous handle's contents,
+ * so creation clears all of it that the handle uses.  Every other call works
+ * on the handle as on one from fkmc_create, with identical results. */
+fkmc_status fkmc_create_static(const fkmc_geometry* geoms, uint32_t n, void* occ, size_t occ_bytes,
+                               void* disp, size_t disp_bytes, void* hip_stream, fkmc_lattice** out);
+
 /* Never frees the caller's buffers. */
 fkmc_status fkmc_destroy(fkmc_lattice* lat);
 

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -327,7 +328,19 @@ struct fkmc_lattice {
     // run with the least interference from the workgroup sharing its CU
     std::vector<uint64_t> cost_ticks;
     uint64_t cost_shape[2] = {0, 0};       // (max_cycles, min_hops) of those calls
+    int static_dev = -1;                   // fkmc_create_static: device whose scratch it holds
 };
+
+// Work space of fkmc_create_static: one array per device, for callers that
+// cannot allocate device memory.  Host code never passes `scratch` itself to
+// a kernel or copy: its device address comes from hipGetSymbolAddress, once
+// per device (with that device current), and is kept in g_scratch.
+static constexpr size_t kStaticWorkBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkBytes];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices] = {};
+static bool g_scratch_held[kMaxDevices] = {};
 
 static constexpr int kGraphCycles = 8;
 
@@ -405,16 +418,12 @@ fkmc_status fkmc_rate_table_host(const fkmc_rate_params* p, double a_angstrom, u
     return quantise(raw_out, n_ev, quant_out, q_out, max_rel_out);
 }
 
-fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffers* buf,
-                        void* hip_stream, fkmc_lattice** out)
+// Handle over n lattices in the given buffers.  static_dev >= 0: the work
+// buffer is that device's static scratch (no pinned host mirror; cleared by
+// a fill kernel).
+static fkmc_status create_impl(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffers* buf,
+                               void* hip_stream, fkmc_lattice** out, const Layout& Y, int static_dev)
 {
-    if (!geoms || !buf || !out || n == 0) return fail(FKMC_E_INVALID, "null argument or n = 0");
-    *out = nullptr;
-    for (uint32_t i = 0; i < n; i++) {
-        fkmc_status s = check_geometry(geoms[i], i);
-        if (s) return s;
-    }
-    Layout Y = plan(geoms, n);
     if (!buf->occ || !buf->disp || !buf->work) return fail(FKMC_E_INVALID, "null device buffer");
     if (buf->bytes[0] < Y.occ_bytes || buf->bytes[1] < Y.disp_bytes || buf->bytes[2] < Y.work_bytes)
         return fail(FKMC_E_NOMEM, "buffers too small: need %zu/%zu/%zu bytes", Y.occ_bytes,
@@ -450,7 +459,10 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
     L->call.resize(n);
     L->qstep.assign(n, 0.0);
     L->qrel.assign(n, 0.0);
-    if (hipHostMalloc((void**)&L->h_state, n * sizeof(LatState), hipHostMallocDefault) != hipSuccess) {
+    L->static_dev = static_dev;
+    if (static_dev >= 0) {
+        L->h_state = new LatState[n];
+    } else if (hipHostMalloc((void**)&L->h_state, n * sizeof(LatState), hipHostMallocDefault) != hipSuccess) {
         delete L;
         return fail(FKMC_E_DEVICE, "pinned host allocation failed");
     }
@@ -524,16 +536,29 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
     }
     L->d_counts = (uint64_t*)(w + Y.o_counts);
 
-    auto cleanup = [&](fkmc_status s) { (void)hipHostFree(L->h_state); delete L; return s; };
+    auto cleanup = [&](fkmc_status s) {
+        if (static_dev >= 0) delete[] L->h_state;
+        else (void)hipHostFree(L->h_state);
+        delete L;
+        return s;
+    };
 #define CREATE_OK(expr)                                                             \
     do {                                                                            \
         hipError_t e_ = (expr);                                                     \
         if (e_ != hipSuccess)                                                       \
             return cleanup(fail(FKMC_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
     } while (0)
-    CREATE_OK(hipMemsetAsync(buf->work, 0, Y.work_bytes, L->stream));
-    CREATE_OK(hipMemsetAsync(buf->occ, 0, Y.occ_bytes, L->stream));
-    CREATE_OK(hipMemsetAsync(buf->disp, 0, Y.disp_bytes, L->stream));
+    if (static_dev >= 0) {
+        // the scratch keeps the previous handle's contents: clear all this
+        // handle uses
+        CREATE_OK((hipError_t)launch_fill_zero(buf->work, Y.work_bytes, L->stream));
+        CREATE_OK((hipError_t)launch_fill_zero(buf->occ, Y.occ_bytes, L->stream));
+        CREATE_OK((hipError_t)launch_fill_zero(buf->disp, Y.disp_bytes, L->stream));
+    } else {
+        CREATE_OK(hipMemsetAsync(buf->work, 0, Y.work_bytes, L->stream));
+        CREATE_OK(hipMemsetAsync(buf->occ, 0, Y.occ_bytes, L->stream));
+        CREATE_OK(hipMemsetAsync(buf->disp, 0, Y.disp_bytes, L->stream));
+    }
     CREATE_OK(hipMemcpyAsync(w + Y.o_desc, L->desc.data(), n * sizeof(LatDesc), hipMemcpyHostToDevice, L->stream));
     if (!bounds.empty())
         CREATE_OK(hipMemcpyAsync(w + Y.o_bounds, bounds.data(), bounds.size() * 4, hipMemcpyHostToDevice, L->stream));
@@ -556,13 +581,70 @@ fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffe
     return FKMC_OK;
 }
 
+fkmc_status fkmc_create(const fkmc_geometry* geoms, uint32_t n, const fkmc_buffers* buf,
+                        void* hip_stream, fkmc_lattice** out)
+{
+    if (!geoms || !buf || !out || n == 0) return fail(FKMC_E_INVALID, "null argument or n = 0");
+    *out = nullptr;
+    for (uint32_t i = 0; i < n; i++) {
+        fkmc_status s = check_geometry(geoms[i], i);
+        if (s) return s;
+    }
+    return create_impl(geoms, n, buf, hip_stream, out, plan(geoms, n), -1);
+}
+
+fkmc_status fkmc_create_static(const fkmc_geometry* geoms, uint32_t n, void* occ, size_t occ_bytes,
+                               void* disp, size_t disp_bytes, void* hip_stream, fkmc_lattice** out)
+{
+    if (!geoms || !out || n == 0) return fail(FKMC_E_INVALID, "null argument or n = 0");
+    *out = nullptr;
+    for (uint32_t i = 0; i < n; i++) {
+        fkmc_status s = check_geometry(geoms[i], i);
+        if (s) return s;
+    }
+    Layout Y = plan(geoms, n);
+    if (Y.work_bytes > kStaticWorkBytes)
+        return fail(FKMC_E_NOMEM, "work space of %zu bytes exceeds the static scratch of %zu bytes",
+                    Y.work_bytes, kStaticWorkBytes);
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FKMC_E_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FKMC_E_DEVICE, "address of the static scratch on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    if (g_scratch_held[dev])
+        return fail(FKMC_E_STATE, "the static scratch of device %d is held by another handle", dev);
+    fkmc_buffers buf{};
+    buf.occ = occ;
+    buf.disp = disp;
+    buf.work = g_scratch[dev];
+    buf.bytes[0] = occ_bytes;
+    buf.bytes[1] = disp_bytes;
+    buf.bytes[2] = kStaticWorkBytes;
+    fkmc_status s = create_impl(geoms, n, &buf, hip_stream, out, Y, dev);
+    if (s == FKMC_OK) g_scratch_held[dev] = true;
+    return s;
+}
+
 fkmc_status fkmc_destroy(fkmc_lattice* L)
 {
     if (!L) return FKMC_OK;
     (void)hipStreamSynchronize(L->stream);
     for (auto e : L->ev) (void)hipEventDestroy(e);
     if (L->graph) (void)hipGraphExecDestroy(L->graph);
-    if (L->h_state) (void)hipHostFree(L->h_state);
+    if (L->static_dev >= 0) {
+        delete[] L->h_state;
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        g_scratch_held[L->static_dev] = false;
+    } else if (L->h_state) {
+        (void)hipHostFree(L->h_state);
+    }
     delete L;
     return FKMC_OK;
 }

@@ -3155,6 +3155,26 @@ int launch_scatter(const DevPtrs& P, int lat, int64_t begin, int64_t count, cons
     return (int)hipGetLastError();
 }
 
+__global__ void k_fill_zero(unsigned char* p, size_t bytes)
+{
+    const size_t n16 = bytes / 16;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        ((int4*)p)[i] = make_int4(0, 0, 0, 0);
+    const size_t t = n16 * 16 + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && t < bytes) p[t] = 0;
+}
+
+int launch_fill_zero(void* p, size_t bytes, void* stream)
+{
+    if (bytes == 0) return 0;
+    size_t blocks = (bytes / 16 + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                       (unsigned char*)p, bytes);
+    return (int)hipGetLastError();
+}
+
 int footprint_stride(int max_footprint_bytes)
 {
     // four segments, each padded to whole 16-byte chunks from its alignment

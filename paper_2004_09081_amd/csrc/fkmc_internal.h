@@ -106,7 +106,9 @@ struct DevPtrs {
     const int32_t* batch_ids;      // lattices run by the persistent kernel
     const int2* groups;            // lockstep kernel: (lattice, first fragment) per wave
     int32_t n_groups;
-    int32_t fp_stride;             // LDS bytes of one staged footprint
+    int32_t fp_stride;             // Zero `bytes` bytes at p (a fill kernel: 16-byte stores, byte tail).
+int launch_fill_zero(void* p, size_t bytes, void* stream);
+// LDS bytes of one staged footprint
     int32_t lds_region_bytes;      // persistent kernel: resident slab or staged footprints
     int32_t lds_wave_bytes;        // lockstep kernel: per-wave scratch plus footprints
 };
@@ -145,6 +147,8 @@ int launch_atomic(const DevPtrs& P, const int32_t* d_ids, int n, size_t lds, uin
 int build_cycle_graph(const DevPtrs& P, int group, int cycles, hipGraphExec_t* out);
 int launch_scatter_disp(const DevPtrs& P, int lat, int64_t begin, int64_t count,
                         const int32_t* d_disp_canon, void* stream);
+// Zero `bytes` bytes at p (a fill kernel: 16-byte stores, byte tail).
+int launch_fill_zero(void* p, size_t bytes, void* stream);
 // LDS bytes of one staged footprint of at most max_footprint_bytes sites
 // (four 16-byte-aligned segments).
 int footprint_stride(int max_footprint_bytes);

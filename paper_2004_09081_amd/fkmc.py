@@ -91,6 +91,8 @@ _P = C.POINTER
 _SIGS = {
     "fkmc_query_sizes": [_P(Geometry), C.c_uint32, _P(C.c_size_t)],
     "fkmc_create": [_P(Geometry), C.c_uint32, _P(Buffers), C.c_void_p, _P(C.c_void_p)],
+    "fkmc_create_static": [_P(Geometry), C.c_uint32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t,
+                           C.c_void_p, _P(C.c_void_p)],
     "fkmc_destroy": [C.c_void_p],
     "fkmc_count": [C.c_void_p],
     "fkmc_init_random": [C.c_void_p, _P(C.c_uint64), _P(C.c_uint64)],
@@ -174,9 +176,12 @@ def query_sizes(geoms: Sequence[Geometry]):
 
 @dataclass
 class LatticeSet:
-    """A set of n >= 1 lattices in caller-owned (torch) device memory."""
+    """A set of n >= 1 lattices in caller-owned (torch) device memory.  With
+    static_work the handle comes from fkmc_create_static: only occupancy and
+    displacements are allocated here, the work space is the library's."""
     geoms: list
     device: str = "cuda:0"
+    static_work: bool = False
     _h: C.c_void_p = field(default=None, init=False, repr=False)
 
     def __post_init__(self):
@@ -188,14 +193,20 @@ class LatticeSet:
         dev = torch.device(self.device)
         self.occ_buf = torch.empty(max(sizes[0], 1), dtype=torch.uint8, device=dev)
         self.disp_buf = torch.empty(max(sizes[1], 16), dtype=torch.uint8, device=dev)
-        self.work_buf = torch.empty(max(sizes[2], 1), dtype=torch.uint8, device=dev)
         self.stream = torch.cuda.current_stream(dev)
-        b = Buffers(self.occ_buf.data_ptr(), self.disp_buf.data_ptr(), self.work_buf.data_ptr(),
-                    (C.c_size_t * 3)(*sizes))
         arr = (Geometry * self.n)(*self.geoms)
         h = C.c_void_p()
-        _check(lib().fkmc_create(arr, self.n, C.byref(b), C.c_void_p(self.stream.cuda_stream),
-                                 C.byref(h)))
+        if self.static_work:
+            self.work_buf = None
+            _check(lib().fkmc_create_static(arr, self.n, self.occ_buf.data_ptr(), sizes[0],
+                                            self.disp_buf.data_ptr(), sizes[1],
+                                            C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        else:
+            self.work_buf = torch.empty(max(sizes[2], 1), dtype=torch.uint8, device=dev)
+            b = Buffers(self.occ_buf.data_ptr(), self.disp_buf.data_ptr(), self.work_buf.data_ptr(),
+                        (C.c_size_t * 3)(*sizes))
+            _check(lib().fkmc_create(arr, self.n, C.byref(b), C.c_void_p(self.stream.cuda_stream),
+                                     C.byref(h)))
         self._h = h
 
     def close(self):
