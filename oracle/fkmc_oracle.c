@@ -466,6 +466,8 @@ static int in_footprint(const or_geom* g, const int c[3], int t, const int lo[3]
  * Event e = slot*8 + direction.  rate = 0 unless the hop edge is active (its
  * owner cell lies in box [lo,hi), or always when box == NULL) and the target
  * holds an ion (O or H). */
+typedef struct site_ctx site_ctx;
+
 typedef struct {
     const or_geom* g;
     const double* k12;
@@ -475,7 +477,10 @@ typedef struct {
     int n_slots;
     const int* lo;
     const int* hi;
+    site_ctx* site; /* site-energy interactions (NULL: none) */
 } step_ctx;
+
+static double site_event_rate(const step_ctx* S, int64_t s, int64_t tgt, int X, int dzi, int g);
 
 static double event_rate(const step_ctx* S, int64_t s, int d)
 {
@@ -492,6 +497,7 @@ static double event_rate(const step_ctx* S, int64_t s, int d)
     if (X == SP_V) return 0.0;
     g = is_gb_site(S->g, c, t) || is_gb_site(S->g, tc, tt);
     dzi = HOPS[t][d][2] + 1;
+    if (S->site) return site_event_rate(S, s, tgt, X, dzi, g);
     return S->k12[(X * 3 + dzi) * 2 + g];
 }
 
@@ -607,7 +613,7 @@ int or_phase(const or_geom* g, const double k12[12], int8_t* occ, int32_t* disp,
         if (w == 0 || slots[w - 1] != slots[m]) slots[w++] = slots[m];
     n_slots = w;
     S.g = g; S.k12 = k12; S.occ = occ; S.disp = disp;
-    S.slot_site = slots; S.n_slots = n_slots; S.lo = lo; S.hi = hi;
+    S.slot_site = slots; S.n_slots = n_slots; S.lo = lo; S.hi = hi; S.site = NULL;
     key[0] = g->seed; key[1] = g->lattice_id;
     for (;;) {
         int r;
@@ -667,7 +673,7 @@ int or_advance_plain(const or_geom* g, const double k12[12], int8_t* occ, int32_
     for (s = 0; s < N; s++)
         if (occ[s] == SP_V) slots[n_slots++] = s;
     S.g = g; S.k12 = k12; S.occ = occ; S.disp = disp;
-    S.slot_site = slots; S.n_slots = n_slots; S.lo = NULL; S.hi = NULL;
+    S.slot_site = slots; S.n_slots = n_slots; S.lo = NULL; S.hi = NULL; S.site = NULL;
     key[0] = g->seed; key[1] = g->lattice_id;
     hops[0] = hops[1] = 0;
     t_end = t_horizon > 0.0 ? *t + t_horizon : 0.0;
@@ -735,7 +741,7 @@ int or_advance_atomic(const or_geom* g, const double k12[12], int8_t* occ, int32
     for (s = 0; s < N; s++)
         if (occ[s] == SP_V) slots[n_slots++] = s;
     S.g = g; S.k12 = k12; S.occ = occ; S.disp = disp;
-    S.slot_site = slots; S.n_slots = n_slots; S.lo = NULL; S.hi = NULL;
+    S.slot_site = slots; S.n_slots = n_slots; S.lo = NULL; S.hi = NULL; S.site = NULL;
     key[0] = g->seed; key[1] = g->lattice_id;
     hops[0] = hops[1] = 0;
     for (st = 0; st < n_stages; st++) {
@@ -845,4 +851,203 @@ void or_sub_block(const or_geom* g, int f, int c, int32_t lo[3], int32_t hi[3])
     int l[3], h[3], a;
     sub_block(g, f, c, l, h);
     for (a = 0; a < 3; a++) { lo[a] = l[a]; hi[a] = h[a]; }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Site-energy interactions (Sec. "Oxygen vacancy diffusion with dopant and
+ * defect interaction", Table TABLEadd01).  The hop rate becomes
+ * k = A exp(-(Ea + dE_site/2 + field and boundary terms)/(k_B T)), where
+ * dE_site is the vacancy's site energy at the target minus that at its
+ * origin, and a site energy sums pair energies over the Fe dopants (on B
+ * sites, the cube centres) and the other vacancies within the tabulated
+ * shells: E_site(s) = sum_shell (number of Fe in the shell) e_Fe[shell] +
+ * sum_shell (number of other vacancies in the shell) e_VV[shell].
+ *
+ * Shells by squared distance in (a/2)^2, minimum image:
+ *  - vacancy-Fe (O site to B site): 1, 5, 9, 13 (a/2, 1.12 a, 1.5 a, 1.80 a);
+ *  - vacancy-vacancy (O site to O site): 2, 4, 6, 8, 10, 16 (a/sqrt2, a,
+ *    1.22 a, 1.41 a, 1.58 a, 2 a); any other distance contributes 0.
+ * Energies are integers in meV, so site energies and their differences are
+ * exact.  The hopping vacancy does not interact with itself: the target's
+ * energy is taken without the vacancy at the origin.  Rates are
+ * k = quantise(k12raw[X][dz][g] * f[dE]), f[dE] = exp(-dE meV / (2 k_B T)),
+ * for |dE| <= window meV; the quantum is set by the largest product, as in
+ * or_quantise.  The draws, clock and selection are those of plain BKL
+ * (or_advance_plain): with all pair energies zero the trajectory is plain
+ * BKL's, bit for bit. */
+typedef struct {
+    int32_t e_fe[4];
+    int32_t e_vv[6];
+    int32_t window;
+} or_site_params;
+
+struct site_ctx {
+    const uint8_t* fe;      /* [L2][L1][L0] cells: 1 = Fe on the cell's B site */
+    const or_site_params* sp;
+    const double* raw12;    /* unquantised rates of Eq. RateCnst1 (zeroed absent species) */
+    const double* f;        /* [2 window + 1] */
+    double q;
+    int err;                /* a hop's |dE| exceeded the window */
+};
+
+static int shell_fe(int n)
+{
+    return n == 1 ? 0 : (n == 5 ? 1 : (n == 9 ? 2 : (n == 13 ? 3 : -1)));
+}
+
+static int shell_vv(int n)
+{
+    return n == 2 ? 0 : (n == 4 ? 1 : (n == 6 ? 2 : (n == 8 ? 3 : (n == 10 ? 4 : (n == 16 ? 5 : -1)))));
+}
+
+/* Site energy (meV) of a vacancy on O site s: Fe pairs and vacancy pairs,
+ * leaving out the vacancy on site `skip` (and s itself).  Brute force over
+ * every lattice point within squared doubled distance 16. */
+int32_t or_site_energy(const or_geom* g, const int8_t* occ, const uint8_t* fe, const or_site_params* sp,
+                       int64_t s, int64_t skip)
+{
+    int c[3], t, P[3], dX, dY, dZ, a;
+    int32_t E = 0;
+    site_coords(g, s, c, &t);
+    P[0] = 2 * c[0] + (t != 0);
+    P[1] = 2 * c[1] + (t != 1);
+    P[2] = 2 * c[2] + (t != 2);
+    for (dX = -4; dX <= 4; dX++)
+        for (dY = -4; dY <= 4; dY++)
+            for (dZ = -4; dZ <= 4; dZ++) {
+                int n = dX * dX + dY * dY + dZ * dZ, Q[3], odd = 0;
+                if (n == 0 || n > 16) continue;
+                Q[0] = modp(P[0] + dX, 2 * g->L[0]);
+                Q[1] = modp(P[1] + dY, 2 * g->L[1]);
+                Q[2] = modp(P[2] + dZ, 2 * g->L[2]);
+                for (a = 0; a < 3; a++) odd += Q[a] & 1;
+                if (odd == 3) {          /* B site: the centre of cell Q/2 */
+                    int sh = shell_fe(n);
+                    int64_t cell = ((int64_t)(Q[2] >> 1) * g->L[1] + (Q[1] >> 1)) * g->L[0] + (Q[0] >> 1);
+                    if (sh >= 0 && fe[cell]) E += sp->e_fe[sh];
+                } else if (odd == 2) {   /* O site: type = the even coordinate */
+                    int sh = shell_vv(n), cc[3], tt = (Q[0] & 1) == 0 ? 0 : ((Q[1] & 1) == 0 ? 1 : 2);
+                    int64_t u;
+                    cc[0] = Q[0] >> 1;
+                    cc[1] = Q[1] >> 1;
+                    cc[2] = Q[2] >> 1;
+                    u = site_index(g, cc, tt);
+                    if (sh >= 0 && u != skip && u != s && occ[u] == SP_V) E += sp->e_vv[sh];
+                }
+            }
+    return E;
+}
+
+static double site_event_rate(const step_ctx* S, int64_t s, int64_t tgt, int X, int dzi, int g)
+{
+    site_ctx* C = S->site;
+    const int32_t W = C->sp->window;
+    const int32_t dE = or_site_energy(S->g, S->occ, C->fe, C->sp, tgt, s) -
+                       or_site_energy(S->g, S->occ, C->fe, C->sp, s, s);
+    double k;
+    if (dE < -W || dE > W) {
+        C->err = 1;
+        return 0.0;
+    }
+    k = C->raw12[(X * 3 + dzi) * 2 + g] * C->f[dE + W];
+    return rint(k / C->q) * C->q;
+}
+
+/* Factors f[j] = exp(-(j - window) meV / (2 k_B T)), j = 0 .. 2 window, and
+ * the quantum of the products raw12[i] * f[j] (as or_quantise: q = 2^e,
+ * e = ceil(log2 kmax) - 53 + ceil(log2 n_ev)).  Returns -4 when a nonzero
+ * product would keep fewer than 10 significant bits, -1 on bad input. */
+int or_site_table(const double raw12[12], double T, int32_t window, uint64_t n_ev, double* f, double* q_out,
+                  double* max_rel)
+{
+    double kmax = 0.0, q, rmax = 0.0;
+    int i, e, ex;
+    int32_t j;
+    if (window < 0 || !(T > 0.0)) return -1;
+    for (j = 0; j <= 2 * window; j++) f[j] = exp(-((double)(j - window) * 1e-3) / (2.0 * KB_EV * T));
+    for (i = 0; i < 12; i++) {
+        if (!(raw12[i] >= 0.0) || isinf(raw12[i])) return -1;
+        if (raw12[i] > rmax) rmax = raw12[i];
+    }
+    *max_rel = 0.0;
+    *q_out = 0.0;
+    if (rmax == 0.0) return 0;
+    kmax = rmax * f[0];
+    if (n_ev < 1) n_ev = 1;
+    frexp(kmax, &ex);
+    if (ldexp(1.0, ex - 1) == kmax) ex = ex - 1;
+    e = ex - 53 + ceil_log2_u64(n_ev);
+    q = ldexp(1.0, e);
+    for (i = 0; i < 12; i++) {
+        if (raw12[i] == 0.0) continue;
+        for (j = 0; j <= 2 * window; j++) {
+            double k = raw12[i] * f[j], m = rint(k / q);
+            double rel = fabs(m * q - k) / k;
+            if (m < 1024.0) return -4;
+            if (rel > *max_rel) *max_rel = rel;
+        }
+    }
+    *q_out = q;
+    return 0;
+}
+
+/* Plain BKL (as or_advance_plain: same draws, clock and selection) with
+ * site-energy interactions.  Returns 0, or -4 when an event's |dE| exceeded
+ * the window (its rate was taken as 0; the call stops after that step, and
+ * the trajectory no longer follows the method). */
+int or_advance_plain_site(const or_geom* g, const double raw12[12], const double* f, double q,
+                          const uint8_t* fe, const or_site_params* sp, int8_t* occ, int32_t* disp,
+                          uint64_t* draws, double* t, double t_horizon, uint64_t n_hops, uint64_t hops[2])
+{
+    int64_t N = n_sites(g), s;
+    int n_slots = 0, rc = 0;
+    int64_t* slots;
+    step_ctx S;
+    site_ctx X;
+    uint32_t key[2], ctr[4];
+    uint64_t done = 0;
+    double t_end;
+    or_hops();
+    for (s = 0; s < N; s++) n_slots += (occ[s] == SP_V);
+    slots = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_slots > 0 ? n_slots : 1));
+    n_slots = 0;
+    for (s = 0; s < N; s++)
+        if (occ[s] == SP_V) slots[n_slots++] = s;
+    X.fe = fe; X.sp = sp; X.raw12 = raw12; X.f = f; X.q = q; X.err = 0;
+    S.g = g; S.k12 = NULL; S.occ = occ; S.disp = disp;
+    S.slot_site = slots; S.n_slots = n_slots; S.lo = NULL; S.hi = NULL; S.site = &X;
+    key[0] = g->seed; key[1] = g->lattice_id;
+    hops[0] = hops[1] = 0;
+    t_end = t_horizon > 0.0 ? *t + t_horizon : 0.0;
+    while (done < n_hops) {
+        int r;
+        double tau = *t;
+        ctr[0] = (uint32_t)*draws; ctr[1] = (uint32_t)(*draws >> 32);
+        ctr[2] = 0xFFFFFFFFu; ctr[3] = TAG_PLAIN;
+        r = bkl_step(&S, ctr, key, &tau, t_end, hops);
+        if (X.err) { rc = -4; break; }
+        if (r == 1) break;
+        *draws = *draws + 1;
+        if (r == 2) { *t = t_end; break; }
+        *t = tau;
+        done++;
+    }
+    free(slots);
+    return rc;
+}
+
+/* Rate of event d of the vacancy on site s under the site-energy model
+ * (0 when the target holds a vacancy; -1 when |dE| exceeds the window). */
+double or_site_rate(const or_geom* g, const double raw12[12], const double* f, double q, const uint8_t* fe,
+                    const or_site_params* sp, const int8_t* occ, int64_t s, int d)
+{
+    step_ctx S;
+    site_ctx X;
+    double k;
+    or_hops();
+    X.fe = fe; X.sp = sp; X.raw12 = raw12; X.f = f; X.q = q; X.err = 0;
+    S.g = g; S.k12 = NULL; S.occ = (int8_t*)occ; S.disp = NULL;
+    S.slot_site = NULL; S.n_slots = 0; S.lo = NULL; S.hi = NULL; S.site = &X;
+    k = event_rate(&S, s, d);
+    return X.err ? -1.0 : k;
 }

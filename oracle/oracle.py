@@ -39,6 +39,10 @@ class _Geom(C.Structure):
                 ("gb_period_cells", C.c_int32), ("gb_axes_mask", C.c_int32)]
 
 
+class _SiteParams(C.Structure):
+    _fields_ = [("e_fe", C.c_int32 * 4), ("e_vv", C.c_int32 * 6), ("window", C.c_int32)]
+
+
 class _Rates(C.Structure):
     _fields_ = [("nu", C.c_double), ("T", C.c_double), ("Ea_O", C.c_double),
                 ("Ea_H", C.c_double), ("E_z", C.c_double), ("q", C.c_double),
@@ -50,9 +54,11 @@ _lib = None
 
 
 def lib():
+    """The compiled oracle; FKMC_ORACLE_LIB names another build of the same
+    source (the sanitizer test loads an instrumented one)."""
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(os.environ.get("FKMC_ORACLE_LIB") or build())
         P = C.POINTER
         _lib.or_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
         _lib.or_ln.argtypes = [C.c_double]
@@ -82,6 +88,18 @@ def lib():
         _lib.or_hop_target.restype = C.c_int64
         _lib.or_is_gb_site.argtypes = [P(_Geom), C.c_int64]
         _lib.or_sub_block.argtypes = [P(_Geom), C.c_int, C.c_int, P(C.c_int32), P(C.c_int32)]
+        _lib.or_site_energy.argtypes = [P(_Geom), C.c_void_p, C.c_void_p, P(_SiteParams), C.c_int64,
+                                        C.c_int64]
+        _lib.or_site_energy.restype = C.c_int32
+        _lib.or_site_table.argtypes = [P(C.c_double), C.c_double, C.c_int32, C.c_uint64, P(C.c_double),
+                                       P(C.c_double), P(C.c_double)]
+        _lib.or_advance_plain_site.argtypes = [P(_Geom), P(C.c_double), P(C.c_double), C.c_double,
+                                               C.c_void_p, P(_SiteParams), C.c_void_p, C.c_void_p,
+                                               P(C.c_uint64), P(C.c_double), C.c_double, C.c_uint64,
+                                               P(C.c_uint64)]
+        _lib.or_site_rate.argtypes = [P(_Geom), P(C.c_double), P(C.c_double), C.c_double, C.c_void_p,
+                                      P(_SiteParams), C.c_void_p, C.c_int64, C.c_int]
+        _lib.or_site_rate.restype = C.c_double
     return _lib
 
 
@@ -158,6 +176,36 @@ def quantise(raw: np.ndarray, n_ev: int):
     if rc != 0:
         raise ValueError("rate quantisation failed (%d)" % rc)
     return o, q.value, rel.value
+
+
+@dataclass
+class SiteParams:
+    """Pair energies (meV) of the site-energy model: vacancy-Fe over the B-site
+    shells |r|^2 = 1, 5, 9, 13 (a/2)^2 and vacancy-vacancy over the O-site
+    shells 2, 4, 6, 8, 10, 16; window = largest |dE_site| (meV) of a hop."""
+    e_fe: tuple = (0, 0, 0, 0)
+    e_vv: tuple = (0, 0, 0, 0, 0, 0)
+    window: int = 1000
+
+    def c(self) -> _SiteParams:
+        p = _SiteParams()
+        p.e_fe[:] = [int(x) for x in self.e_fe]
+        p.e_vv[:] = [int(x) for x in self.e_vv]
+        p.window = int(self.window)
+        return p
+
+
+def site_table(raw12: np.ndarray, T: float, window: int, n_ev: int):
+    """(f, q, max_rel): f[j] = exp(-(j - window) meV/(2 k_B T)) and the
+    quantum of the products raw12[i] f[j]."""
+    raw12 = np.ascontiguousarray(raw12, dtype=np.float64)
+    f = np.zeros(2 * int(window) + 1)
+    q = C.c_double()
+    rel = C.c_double()
+    rc = lib().or_site_table(_dp(raw12), float(T), int(window), int(n_ev), _dp(f), C.byref(q), C.byref(rel))
+    if rc != 0:
+        raise ValueError("site rate table failed (%d)" % rc)
+    return f, q.value, rel.value
 
 
 # --------------------------------------------------------------------------- lattice
@@ -304,6 +352,46 @@ class Lattice:
         self.draws = d.value
         self.t = t.value
         self.hops += np.array([h[0], h[1]], dtype=np.uint64)
+        return (h[0], h[1])
+
+    # -- site-energy interactions (plain BKL only)
+    def set_site_model(self, fe: np.ndarray, sp: SiteParams, p: RateParams):
+        """Fe map (one byte per cell, canonical cell order, 1 = Fe on its B
+        site), pair energies and rate parameters of plain BKL with site
+        energies; the quantum follows the largest possible rate."""
+        L = self.g.L
+        self.fe = np.ascontiguousarray(fe, dtype=np.uint8).reshape(L[0] * L[1] * L[2])
+        self.sp = sp
+        self._spc = sp.c()
+        raw = absent_species_zeroed(rate_raw(p, self.g.a_angstrom), self.occ)
+        nv = int((self.occ == SP_V).sum())
+        n_ev = 8 * min(max(nv, 1), self.g.n_sites)
+        self.site_raw = raw
+        self.site_f, self.site_q, self.site_rel = site_table(raw, p.T, sp.window, n_ev)
+
+    def site_energy(self, s: int, skip: int = -1) -> int:
+        return lib().or_site_energy(C.byref(self._gc), self.occ.ctypes.data, self.fe.ctypes.data,
+                                    C.byref(self._spc), int(s), int(skip))
+
+    def site_rate(self, s: int, d: int) -> float:
+        return lib().or_site_rate(C.byref(self._gc), _dp(self.site_raw), _dp(self.site_f), self.site_q,
+                                  self.fe.ctypes.data, C.byref(self._spc), self.occ.ctypes.data, int(s), int(d))
+
+    def advance_plain_site(self, n_hops: int, t_horizon: float = 0.0):
+        """Plain BKL with site energies: same draws, clock and selection as
+        advance_plain."""
+        h = (C.c_uint64 * 2)()
+        d = C.c_uint64(self.draws)
+        t = C.c_double(self.t)
+        rc = lib().or_advance_plain_site(C.byref(self._gc), _dp(self.site_raw), _dp(self.site_f), self.site_q,
+                                         self.fe.ctypes.data, C.byref(self._spc), self.occ.ctypes.data,
+                                         self.disp.ctypes.data, C.byref(d), C.byref(t), float(t_horizon),
+                                         int(n_hops), h)
+        self.draws = d.value
+        self.t = t.value
+        self.hops += np.array([h[0], h[1]], dtype=np.uint64)
+        if rc != 0:
+            raise ValueError("site-energy difference outside the window (%d)" % rc)
         return (h[0], h[1])
 
     @property
