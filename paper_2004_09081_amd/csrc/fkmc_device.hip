@@ -680,6 +680,86 @@ __device__ __forceinline__ void scan_staged(const WaveLds& W, const TileGeo& G, 
     }
 }
 
+// 16-bit mask of the vacancy bytes of a 16-byte chunk (the only code with
+// bit 1 set): a product gathers bit 1 of the four bytes of a word into its
+// top nibble.
+__device__ __forceinline__ uint32_t vacancy_mask16(uint4 v)
+{
+    uint32_t m = (((v.x >> 1) & 0x01010101u) * 0x10204080u) >> 28;
+    m |= ((((v.y >> 1) & 0x01010101u) * 0x10204080u) >> 28) << 4;
+    m |= ((((v.z >> 1) & 0x01010101u) * 0x10204080u) >> 28) << 8;
+    m |= ((((v.w >> 1) & 0x01010101u) * 0x10204080u) >> 28) << 12;
+    return m;
+}
+
+// Slots of the entries [0, n) of a group's vacancy list (tile k, chunk c of
+// its staged footprint, byte b: k << 28 | c << 4 | b), one entry per lane:
+// site, canonical key, append to tile k's slot list (entries
+// [k*cap, k*cap + cap), counter cnt[k]).
+__device__ __forceinline__ void group_slots(const WaveLds& W, const TileRec* R, const uint32_t* ent, int n,
+                                            int fp, int fps, int L0, int L1, int L2, int cap, int lane)
+{
+    for (int e = lane; e < n; e += 64) {
+        const uint32_t x = ent[e];
+        const int k = (int)(x >> 28), c = (int)((x >> 4) & 0xFFFFFFu), b = (int)(x & 15u);
+        TileGeo G = tile_geo_rec(R[k]);
+        tile_lds_at(G, fp + k * fps);
+        int n0, n1, n2, n3, cj;
+        seg_chunks(G, n0, n1, n2, n3);
+        const int sg = locate_chunk(c, n0, n1, n2, cj);
+        const int li = 16 * cj + b - (int)(seg_st(G, sg) & 15);
+        if (li < 0 || li >= seg_len(G, sg)) continue;
+        int lx, ly, lz, t;
+        seg_site(G, sg, li, lx, ly, lz, t);
+        put_slot(W, G, L0, L1, L2, k, k * cap, cap, lx, ly, lz, t, -1);
+    }
+}
+
+// Vacancies of the nt staged footprints of a group (tile k at LDS offset
+// fp + k*fps, records R): every lane tests 16-byte chunks of all the
+// footprints; the vacancy bytes found go to a compact list (W.xyz, not in
+// use until the slots are sorted), which the whole wave then decodes one
+// entry per lane.  The result equals scan_staged on each tile.
+__device__ __forceinline__ void scan_group(const WaveLds& W, const TileRec* R, const unsigned char* occl,
+                                           int nt, int fp, int fps, int L0, int L1, int L2, int cap, int lane)
+{
+    uint32_t* ent = W.xyz;  // 128 entries
+    int n = 0;              // wave-uniform
+    for (int k = 0; k < nt; k++) {
+        TileGeo G = tile_geo_rec(R[k]);
+        tile_lds_at(G, fp + k * fps);
+        int n0, n1, n2, n3;
+        seg_chunks(G, n0, n1, n2, n3);
+        const int total = n0 + n1 + n2 + n3;
+        const int base = G.lds0 - (int)(G.st0 & 15);
+        for (int c0 = 0; c0 < total; c0 += 64) {
+            const int c = c0 + lane;
+            uint32_t m = 0;
+            if (c < total) m = vacancy_mask16(*(const uint4*)(occl + base + 16 * c));
+            for (;;) {
+                const bool has = m != 0;
+                const uint64_t mk = __ballot(has);
+                if (mk == 0) break;
+                if (has) {
+                    const int pos = n + (int)__builtin_amdgcn_mbcnt_hi(
+                                            (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                    ent[pos] = ((uint32_t)k << 28) | ((uint32_t)c << 4) | (uint32_t)(__ffs(m) - 1);
+                    m &= m - 1;
+                }
+                n += __popcll(mk);
+                if (n > 64) {
+                    wave_lds_fence();
+                    group_slots(W, R, ent, n, fp, fps, L0, L1, L2, cap, lane);
+                    wave_lds_fence();
+                    n = 0;
+                }
+            }
+        }
+    }
+    wave_lds_fence();
+    group_slots(W, R, ent, n, fp, fps, L0, L1, L2, cap, lane);
+}
+
 // Issue the 16-byte HBM->LDS copies of a tile's footprint straight into LDS
 // (no registers): wave instruction i fills chunks [64 i, 64 i + 64).
 __device__ __forceinline__ void stage_footprint(const TileGeo& G, const int8_t* occ_lat,
@@ -1087,7 +1167,24 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
     }
     if (lane < 16) W.cnt[lane] = 0;
     wave_lds_fence();
-    const RateCtx C = {D.L[0], D.L[1], D.L[2], D.gb_period, D.gb_mask, W.k12};
+    // boundary planes: when no footprint of the group reaches a plane cell
+    // (cells [o, o + w] along a masked axis, the +face included), every
+    // boundary flag of its edges is 0 and the rates skip the test
+    bool gb_live = false;
+    if (D.gb_period > 0) {
+        bool hit = false;
+        if (lane < nt) {
+            const TileRec& T = R[lane];
+            const int o[3] = {T.ox, T.oy, T.oz}, w[3] = {T.wx, T.wy, T.wz};
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                const int hi = o[a] + w[a];
+                hit |= ((D.gb_mask >> a) & 1) && (hi >= D.L[a] || (hi / D.gb_period) * D.gb_period >= o[a]);
+            }
+        }
+        gb_live = __ballot(hit) != 0;
+    }
+    const RateCtx C = {D.L[0], D.L[1], D.L[2], gb_live ? D.gb_period : 0, D.gb_mask, W.k12};
     int n_seg = 0;
     if (!single) {
         if (resident) {
@@ -1100,11 +1197,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
             }
             __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the staged footprints have landed
             __builtin_amdgcn_wave_barrier();
-            for (int k = 0; k < nt; k++) {
-                TileGeo T = tile_geo_rec(R[k]);
-                tile_lds_at(T, fp + k * fps);
-                scan_staged(W, T, lds0, D.L[0], D.L[1], D.L[2], k, k * S, S, lane);
-            }
+            scan_group(W, R, lds0, nt, fp, fps, D.L[0], D.L[1], D.L[2], S, lane);
         }
         wave_lds_fence();
         // this lane's tile

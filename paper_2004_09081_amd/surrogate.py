@@ -200,14 +200,15 @@ def label_fragment_edge(L: int) -> int:
 
 def run_cfg5(n_train: int = 4096, n_test: int = 512, cycles: int = 2000, members: int = 5,
              steps: int = 6000, batch: int = 256, threshold: float = 0.1, frag=label_fragment_edge,
-             chunk: int = 512, log=None, L_range=None):
+             chunk: int = 512, log=None, L_range=None, detail: bool = False):
     """Train the ensemble on kMC labels of n_train lattices drawn from the
     ensemble workload's parameter distribution (own key stream), evaluate on
     n_test held-out lattices (another stream): MAE of served answers against
     kMC, served fraction, and time-to-answer with and without the surrogate.
     Every run lasts `cycles` synchronisation windows (about that many hops
     per vacancy), so a label depends on the four inputs and not on the
-    lattice size."""
+    lattice size.  With detail, the report also holds the per-query
+    answers, the served mask and the kMC labels with their masks."""
     hops = 0
     from . import workloads as W
     say = log or (lambda *a: None)
@@ -253,7 +254,7 @@ def run_cfg5(n_train: int = 4096, n_test: int = 512, cycles: int = 2000, members
     mae = float(err[ok].mean()) if ok.any() else float("nan")
     mae_o = float(err[:, 0][ok[:, 0]].mean()) if ok[:, 0].any() else float("nan")
     mae_h = float(err[:, 1][ok[:, 1]].mean()) if ok[:, 1].any() else float("nan")
-    return {
+    rep = {
         "mae_log10D": mae, "mae_log10D_O": mae_o, "mae_log10D_H": mae_h,
         "served_fraction": float(served.mean()), "fallbacks": n_fb,
         "label_coverage": [float(Mtr[:, 0].mean()), float(Mtr[:, 1].mean())],
@@ -264,3 +265,6 @@ def run_cfg5(n_train: int = 4096, n_test: int = 512, cycles: int = 2000, members
         "threshold_decades": threshold, "label_time_s": t_labels, "train_time_s": t_train,
         "final_loss": [float(x) for x in loss],
     }
+    if detail:
+        rep.update(answers=ans, served=served, kmc=Yte, kmc_mask=Mte)
+    return rep

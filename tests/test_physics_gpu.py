@@ -152,11 +152,12 @@ def test_cfg3_drift_and_diffusion_tensor():
     H, 0.75 eV, 450 K, E_z 1e7 V/m, +0.3 eV z-planes every 50 cells,
     16^3-cell fragments, t_sync 1/(8 k_O)) advanced by at least 1e8 hops:
     the sums obey N_V <r_V> = -N_O <r_O> exactly (every hop moves the
-    vacancy by h and an O by -h), so v_O = -(N_V/N_O) v_V; the vacancy
-    drift matches the exact drift of the single-vacancy chain projected on
-    the z layers of one 50-cell period within 3 sigma plus 3 % (the rest is
-    vacancy blocking and the one-hop-per-cycle splitting); the transverse
-    drift is zero within 4 sigma; and the D tensor is reported."""
+    vacancy by h and an O by -h), so v_O = -(N_V/N_O) v_V; the mean vacancy
+    drift over the run matches the exact transient drift of one vacancy on
+    the chain of z layers of one 50-cell period (from the same uniform
+    start, over the same time) within 3 sigma plus 1 % (the rest is vacancy
+    blocking and the one-hop-per-cycle splitting); the transverse drift is
+    zero within 4 sigma; and the D tensor is reported."""
     from scipy.linalg import null_space
     from paper_2004_09081_amd import fkmc as F
     from paper_2004_09081_amd import workloads as W
@@ -175,20 +176,27 @@ def test_cfg3_drift_and_diffusion_tensor():
     t = st["t"]
     vV = st["drift"][2] * 1e-10   # m/s
     vO = st["drift"][0] * 1e-10
-    assert abs(vO + nV / nO * vV) <= 1e-12 * abs(vV)
+    assert np.allclose(vO, -nV / nO * vV, rtol=1e-12, atol=0.0)
     # statistical error of the mean vacancy displacement along each axis
     n = float(nV)
     mean = st["sum_r"][2] / n
     var = np.array([st["sum_rr"][2][a] for a in range(3)]) / n - mean ** 2
     se_v = np.sqrt(var / n) * (A / 2) * 1e-10 / t
-    # exact drift of one vacancy on the ring of z layers (doubled units) of one period
+    # exact mean z displacement at time t of one vacancy on the ring of z
+    # layers (doubled units) of one boundary period, from the uniform start
+    # (layers with Z odd hold two sites per cell, even one): the first
+    # derivative at 0 of p0 exp(t Q(lam)) 1, Q(lam) tilting each rate by
+    # exp(lam dz); within this time a vacancy drifts a few cells and seldom
+    # meets a plane, so the transient, not the long-time drift, applies
     kp = lambda up, g: brute.arrhenius(1e13, sp.Ea_O, sp.T, sp.E_z, sp.q, 0.5 if up else -0.5, A,
                                        gb=sp.gb_dE if g else 0.0)
     nz = 2 * sp.gb_period
     Q = np.zeros((nz, nz))
+    dz = np.zeros((nz, nz))
     gb_layer = lambda Z: Z % 2 == 0 and (Z // 2) % sp.gb_period == 0
     for Z in range(nz):
         up, dn = (Z + 1) % nz, (Z - 1) % nz
+        dz[Z, up], dz[Z, dn] = 1.0, -1.0
         if Z % 2:
             Q[Z, up] += 2 * kp(True, gb_layer(up))
             Q[Z, dn] += 2 * kp(False, gb_layer(dn))
@@ -196,12 +204,19 @@ def test_cfg3_drift_and_diffusion_tensor():
             Q[Z, up] += 4 * kp(True, gb_layer(Z))
             Q[Z, dn] += 4 * kp(False, gb_layer(Z))
     Q -= np.diag(Q.sum(1))
-    pi = null_space(Q.T)[:, 0]
-    pi /= pi.sum()
-    v_ref = sum(pi[Z] * (Q[Z, (Z + 1) % nz] - Q[Z, (Z - 1) % nz]) for Z in range(nz)) * A / 2 * 1e-10
+    p0 = np.array([2.0 if Z % 2 else 1.0 for Z in range(nz)])
+    p0 /= p0.sum()
+
+    def mgf(lam):
+        M = Q * np.exp(lam * dz)
+        np.fill_diagonal(M, np.diag(Q))
+        return float(p0 @ brute.propagate(M, t) @ np.ones(nz))
+    lam = 1e-4
+    m1 = (mgf(lam) - mgf(-lam)) / (2 * lam)
+    v_ref = m1 * (A / 2) * 1e-10 / t
     say("  %d hops, t = %.4g s: v_V = (%.3g, %.3g, %.5g) m/s (+- %.2g), chain %.5g m/s (%+.2f %%); "
         "v_O z %.4g m/s" % (int(st["hops"].sum()), t, vV[0], vV[1], vV[2], se_v[2], v_ref,
                             100 * (vV[2] / v_ref - 1), vO[2]))
     say("  D tensor of V (A^2/s, xx yy zz xy xz yz): %s" % np.array2string(st["Dtensor"][2], precision=4))
-    assert abs(vV[2] - v_ref) < 3 * se_v[2] + 0.03 * abs(v_ref)
+    assert abs(vV[2] - v_ref) < 3 * se_v[2] + 0.01 * abs(v_ref)
     assert abs(vV[0]) < 4 * se_v[0] and abs(vV[1]) < 4 * se_v[1]
