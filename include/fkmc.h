@@ -197,6 +197,39 @@ fkmc_status fkmc_set_rates(fkmc_lattice* lat, const fkmc_rate_params* params);
 /* Same quantisation applied to a caller-supplied raw table of lattice i. */
 fkmc_status fkmc_set_rate_table(fkmc_lattice* lat, uint32_t i, const double* k12, size_t n);
 
+/* Site-energy interactions (Sec. "Oxygen vacancy diffusion with dopant and
+ * defect interaction", with the pair energies of its Table TABLEadd01 as
+ * inputs), for plain lattices of at least 5 cells per axis with at most 2048
+ * vacancies.  The rate of a hop becomes
+ * k = nu exp(-(Ea_X + dE/2 + g dE_gb + dE_site/2)/(k_B T)) with dE_site the
+ * vacancy's site energy at the target minus that at its origin.  The site
+ * energy of an anion site sums integer pair energies (meV) over the Fe
+ * dopants on B sites (cube centres) at squared distance 1, 5, 9, 13 (a/2)^2
+ * (e_fe[0..3]) and over the other vacancies at 2, 4, 6, 8, 10, 16 (a/2)^2
+ * (e_vv[0..5]); the hopping vacancy does not interact with itself.  Every
+ * possible rate, |dE_site| <= window_meV (0..2047), is tabulated as
+ * quantise(k_Arrhenius x exp(-dE_site/(2 k_B T))) with the quantum of the
+ * largest (FKMC_E_RANGE when a rate would keep fewer than 10 bits: narrow
+ * the window).  A hop whose |dE_site| exceeds the window sets FKMC_E_RANGE
+ * (the event counted as impossible; the trajectory no longer follows the
+ * method).  Draws, clock and selection are plain BKL's (fkmc_advance), so
+ * with all pair energies zero the run equals plain BKL bit for bit.
+ * Returns the bytes of the caller-owned device buffer that holds lattice
+ * i's Fe bitmap and rate table for a given window. */
+fkmc_status fkmc_site_model_bytes(const fkmc_lattice* lat, uint32_t i, int32_t window_meV, size_t* bytes);
+
+/* Enable site energies on plain lattice i: fe (host, L0 L1 L2 bytes in
+ * canonical cell order (k L1 + j) L0 + i, 1 = Fe on that cell's B site),
+ * pair energies and window as above, dev a caller-owned device buffer of
+ * fkmc_site_model_bytes bytes (256-byte aligned) that must outlive the
+ * model.  Call after fkmc_set_rates (FKMC_E_STATE otherwise; the table
+ * uses those parameters); fkmc_set_rates, fkmc_set_rate_table,
+ * fkmc_init_random, fkmc_set_occupancy and fkmc_restore remove it.
+ * FKMC_E_UNSUPPORTED for fragment lattices, L < 5 or more than 2048
+ * vacancies; fkmc_advance_atomic refuses such lattices. */
+fkmc_status fkmc_set_site_model(fkmc_lattice* lat, uint32_t i, const uint8_t* fe, const int32_t e_fe[4],
+                                const int32_t e_vv[6], int32_t window_meV, void* dev, size_t bytes);
+
 /* Current quantised table of lattice i (12 doubles). */
 fkmc_status fkmc_get_rate_table(const fkmc_lattice* lat, uint32_t i, double* k12, size_t n);
 

@@ -183,6 +183,7 @@ struct Layout {
     std::vector<int64_t> occ_off, disp_off;
     size_t o_desc, o_call, o_state, o_buckets, o_stat, o_counts, o_plain, o_batch, o_tile2lat, o_tiles, o_bounds, o_c2s, o_groups;
     size_t o_stage;          // canonical-order transfers: stage_sites bytes, then stage_sites int32x3
+    size_t o_site;           // ids of the plain lattices with site energies
     int64_t stage_sites;
     int32_t n_tiles;
     std::vector<std::vector<int32_t>> bounds[3];
@@ -230,6 +231,7 @@ Layout plan(const fkmc_geometry* g, uint32_t n)
     Y.o_bounds = take((size_t)nb * sizeof(int32_t));
     Y.o_c2s = take((size_t)nc * sizeof(int32_t));
     Y.o_groups = take((size_t)std::max(tiles, 1) * sizeof(int2));
+    Y.o_site = take((size_t)n * sizeof(int32_t));
     Y.stage_sites = (int64_t)std::min<uint64_t>(maxN, (uint64_t)kStageSites);
     Y.o_stage = take(align_up((size_t)Y.stage_sites, 16) + (size_t)Y.stage_sites * 12);
     Y.work_bytes = w;
@@ -329,6 +331,9 @@ struct fkmc_lattice {
     std::vector<uint64_t> cost_ticks;
     uint64_t cost_shape[2] = {0, 0};       // (max_cycles, min_hops) of those calls
     int static_dev = -1;                   // fkmc_create_static: device whose scratch it holds
+    std::vector<fkmc_rate_params> params;  // last fkmc_set_rates parameters
+    std::vector<char> have_params;         // 0 after fkmc_set_rate_table
+    int32_t* d_site_ids = nullptr;
 };
 
 // Work space of fkmc_create_static: one array per device, for callers that
@@ -376,6 +381,8 @@ fkmc_status read_states(fkmc_lattice* L)
     for (uint32_t i = 0; i < L->n; i++)
         if (L->h_state[i].err & 1u)
             return fail(FKMC_E_RANGE, "lattice %u: too many vacancies in one BKL domain", i);
+        else if (L->h_state[i].err & 4u)
+            return fail(FKMC_E_RANGE, "lattice %u: a hop's site-energy difference exceeds the window", i);
     return FKMC_OK;
 }
 
@@ -459,6 +466,8 @@ static fkmc_status create_impl(const fkmc_geometry* geoms, uint32_t n, const fkm
     L->call.resize(n);
     L->qstep.assign(n, 0.0);
     L->qrel.assign(n, 0.0);
+    L->params.assign(n, fkmc_rate_params{});
+    L->have_params.assign(n, 0);
     L->static_dev = static_dev;
     if (static_dev >= 0) {
         L->h_state = new LatState[n];
@@ -479,6 +488,7 @@ static fkmc_status create_impl(const fkmc_geometry* geoms, uint32_t n, const fkm
             D.nsb[a] = (int32_t)Y.bounds[a][i].size() - 1;
         }
         D.plain = is_plain(g) ? 1 : 0;
+        D.site_window = -1;
         for (int a = 0; a < 3; a++) {
             D.nf[a] = D.plain ? 1 : D.nsb[a] / 2;
             D.F[a] = (D.plain || g.frag[a] >= g.L[a]) ? g.L[a] : g.frag[a];
@@ -523,6 +533,7 @@ static fkmc_status create_impl(const fkmc_geometry* geoms, uint32_t n, const fkm
     L->P.n_tiles = Y.n_tiles;
     L->d_plain_ids = (int32_t*)(w + Y.o_plain);
     L->d_batch_ids = (int32_t*)(w + Y.o_batch);
+    L->d_site_ids = (int32_t*)(w + Y.o_site);
     L->P.batch_ids = L->d_batch_ids;
     L->P.fp_stride = fps;
     L->d_groups = (int2*)(w + Y.o_groups);
@@ -676,6 +687,7 @@ fkmc_status fkmc_init_random(fkmc_lattice* L, const uint64_t* n_vac, const uint6
         L->phase_group = 0;
         L->n_o[i] = (uint64_t)L->desc[i].n_sites - n_vac[i] - n_h[i];
         L->rates_ok[i] = 0;
+        L->desc[i].site_window = -1;
     }
     return FKMC_OK;
 }
@@ -713,6 +725,7 @@ fkmc_status fkmc_set_occupancy(fkmc_lattice* L, uint32_t i, const int8_t* host, 
     L->phase_group = 0;
     L->n_o[i] = N - nv - nh;
     L->rates_ok[i] = 0;
+    L->desc[i].site_window = -1;
     return FKMC_OK;
 }
 
@@ -754,13 +767,113 @@ fkmc_status fkmc_set_rates(fkmc_lattice* L, const fkmc_rate_params* params)
         }
         L->desc[i].gb_period = p.gb_period_cells;
         L->desc[i].gb_mask = p.gb_axes_mask;
+        L->desc[i].site_window = -1;
     }
     fkmc_status s = upload_desc(L);
     if (s) {
         L->desc = backup;
         return s;
     }
-    for (uint32_t i = 0; i < L->n; i++) L->rates_ok[i] = 1;
+    for (uint32_t i = 0; i < L->n; i++) {
+        L->rates_ok[i] = 1;
+        L->params[i] = params[i];
+        L->have_params[i] = 1;
+    }
+    return FKMC_OK;
+}
+
+// Site-energy model buffer of lattice i: Fe bitmap (one bit per cell, 32-bit
+// words), padded to 256 bytes, then 12 (2 window + 1) quantised rates.
+static size_t site_fe_bytes(const fkmc_geometry& g)
+{
+    const uint64_t cells = (uint64_t)g.L[0] * g.L[1] * g.L[2];
+    return align_up((size_t)((cells + 31) / 32) * 4, 256);
+}
+
+fkmc_status fkmc_site_model_bytes(const fkmc_lattice* L, uint32_t i, int32_t window_meV, size_t* bytes)
+{
+    if (!L || !bytes) return fail(FKMC_E_INVALID, "null argument");
+    if (i >= L->n) return fail(FKMC_E_INVALID, "lattice index %u out of range", i);
+    if (window_meV < 0 || window_meV > kMaxSiteWindow)
+        return fail(FKMC_E_INVALID, "window %d meV outside 0..%d", window_meV, kMaxSiteWindow);
+    *bytes = site_fe_bytes(L->geo[i]) + (size_t)12 * (2 * window_meV + 1) * sizeof(double);
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_set_site_model(fkmc_lattice* L, uint32_t i, const uint8_t* fe, const int32_t e_fe[4],
+                                const int32_t e_vv[6], int32_t window_meV, void* dev, size_t bytes)
+{
+    if (!L || !fe || !e_fe || !e_vv || !dev) return fail(FKMC_E_INVALID, "null argument");
+    size_t need = 0;
+    fkmc_status st = fkmc_site_model_bytes(L, i, window_meV, &need);
+    if (st) return st;
+    const fkmc_geometry& g = L->geo[i];
+    if (!L->desc[i].plain) return fail(FKMC_E_UNSUPPORTED, "lattice %u: site energies need a plain lattice", i);
+    for (int a = 0; a < 3; a++)
+        if (g.L[a] < 5) return fail(FKMC_E_UNSUPPORTED, "lattice %u: site energies need L >= 5 cells", i);
+    if (L->n_vac[i] > (uint64_t)kMaxSiteSlots)
+        return fail(FKMC_E_UNSUPPORTED, "lattice %u: %llu vacancies, site energies hold %d", i,
+                    (unsigned long long)L->n_vac[i], kMaxSiteSlots);
+    if (!L->rates_ok[i] || !L->have_params[i])
+        return fail(FKMC_E_STATE, "lattice %u: set the rates with fkmc_set_rates first", i);
+    if (bytes < need || ((uintptr_t)dev & 255)) return fail(FKMC_E_NOMEM, "site buffer: need %zu bytes, 256-aligned", need);
+    const uint64_t cells = (uint64_t)g.L[0] * g.L[1] * g.L[2];
+    std::vector<uint32_t> bits((size_t)((cells + 31) / 32), 0u);
+    for (uint64_t c = 0; c < cells; c++) {
+        if (fe[c] > 1) return fail(FKMC_E_INVALID, "Fe map value %d at cell %llu", fe[c], (unsigned long long)c);
+        if (fe[c]) bits[c >> 5] |= 1u << (c & 31);
+    }
+    // rates: quantised products of the Arrhenius rates (absent species
+    // zeroed) and exp(-dE/(2 k_B T)), quantum from the largest product
+    const fkmc_rate_params& p = L->params[i];
+    double raw[12];
+    raw_rates(p, g.a_angstrom, raw);
+    if (L->n_o[i] == 0)
+        for (int e = 0; e < 6; e++) raw[e] = 0.0;
+    if (L->n_h[i] == 0)
+        for (int e = 6; e < 12; e++) raw[e] = 0.0;
+    const int W = window_meV, WW = 2 * window_meV + 1;
+    std::vector<double> f((size_t)WW), table((size_t)12 * WW, 0.0);
+    for (int j = 0; j < WW; j++) f[j] = std::exp(-((double)(j - W) * 1e-3) / (2.0 * kKB * p.T));
+    double rmax = 0.0;
+    for (int e = 0; e < 12; e++) rmax = std::max(rmax, raw[e]);
+    if (rmax > 0.0) {
+        const double kmax = rmax * f[0];
+        uint64_t n_ev = 8ull * std::min<uint64_t>(std::max<uint64_t>(L->n_vac[i], 1), (uint64_t)L->desc[i].n_sites);
+        int ex;
+        std::frexp(kmax, &ex);
+        if (std::ldexp(1.0, ex - 1) == kmax) ex -= 1;
+        int lg = 0;
+        while ((1ull << lg) < n_ev) lg++;
+        const double q = std::ldexp(1.0, ex - 53 + lg);
+        for (int e = 0; e < 12; e++) {
+            if (raw[e] == 0.0) continue;
+            for (int j = 0; j < WW; j++) {
+                const double k = raw[e] * f[j];
+                const double m = std::rint(k / q);
+                if (m < 1024.0)
+                    return fail(FKMC_E_RANGE, "lattice %u: rate %g at dE %d meV keeps fewer than 10 bits at "
+                                "quantum %g (narrow the window)", i, k, j - W, q);
+                table[(size_t)e * WW + j] = m * q;
+            }
+        }
+    }
+    char* d = (char*)dev;
+    HIP_OK(hipMemcpyAsync(d, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, L->stream));
+    HIP_OK(hipMemcpyAsync(d + site_fe_bytes(g), table.data(), table.size() * sizeof(double), hipMemcpyHostToDevice,
+                          L->stream));
+    LatDesc backup = L->desc[i];
+    LatDesc& D = L->desc[i];
+    D.site_window = W;
+    for (int k = 0; k < 4; k++) D.site_e_fe[k] = e_fe[k];
+    for (int k = 0; k < 6; k++) D.site_e_vv[k] = e_vv[k];
+    D.site_fe = (const uint32_t*)d;
+    D.site_table = (const double*)(d + site_fe_bytes(g));
+    st = upload_desc(L);
+    if (st) {
+        L->desc[i] = backup;
+        return st;
+    }
     return FKMC_OK;
 }
 
@@ -771,12 +884,14 @@ fkmc_status fkmc_set_rate_table(fkmc_lattice* L, uint32_t i, const double* k12, 
     LatDesc backup = L->desc[i];
     fkmc_status s = set_table(L, i, k12);
     if (s) return s;
+    L->desc[i].site_window = -1;
     s = upload_desc(L);
     if (s) {
         L->desc[i] = backup;
         return s;
     }
     L->rates_ok[i] = 1;
+    L->have_params[i] = 0;
     return FKMC_OK;
 }
 
@@ -990,11 +1105,12 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
     // Plain lattices that fit run in LDS in the persistent kernel (with the
     // fragment lattices when those use it); the others keep the HBM kernel.
     const bool persist = any_frag && max_cycles > 0 && use_persistent(L);
-    std::vector<int32_t> ids, slow;
+    std::vector<int32_t> ids, slow, site;
     if (persist) ids = L->batch_ids;
     for (int32_t i : L->plain_ids) {
         L->desc[i].resident = 0;
-        if (plain_lds_fits(L, (uint32_t)i)) ids.push_back(i);
+        if (L->desc[i].site_window >= 0) site.push_back(i);
+        else if (plain_lds_fits(L, (uint32_t)i)) ids.push_back(i);
         else slow.push_back(i);
     }
     // Order of the persistent launch (results do not depend on it): once
@@ -1030,9 +1146,12 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
             HIP_OK(hipMemcpyAsync(L->d_batch_ids, L->launch_ids.data(), ids.size() * 4, hipMemcpyHostToDevice,
                                   L->stream));
     }
+    if (!site.empty())
+        HIP_OK(hipMemcpyAsync(L->d_site_ids, site.data(), site.size() * 4, hipMemcpyHostToDevice, L->stream));
     fkmc_status s = prepare_call(L, t_sync, max_cycles, min_hops, true);
     if (s) return s;
     LAUNCH_OK(launch_plain(L->P, L->d_plain_ids, (int)slow.size(), L->stream));
+    LAUNCH_OK(launch_plain_site(L->P, L->d_site_ids, (int)site.size(), L->stream));
     size_t ev_used = 0;
     if (L->timing && any_frag && L->ev.empty()) {
         L->ev.resize(2 * 2048);
@@ -1232,6 +1351,7 @@ fkmc_status fkmc_restore(fkmc_lattice* L, uint32_t i, const void* host, size_t b
     s = upload_desc(L);
     if (s) return s;
     L->rates_ok[i] = h.rates_ok;
+    L->have_params[i] = 0;
     return FKMC_OK;
 }
 
@@ -1251,6 +1371,8 @@ fkmc_status fkmc_advance_atomic(fkmc_lattice* L, uint32_t n_frg, uint64_t n_stag
     for (uint32_t i = 0; i < L->n; i++) {
         if (!L->rates_ok[i]) return fail(FKMC_E_STATE, "lattice %u: rates not set", i);
         const fkmc_geometry& g = L->geo[i];
+        if (L->desc[i].site_window >= 0)
+            return fail(FKMC_E_UNSUPPORTED, "lattice %u: the atom-selection scheme has no site energies", i);
         if (!L->desc[i].plain)
             return fail(FKMC_E_UNSUPPORTED, "lattice %u: the atom-selection scheme runs unfragmented lattices", i);
         const int64_t b = plain_lds_bytes(L, i);

@@ -2540,7 +2540,7 @@ __device__ __forceinline__ bool plain_adjacent(const LatDesc& D, uint64_t a, uin
 // cell/type positions (at most kMaxPlainSlots are stored); every thread of
 // the workgroup calls it and gets the vacancy count.
 __device__ int plain_collect_slots(const LatDesc& D, const DevPtrs& P, uint64_t* slots, int* wcount,
-                                   int* n_sh, int tid)
+                                   int* n_sh, int tid, int cap = kMaxPlainSlots)
 {
     const int lane = tid & 63, wv = tid >> 6;
     constexpr int NW = kPlainThreads / 64;
@@ -2567,7 +2567,7 @@ __device__ int plain_collect_slots(const LatDesc& D, const DevPtrs& P, uint64_t*
         for (int w = 0; w < wv; w++) before += wcount[w];
         if (v) {
             const int r = before + __popcll(mk & ((1ull << lane) - 1ull));
-            if (r < kMaxPlainSlots) slots[r] = pk;
+            if (r < cap) slots[r] = pk;
         }
         __syncthreads();
         if (tid == 0) {
@@ -2737,6 +2737,323 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
         __syncthreads();
     }
     if (tid == 0) {
+        S->t = t;
+        S->draws = draws;
+        S->hops[0] += ho;
+        S->hops[1] += hh;
+        S->busy_ticks = __builtin_amdgcn_s_memrealtime() - t_begin;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Plain BKL with site-energy interactions (Sec. "Oxygen vacancy diffusion
+// with dopant and defect interaction", Table TABLEadd01): the hop rate is
+// k = A exp(-(Ea + dE_site/2 + field and boundary terms)/(k_B T)), with
+// dE_site the vacancy's site energy at the target (without itself at the
+// origin) minus that at the origin.  A site energy sums the pair energies
+// (integers in meV) of the Fe dopants on B sites within squared doubled
+// distance 1, 5, 9, 13 and of the other vacancies on O sites within 2, 4, 6,
+// 8, 10, 16.  The host tabulates every rate as the quantised product of the
+// Arrhenius rate and exp(-dE/(2 k_B T)) for |dE| <= window, so sums stay
+// exact and a rate is one table entry.  One workgroup per lattice, the
+// occupancy in HBM; per vacancy slot the LDS holds its position, its total
+// rate and the table indices of its 8 events.  A slot's events are
+// evaluated by the whole workgroup: 9 site energies (origin and 8 targets)
+// over 92 lattice points each, summed with LDS integer atomics.  After a hop
+// only the slots within squared doubled distance 29 of its two sites (the
+// reach of an energy change onto a slot's origin or targets) are evaluated
+// again.  Draws, clock and selection are those of plain BKL (k_plain).
+constexpr int kSiteOffsets = 96;  // interacting lattice points around an anion site (92)
+
+__device__ __forceinline__ int site_shell(bool bsite, int n)
+{
+    if (bsite) return n == 1 ? 0 : (n == 5 ? 1 : (n == 9 ? 2 : (n == 13 ? 3 : -1)));
+    return n == 2 ? 0 : (n == 4 ? 1 : (n == 6 ? 2 : (n == 8 ? 3 : (n == 10 ? 4 : (n == 16 ? 5 : -1)))));
+}
+
+__device__ __forceinline__ int wrap2(int v, int L2)
+{
+    v = v < 0 ? v + L2 : v;
+    return v >= L2 ? v - L2 : v;
+}
+
+// Squared doubled distance between two packed plain positions (minimum image).
+__device__ __forceinline__ int plain_dist2(const LatDesc& D, uint64_t a, uint64_t b)
+{
+    const int ta = (int)(a >> 48), tb = (int)(b >> 48);
+    int d[3];
+    d[0] = (2 * (int)(a & 0xffff) + (ta != 0)) - (2 * (int)(b & 0xffff) + (tb != 0));
+    d[1] = (2 * (int)((a >> 16) & 0xffff) + (ta != 1)) - (2 * (int)((b >> 16) & 0xffff) + (tb != 1));
+    d[2] = (2 * (int)((a >> 32) & 0xffff) + (ta != 2)) - (2 * (int)((b >> 32) & 0xffff) + (tb != 2));
+    int r = 0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        int v = d[k] < 0 ? -d[k] : d[k];
+        const int L2 = 2 * D.L[k];
+        v = v > L2 - v ? L2 - v : v;
+        r += v * v;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(kPlainThreads) void k_plain_site(DevPtrs P, const int32_t* ids)
+{
+    extern __shared__ __align__(16) unsigned char psm[];
+    uint64_t* slots = (uint64_t*)psm;                           // [kMaxSiteSlots]
+    double* stot = (double*)(psm + 8 * kMaxSiteSlots);          // [kMaxSiteSlots]
+    uint16_t* eidx = (uint16_t*)(psm + 16 * kMaxSiteSlots);     // [kMaxSiteSlots][8]
+    uint16_t* offs = (uint16_t*)(psm + 32 * kMaxSiteSlots);     // [3][kSiteOffsets]
+    __shared__ int wcount[kPlainThreads / 64];
+    __shared__ double wsum[kPlainThreads / 64];
+    __shared__ uint64_t wmask[kPlainThreads / 64];
+    __shared__ uint64_t wnz[kPlainThreads / 64];
+    __shared__ int n_sh, ev_sh, hop_slot, n_off[3], Eacc[9], tsp[8], tcol[8], n_aff, err_sh;
+    __shared__ uint64_t hop_s, hop_t, tpk[8];
+    __shared__ int16_t aff[kPlainThreads];
+    const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
+    const int lat = ids[blockIdx.x];
+    const LatDesc& D = P.desc[lat];
+    LatState* S = P.state + lat;
+    const LatCall* C = P.call + lat;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = kPlainThreads / 64;
+    const int W = D.site_window;
+    const int WW = 2 * W + 1;
+    const int8_t* occ = P.occ + D.occ_off;
+
+    // interacting lattice points of each anion type (order is irrelevant: integer sums)
+    if (tid < 3) n_off[tid] = 0;
+    if (tid == 0) err_sh = 0;
+    __syncthreads();
+    for (int c = tid; c < 729; c += kPlainThreads) {
+        const int dX = c % 9 - 4, dY = (c / 9) % 9 - 4, dZ = c / 81 - 4;
+        const int n = dX * dX + dY * dY + dZ * dZ;
+        if (n == 0 || n > 16) continue;
+        for (int t = 0; t < 3; t++) {
+            const int odd = ((t != 0) + dX) & 1;
+            const int odd_y = ((t != 1) + dY) & 1;
+            const int odd_z = ((t != 2) + dZ) & 1;
+            const int nodd = odd + odd_y + odd_z;
+            const bool bsite = nodd == 3;
+            if (nodd < 2) continue;
+            const int sh = site_shell(bsite, n);
+            if (sh < 0) continue;
+            const int e = bsite ? D.site_e_fe[sh] : D.site_e_vv[sh];
+            if (e == 0) continue;
+            const int k = atomicAdd(&n_off[t], 1);
+            if (k < kSiteOffsets)
+                offs[t * kSiteOffsets + k] =
+                    (uint16_t)((dX + 4) | ((dY + 4) << 4) | ((dZ + 4) << 8) | ((bsite ? 1 : 0) << 12) | (sh << 13));
+        }
+    }
+    const int n = plain_collect_slots(D, P, slots, wcount, &n_sh, tid, kMaxSiteSlots);
+    if (n > kMaxSiteSlots) {
+        if (tid == 0) atomicOr(&S->err, 1u);
+        return;
+    }
+    const int noff_max = max(n_off[0], max(n_off[1], n_off[2]));
+
+    // events of slot sidx: 9 site energies by the whole workgroup, then the
+    // 8 table indices and the slot total (all threads call it together)
+    auto eval_slot = [&](int sidx) {
+        const uint64_t pk = slots[sidx];
+        if (tid < 9) Eacc[tid] = 0;
+        if (tid < 8) {
+            int64_t ts;
+            const int i = (int)(pk & 0xffff), j = (int)((pk >> 16) & 0xffff), k = (int)((pk >> 32) & 0xffff);
+            const int t = (int)(pk >> 48);
+            int hx, hy, hz;
+            hop_vec(t, tid, hx, hy, hz);
+            const int X = wrap2(2 * i + (t != 0) + hx, 2 * D.L[0]);
+            const int Y = wrap2(2 * j + (t != 1) + hy, 2 * D.L[1]);
+            const int Z = wrap2(2 * k + (t != 2) + hz, 2 * D.L[2]);
+            const int tt = site_type(X, Y);
+            ts = plain_store(D, X >> 1, Y >> 1, Z >> 1, tt);
+            const int sp = occ[ts];
+            const int cs = t == 0 ? i : (t == 1 ? j : k);
+            const int ct = tt == 0 ? (X >> 1) : (tt == 1 ? (Y >> 1) : (Z >> 1));
+            const int g = is_gb(D, t, cs) | is_gb(D, tt, ct);
+            tpk[tid] = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) | ((uint64_t)(Z >> 1) << 32) |
+                       ((uint64_t)tt << 48);
+            tsp[tid] = sp;
+            tcol[tid] = (sp * 3 + hz + 1) * 2 + g;
+        }
+        __syncthreads();
+        for (int w = tid; w < 9 * noff_max; w += kPlainThreads) {
+            const int c = w / noff_max, kk = w - c * noff_max;
+            if (c > 0 && tsp[c - 1] == kSpV) continue;
+            const uint64_t ck = c == 0 ? pk : tpk[c - 1];
+            const int t = (int)(ck >> 48);
+            if (kk >= n_off[t]) continue;
+            const int o = offs[t * kSiteOffsets + kk];
+            const int X = wrap2(2 * (int)(ck & 0xffff) + (t != 0) + (o & 15) - 4, 2 * D.L[0]);
+            const int Y = wrap2(2 * (int)((ck >> 16) & 0xffff) + (t != 1) + ((o >> 4) & 15) - 4, 2 * D.L[1]);
+            const int Z = wrap2(2 * (int)((ck >> 32) & 0xffff) + (t != 2) + ((o >> 8) & 15) - 4, 2 * D.L[2]);
+            const int sh = o >> 13;
+            int e = 0;
+            if ((o >> 12) & 1) {
+                const int64_t cell = ((int64_t)(Z >> 1) * D.L[1] + (Y >> 1)) * D.L[0] + (X >> 1);
+                if ((D.site_fe[cell >> 5] >> (cell & 31)) & 1u) e = D.site_e_fe[sh];
+            } else {
+                const int tt = site_type(X, Y);
+                // the origin's own vacancy is never a partner (it is the one hopping)
+                const uint64_t upk = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) |
+                                     ((uint64_t)(Z >> 1) << 32) | ((uint64_t)tt << 48);
+                if (upk != pk && occ[plain_store(D, X >> 1, Y >> 1, Z >> 1, tt)] == kSpV)
+                    e = D.site_e_vv[sh];
+            }
+            if (e) atomicAdd(&Eacc[c], e);
+        }
+        __syncthreads();
+        if (tid < 8) {
+            int ix = 0xFFFF;
+            if (tsp[tid] != kSpV) {
+                const int dE = Eacc[1 + tid] - Eacc[0];
+                if (dE < -W || dE > W) err_sh = 1;
+                else ix = tcol[tid] * WW + dE + W;
+            }
+            eidx[sidx * 8 + tid] = (uint16_t)ix;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double r = 0.0;
+            for (int d = 0; d < 8; d++) {
+                const int ix = eidx[sidx * 8 + d];
+                r += ix == 0xFFFF ? 0.0 : D.site_table[ix];
+            }
+            stot[sidx] = r;
+        }
+        __syncthreads();
+    };
+    for (int sidx = 0; sidx < n; sidx++) eval_slot(sidx);
+
+    const int m = (n + kPlainThreads - 1) / kPlainThreads;
+    const int s0 = tid * m < n ? tid * m : n;
+    const int s1 = s0 + m < n ? s0 + m : n;
+    double t = S->t;
+    uint64_t draws = S->draws;
+    const double horizon = C->t_sync;
+    const double t_end = t + horizon;
+    const uint64_t target = C->min_hops;
+    uint64_t done = 0, ho = 0, hh = 0;
+    while (done < target && !err_sh) {
+        double ls = 0.0;
+        for (int sidx = s0; sidx < s1; sidx++) ls += stot[sidx];
+        double incl = wave_incl_scan(ls, lane);
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        double before = 0.0, R = 0.0;
+        for (int w = 0; w < NW; w++) {
+            if (w < wv) before += wsum[w];
+            R += wsum[w];
+        }
+        incl += before;
+        if (R == 0.0) break;
+        uint32_t x0, x1, x2, x3;
+        philox10((uint32_t)draws, (uint32_t)(draws >> 32), 0xFFFFFFFFu, 3u, D.seed, D.lattice_id,
+                 x0, x1, x2, x3);
+        draws++;
+        const double u_sel = u53_lo(x0, x1);
+        const double u_t = u53_hi(x2, x3);
+        const double dt = -clock_ln(u_t) / R;
+        const double tn = t + dt;
+        if (horizon > 0.0 && tn > t_end) {
+            t = t_end;
+            break;
+        }
+        t = tn;
+        const double y = u_sel * R;
+        const uint64_t mk = __ballot(incl > y);
+        const uint64_t nz = __ballot(ls > 0.0);
+        if (lane == 0) {
+            wmask[wv] = mk;
+            wnz[wv] = nz;
+        }
+        __syncthreads();
+        int sel = -1;
+        bool fallback = false;
+        for (int w = 0; w < NW && sel < 0; w++)
+            if (wmask[w]) sel = w * 64 + __ffsll((unsigned long long)wmask[w]) - 1;
+        if (sel < 0) {
+            fallback = true;
+            for (int w = NW - 1; w >= 0 && sel < 0; w--)
+                if (wnz[w]) sel = w * 64 + 63 - __clzll((long long)wnz[w]);
+        }
+        if (tid == sel) {
+            double Cc = incl - ls;
+            int sp_slot = -1, last = -1;
+            for (int sidx = s0; sidx < s1; sidx++) {
+                if (stot[sidx] > 0.0) last = sidx;
+                if (!fallback && sp_slot < 0 && Cc + stot[sidx] > y) {
+                    sp_slot = sidx;
+                    break;
+                }
+                Cc += stot[sidx];
+            }
+            if (sp_slot < 0) sp_slot = last;
+            int dsel = -1, dlast = -1;
+            for (int d = 0; d < 8; d++) {
+                const int ix = eidx[sp_slot * 8 + d];
+                const double k = ix == 0xFFFF ? 0.0 : D.site_table[ix];
+                if (k > 0.0) dlast = d;
+                Cc += k;
+                if (!fallback && dsel < 0 && Cc > y) dsel = d;
+            }
+            const int d = dsel >= 0 ? dsel : dlast;
+            const uint64_t pk = slots[sp_slot];
+            const int i = (int)(pk & 0xffff), j = (int)((pk >> 16) & 0xffff), k = (int)((pk >> 32) & 0xffff);
+            const int tp = (int)(pk >> 48);
+            int hx, hy, hz;
+            hop_vec(tp, d, hx, hy, hz);
+            const int X = wrap2(2 * i + (tp != 0) + hx, 2 * D.L[0]);
+            const int Y = wrap2(2 * j + (tp != 1) + hy, 2 * D.L[1]);
+            const int Z = wrap2(2 * k + (tp != 2) + hz, 2 * D.L[2]);
+            const int tt = site_type(X, Y);
+            const int64_t ss = plain_store(D, i, j, k, tp);
+            const int64_t ts = plain_store(D, X >> 1, Y >> 1, Z >> 1, tt);
+            const int sp = P.occ[D.occ_off + ts];
+            P.occ[D.occ_off + ss] = (int8_t)sp;
+            P.occ[D.occ_off + ts] = (int8_t)kSpV;
+            int4* dsrc = P.disp + (D.disp_off + ss);
+            int4* dtgt = P.disp + (D.disp_off + ts);
+            const int4 dv = *dsrc;
+            const int4 di = *dtgt;
+            *dtgt = make_int4(dv.x + hx, dv.y + hy, dv.z + hz, 0);
+            *dsrc = make_int4(di.x - hx, di.y - hy, di.z - hz, 0);
+            const uint64_t npk = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) | ((uint64_t)(Z >> 1) << 32) |
+                                 ((uint64_t)tt << 48);
+            slots[sp_slot] = npk;
+            hop_slot = sp_slot;
+            hop_s = pk;
+            hop_t = npk;
+            ev_sh = sp;
+        }
+        if (tid == 0) n_aff = 0;
+        // the barrier's workgroup-scope fence makes the hop's HBM writes
+        // visible to every wave of this workgroup, the only readers
+        __syncthreads();
+        if (ev_sh == kSpO) ho++;
+        else hh++;
+        done++;
+        // slots whose events can have changed: within squared doubled
+        // distance 29 of either site (energies reach 16, a target is 2 away)
+        const uint64_t ps = hop_s, pt = hop_t;
+        for (int sidx = s0; sidx < s1; sidx++)
+            if (sidx == hop_slot || plain_dist2(D, slots[sidx], ps) <= 29 || plain_dist2(D, slots[sidx], pt) <= 29) {
+                const int a = atomicAdd(&n_aff, 1);
+                if (a < kPlainThreads) aff[a] = (int16_t)sidx;
+            }
+        __syncthreads();
+        const int na = n_aff;
+        if (na > kPlainThreads) {
+            for (int sidx = 0; sidx < n; sidx++) eval_slot(sidx);
+        } else {
+            for (int a = 0; a < na; a++) eval_slot(aff[a]);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (err_sh) atomicOr(&S->err, 4u);
         S->t = t;
         S->draws = draws;
         S->hops[0] += ho;
@@ -3184,6 +3501,17 @@ int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(k_plain, dim3(n_plain), dim3(kPlainThreads), lds, (hipStream_t)stream, P,
                        d_plain_ids);
+    return (int)hipGetLastError();
+}
+
+int launch_plain_site(const DevPtrs& P, const int32_t* d_ids, int n, void* stream)
+{
+    if (n == 0) return 0;
+    const size_t lds = (size_t)32 * kMaxSiteSlots + 2 * 3 * kSiteOffsets;
+    hipError_t e = hipFuncSetAttribute((const void*)k_plain_site, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k_plain_site, dim3(n), dim3(kPlainThreads), lds, (hipStream_t)stream, P, d_ids);
     return (int)hipGetLastError();
 }
 

@@ -56,6 +56,13 @@ struct LatDesc {
     int64_t disp_off;     // element (int4) offset in the displacement buffer
     int64_t n_sites;
     double k12[12];       // quantised rates, (X*3 + dz+1)*2 + g
+    // site-energy interactions (plain lattices; site_window < 0: none)
+    int32_t site_window;  // largest |dE_site| of a hop, meV
+    int32_t site_e_fe[4]; // meV, vacancy-Fe over B-site shells |r|^2 = 1, 5, 9, 13 (a/2)^2
+    int32_t site_e_vv[6]; // meV, vacancy-vacancy over O-site shells 2, 4, 6, 8, 10, 16
+    int32_t site_pad;
+    const uint32_t* site_fe;   // Fe bitmap, one bit per cell (canonical cell order)
+    const double* site_table;  // quantised rates [(X*3 + dz+1)*2 + g][dE + window]
 };
 
 // Per-call parameters.
@@ -132,6 +139,10 @@ int launch_phase(const DevPtrs& P, int colour, int group, void* stream);
 int launch_cycle_begin(const DevPtrs& P, void* stream);
 int launch_cycle_end(const DevPtrs& P, void* stream);
 int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void* stream);
+// Plain BKL with site-energy interactions, one workgroup per listed lattice.
+constexpr int kMaxSiteSlots = 2048;
+constexpr int kMaxSiteWindow = 2047;  // meV: table indices stay below 2^16
+int launch_plain_site(const DevPtrs& P, const int32_t* d_ids, int n, void* stream);
 int launch_atomic_hbm(const DevPtrs& P, const int32_t* d_ids, int n, uint32_t n_frg, uint64_t n_stages,
                       void* stream);
 int launch_stats(const DevPtrs& P, int lat, int64_t n_sites, void* stream);

@@ -119,6 +119,9 @@ _SIGS = {
     "fkmc_restore": [C.c_void_p, C.c_uint32, C.c_void_p, C.c_size_t],
     "fkmc_phase_timing": [C.c_void_p, _P(C.c_double), _P(C.c_uint64)],
     "fkmc_quantisation": [C.c_void_p, C.c_uint32, _P(C.c_double), _P(C.c_double)],
+    "fkmc_site_model_bytes": [C.c_void_p, C.c_uint32, C.c_int32, _P(C.c_size_t)],
+    "fkmc_set_site_model": [C.c_void_p, C.c_uint32, C.c_void_p, _P(C.c_int32), _P(C.c_int32), C.c_int32,
+                            C.c_void_p, C.c_size_t],
     "fkmc_last_error": [],
 }
 
@@ -235,6 +238,23 @@ class LatticeSet:
             params = [params] * self.n
         arr = (RateParams * self.n)(*params)
         _check(lib().fkmc_set_rates(self._h, arr))
+
+    def set_site_model(self, i: int, fe, e_fe, e_vv, window_meV: int):
+        """Site energies on plain lattice i (fkmc_set_site_model): Fe map of
+        one byte per cell, pair energies in meV; the device buffer is
+        allocated here and kept with the set."""
+        import torch
+        n = C.c_size_t()
+        _check(lib().fkmc_site_model_bytes(self._h, int(i), int(window_meV), C.byref(n)))
+        buf = torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+        fe = np.ascontiguousarray(fe, dtype=np.uint8)
+        ef = (C.c_int32 * 4)(*[int(x) for x in e_fe])
+        ev = (C.c_int32 * 6)(*[int(x) for x in e_vv])
+        _check(lib().fkmc_set_site_model(self._h, int(i), fe.ctypes.data, ef, ev, int(window_meV),
+                                         buf.data_ptr(), n.value))
+        if not hasattr(self, "_site_bufs"):
+            self._site_bufs = {}
+        self._site_bufs[int(i)] = buf
 
     def set_rate_table(self, i: int, k12):
         _check(lib().fkmc_set_rate_table(self._h, i, _dbl(k12), 12))

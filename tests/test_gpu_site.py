@@ -1,0 +1,114 @@
+"""Site-energy interactions on the GPU (plain BKL with vacancy-Fe and
+vacancy-vacancy pair energies, Table TABLEadd01 as inputs) against the
+oracle bit for bit: draws, clock, hop counts, occupancy and displacements
+over several calls (hop counts and a horizon); the zero-energy model equals
+plain BKL; and the error and refusal paths."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2004_09081_amd import workloads as W
+from tests.common import Case, assert_same_state, gpu_set, say
+
+pytestmark = pytest.mark.gpu
+
+E_FE, E_VV = W.SITE_E_FE_MEV, W.SITE_E_VV_MEV
+WINDOW = 1200
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_09081_amd import fkmc
+    fkmc.lib()
+
+
+SITE_CASES = [
+    (Case((6, 6, 6), seed=71, lattice_id=0, nv=8, nh=0, T=1000.0, Ea_O=0.6), 0.05),
+    (Case((5, 7, 6), seed=71, lattice_id=1, nv=12, nh=40, T=1100.0, Ea_O=0.6, Ea_H=0.5), 0.04),
+    (Case((8, 8, 8), seed=71, lattice_id=2, nv=20, nh=100, T=1200.0, Ea_O=0.6, Ea_H=0.5, E_z=2e8,
+          gb_period=4, gb_mask=5, gb_dE=0.05), 0.03),
+    (Case((10, 9, 11), seed=71, lattice_id=3, nv=30, nh=0, T=1300.0, Ea_O=0.6), 0.01),
+    (Case((10, 10, 10), seed=71, lattice_id=4, nv=40, nh=300, T=1400.0, Ea_O=0.65, Ea_H=0.55), 0.02),
+]
+
+
+def _oracle(c, x_fe, e_fe=E_FE, e_vv=E_VV, window=WINDOW):
+    lat = c.oracle()
+    fe = W.fe_map(c.L, x_fe, c.lattice_id)
+    lat.set_site_model(fe, O.SiteParams(e_fe=e_fe, e_vv=e_vv, window=window), O.RateParams(**c.rp))
+    return lat, fe
+
+
+def test_site_energy_bkl_matches_oracle():
+    say("site energies: %d plain lattices" % len(SITE_CASES))
+    cases = [c for c, _ in SITE_CASES]
+    pairs = [_oracle(c, x) for c, x in SITE_CASES]
+    g = gpu_set(cases)
+    for i, (lat, fe) in enumerate(pairs):
+        g.set_site_model(i, fe, E_FE, E_VV, WINDOW)
+    for n_hops, horizon in ((400, 0.0), (900, 0.0), (10**6, 1)):
+        hz = [0.0] * len(cases)
+        for i, (lat, _) in enumerate(pairs):
+            if horizon:
+                hz[i] = 40.0 / (8 * lat.site_raw[0])
+            lat.advance_plain_site(n_hops, hz[i])
+        g.advance(hz, 0, n_hops)
+        st = g.read_stats()
+        for i, (lat, _) in enumerate(pairs):
+            what = "site member %d %s" % (i, cases[i].L)
+            assert st[i]["draws"] == lat.draws and st[i]["t"] == lat.t, what
+            assert st[i]["hops"].tolist() == [int(x) for x in lat.hops], what
+            assert_same_state(g, i, lat, what)
+    assert all(int(l.hops.sum()) > 1300 for l, _ in pairs)
+
+
+def test_zero_pair_energies_equal_plain_bkl_on_the_gpu():
+    c = SITE_CASES[2][0]
+    say("site energies all zero against plain BKL")
+    a = gpu_set([c])
+    b = gpu_set([c])
+    b.set_site_model(0, W.fe_map(c.L, 0.05, 9), (0,) * 4, (0,) * 6, 0)
+    for n in (500, 1500):
+        a.advance([0.0], 0, n)
+        b.advance([0.0], 0, n)
+        sa, sb = a.read_stats()[0], b.read_stats()[0]
+        assert sa["t"] == sb["t"] and sa["draws"] == sb["draws"]
+        oa, da = a.read_state(0)
+        ob, db = b.read_state(0)
+        assert np.array_equal(oa, ob) and np.array_equal(da, db)
+
+
+def test_site_model_errors_and_refusals():
+    from paper_2004_09081_amd import fkmc as F
+    say("site energies: errors and refusals")
+    c = SITE_CASES[0][0]
+    # a window too narrow for the first hop: E_RANGE, as the oracle reports
+    lat, fe = _oracle(c, 0.05, window=0)
+    with pytest.raises(ValueError):
+        lat.advance_plain_site(200)
+    g = gpu_set([c])
+    g.set_site_model(0, fe, E_FE, E_VV, 0)
+    with pytest.raises(F.FkmcError) as e:
+        g.advance([0.0], 0, 200)
+    assert e.value.code == -4
+    # a fragment lattice, a lattice under 5 cells, and rates not set
+    with pytest.raises(F.FkmcError) as e:
+        gpu_set([Case((6, 6, 6), (3, 3, 3), nv=4)]).set_site_model(0, fe, E_FE, E_VV, 500)
+    assert e.value.code == -6
+    with pytest.raises(F.FkmcError) as e:
+        gpu_set([Case((4, 6, 6), nv=4)]).set_site_model(0, np.zeros(144, np.uint8), E_FE, E_VV, 500)
+    assert e.value.code == -6
+    h = F.LatticeSet([c.gpu_geometry()])
+    h.init_random([4], [0])
+    with pytest.raises(F.FkmcError) as e:
+        h.set_site_model(0, fe, E_FE, E_VV, 500)
+    assert e.value.code == -2
+    # the atom-selection scheme refuses a lattice with site energies
+    g2 = gpu_set([c])
+    g2.set_site_model(0, fe, E_FE, E_VV, WINDOW)
+    with pytest.raises(F.FkmcError) as e:
+        g2.advance_atomic(1, 10)
+    assert e.value.code == -6
