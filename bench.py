@@ -25,6 +25,7 @@ import argparse
 import copy
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -273,6 +274,53 @@ def cpu_leg(args):
                                     % (allc["processes"], args.cpu_budget, allc["finished"])}}
 
 
+def micro_run(F, W):
+    """The reduced micro-scale BaTiO3 model (Voronoi grains with a +0.2 eV
+    boundary layer, the paper's bias, 0.1 % vacancies, 450 K) run for 5 ms
+    of simulated time: hops/s, and where the vacancies gather (on boundary
+    sites against the boundary-site fraction; the densest 5^3-cell block
+    against the mean)."""
+    import torch
+    t0 = time.perf_counter()
+    spec, gmap = W.micro()
+    t_map = time.perf_counter() - t0
+    S = build_set([spec], F)
+    S.set_gb_map(0, gmap)
+    S.set_schedule("lockstep")
+    cycles = int(math.ceil(spec.extra["t_end"] / spec.t_sync))
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    S.advance([spec.t_sync], max_cycles=cycles, min_hops=0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - a
+    st = S.read_stats()[0]
+    occ, _ = S.read_state(0, with_disp=False)
+    S.close()
+    hops = int(st["hops"].sum())
+    v = occ == 2
+    L = spec.L
+    cellv = v.reshape(L[2], L[1], L[0], 3).sum(axis=3)
+    b = 5
+    blocks = cellv[:L[2] // b * b, :L[1] // b * b, :L[0] // b * b].reshape(
+        L[2] // b, b, L[1] // b, b, L[0] // b, b).sum(axis=(1, 3, 5))
+    rep = {"hops": hops, "seconds": el, "hops_per_s": hops / el, "t_simulated_s": st["t"],
+           "cycles": int(st["cycles"]), "vacancies": int(v.sum()),
+           "boundary_site_fraction": float(gmap.mean()),
+           "vacancies_on_boundary_sites": float(gmap[v].mean()),
+           "densest_block_over_mean": float(blocks.max() / blocks.mean()),
+           "drift_V_m_per_s": [float(x) * 1e-10 for x in st["drift"][2]],
+           "map_seconds": t_map,
+           "workload": "%dx%dx%d cells, %d Voronoi grains, boundary layer %.1f cell +%.1f eV, E_z %.3g V/m, "
+                       "0.1%% V, %.0f K, %d^3 fragments, %.0e s" % (L[0], L[1], L[2], spec.extra["n_grains"],
+                                                                  spec.extra["width"], spec.gb_dE, spec.E_z,
+                                                                  spec.T, spec.frag[0], spec.extra["t_end"])}
+    log("micro model: %d hops in %.2f s (%.3g hops/s) to t = %.3g s; vacancies on boundary sites %.3f "
+        "(site fraction %.3f), densest 5^3 block %.1f x the mean" % (
+            hops, el, rep["hops_per_s"], st["t"], rep["vacancies_on_boundary_sites"],
+            rep["boundary_site_fraction"], rep["densest_block_over_mean"]))
+    return rep
+
+
 def sweep_leg(F, W, cycles: int, warm: int):
     """Lockstep fragment sweep of the 600^3 biased lattice: HIP-event time of
     every phase launch over `cycles` whole cycles after `warm` cycles."""
@@ -453,7 +501,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg4", choices=["cfg4", "cfg3", "cfg2"])
+    ap.add_argument("--workload", default="cfg4", choices=["cfg4", "cfg3", "cfg2", "micro"])
     ap.add_argument("--lattices", type=int, default=512, help="cfg4 ensemble size")
     ap.add_argument("--hops", type=int, default=1_000_000, help="cfg4 hops per lattice per step")
     ap.add_argument("--plain-sample", type=int, default=16,
@@ -495,7 +543,7 @@ def main():
     # The CPU oracle leg runs first, before this process touches the GPU, so
     # that its worker processes start from a process without GPU state.
     cpu_rep = None
-    if not args.no_cpu_baseline and not args.calibrate_copy_mib:
+    if not args.no_cpu_baseline and not args.calibrate_copy_mib and args.workload != "micro":
         cpu_rep = cpu_leg(args)
 
     import torch
@@ -514,6 +562,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     F.lib()
+
+    if args.workload == "micro":
+        rep = micro_run(F, W)
+        print(json.dumps({"metric": METRIC, "value": rep["hops_per_s"], "unit": "hops/s", "n_gpus": 1,
+                          "steps": 1, "warmup": 0, "ms_per_step": rep["seconds"] * 1e3,
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+                          "data": "synthetic", "config": {"workload": rep["workload"]}, "micro": rep}),
+              flush=True)
+        return
 
     decomposition = None
     if args.workload == "cfg4":

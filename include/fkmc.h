@@ -230,6 +230,20 @@ fkmc_status fkmc_site_model_bytes(const fkmc_lattice* lat, uint32_t i, int32_t w
 fkmc_status fkmc_set_site_model(fkmc_lattice* lat, uint32_t i, const uint8_t* fe, const int32_t e_fe[4],
                                 const int32_t e_vv[6], int32_t window_meV, void* dev, size_t bytes);
 
+/* Grain boundaries as a site map (Sec. "Oxygen diffusion in micro-scale
+ * BaTiO3 model": grains from a Voronoi tessellation, separated by a
+ * boundary layer whose hops carry the extra barrier gb_dE).  map (host, n
+ * bytes in canonical site order, 1 = boundary site) replaces lattice i's
+ * boundary planes: an edge with either end on a boundary site takes gb_dE
+ * from its rate parameters.  dev is caller-owned device memory of
+ * fkmc_gb_map_bytes bytes (256-byte aligned) that must outlive the map;
+ * map = NULL removes it (the planes apply again).  Lattices with a map run
+ * the tile-group fragment paths (both schedules) and, when plain, the HBM
+ * plain kernel or the site-energy kernel; fkmc_advance_atomic refuses
+ * them.  Results equal the oracle's with the same map. */
+fkmc_status fkmc_gb_map_bytes(const fkmc_lattice* lat, uint32_t i, size_t* bytes);
+fkmc_status fkmc_set_gb_map(fkmc_lattice* lat, uint32_t i, const uint8_t* map, void* dev, size_t bytes);
+
 /* Current quantised table of lattice i (12 doubles). */
 fkmc_status fkmc_get_rate_table(const fkmc_lattice* lat, uint32_t i, double* k12, size_t n);
 

@@ -170,6 +170,9 @@ typedef struct {
     uint32_t seed, lattice_id;
     int32_t gb_period_cells; /* 0 = no grain-boundary planes              */
     int32_t gb_axes_mask;    /* bit a: planes normal to axis a            */
+    const uint8_t* gb_map;   /* NULL, or one byte per site in canonical
+                                order, 1 = boundary site (Voronoi grain
+                                boundaries); replaces the planes         */
 } or_geom;
 
 static const int TYPE_OFF[3][3] = {{0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
@@ -279,6 +282,7 @@ static void edge_owner(const or_geom* g, const int c[3], int t, int d, int own[3
 static int is_gb_site(const or_geom* g, const int c[3], int t)
 {
     int P = g->gb_period_cells;
+    if (g->gb_map) return g->gb_map[site_index(g, c, t)] != 0;
     if (P <= 0) return 0;
     if (!(g->gb_axes_mask & (1 << t))) return 0;
     return (c[t] % P) == 0;

@@ -36,7 +36,8 @@ def build(force: bool = False) -> str:
 class _Geom(C.Structure):
     _fields_ = [("L", C.c_int32 * 3), ("frag", C.c_int32 * 3), ("a_angstrom", C.c_double),
                 ("seed", C.c_uint32), ("lattice_id", C.c_uint32),
-                ("gb_period_cells", C.c_int32), ("gb_axes_mask", C.c_int32)]
+                ("gb_period_cells", C.c_int32), ("gb_axes_mask", C.c_int32),
+                ("gb_map", C.c_void_p)]
 
 
 class _SiteParams(C.Structure):
@@ -218,6 +219,9 @@ class Geometry:
     lattice_id: int = 0
     gb_period_cells: int = 0
     gb_axes_mask: int = 4
+    # one byte per site (canonical order), 1 = grain-boundary site; replaces
+    # the planes when given (Voronoi grain boundaries)
+    gb_map: np.ndarray = None
 
     def c(self) -> _Geom:
         g = _Geom()
@@ -228,6 +232,12 @@ class Geometry:
         g.lattice_id = self.lattice_id & 0xFFFFFFFF
         g.gb_period_cells = self.gb_period_cells
         g.gb_axes_mask = self.gb_axes_mask
+        if self.gb_map is not None:
+            self._gb_keep = np.ascontiguousarray(self.gb_map, dtype=np.uint8).reshape(-1)
+            assert self._gb_keep.size == self.n_sites
+            g.gb_map = self._gb_keep.ctypes.data
+        else:
+            g.gb_map = None
         return g
 
     @property

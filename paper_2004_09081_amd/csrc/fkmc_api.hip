@@ -877,6 +877,44 @@ fkmc_status fkmc_set_site_model(fkmc_lattice* L, uint32_t i, const uint8_t* fe, 
     return FKMC_OK;
 }
 
+fkmc_status fkmc_gb_map_bytes(const fkmc_lattice* L, uint32_t i, size_t* bytes)
+{
+    if (!L || !bytes) return fail(FKMC_E_INVALID, "null argument");
+    if (i >= L->n) return fail(FKMC_E_INVALID, "lattice index %u out of range", i);
+    *bytes = align_up((size_t)((L->desc[i].n_sites + 31) / 32) * 4, 256);
+    return FKMC_OK;
+}
+
+fkmc_status fkmc_set_gb_map(fkmc_lattice* L, uint32_t i, const uint8_t* map, void* dev, size_t bytes)
+{
+    if (!L) return fail(FKMC_E_INVALID, "null handle");
+    if (i >= L->n) return fail(FKMC_E_INVALID, "lattice index %u out of range", i);
+    LatDesc backup = L->desc[i];
+    if (!map) {
+        L->desc[i].gb_map = nullptr;
+    } else {
+        size_t need = 0;
+        fkmc_status st = fkmc_gb_map_bytes(L, i, &need);
+        if (st) return st;
+        if (!dev || bytes < need || ((uintptr_t)dev & 255))
+            return fail(FKMC_E_NOMEM, "boundary map buffer: need %zu bytes, 256-aligned", need);
+        const int64_t N = L->desc[i].n_sites;
+        std::vector<uint32_t> bits((size_t)((N + 31) / 32), 0u);
+        for (int64_t n = 0; n < N; n++) {
+            if (map[n] > 1) return fail(FKMC_E_INVALID, "boundary map value %d at site %lld", map[n], (long long)n);
+            if (map[n]) bits[(size_t)(n >> 5)] |= 1u << (n & 31);
+        }
+        HIP_OK(hipMemcpyAsync(dev, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, L->stream));
+        L->desc[i].gb_map = (const uint32_t*)dev;
+    }
+    fkmc_status st = upload_desc(L);
+    if (st) {
+        L->desc[i] = backup;
+        return st;
+    }
+    return FKMC_OK;
+}
+
 fkmc_status fkmc_set_rate_table(fkmc_lattice* L, uint32_t i, const double* k12, size_t n)
 {
     if (!L || !k12) return fail(FKMC_E_INVALID, "null argument");
@@ -1020,6 +1058,7 @@ static bool plain_lds_fits(const fkmc_lattice* L, uint32_t i)
 {
     const fkmc_geometry& g = L->geo[i];
     if (!L->plain_lds || !L->desc[i].plain || L->n_vac[i] > (uint64_t)kPlainLdsSlots) return false;
+    if (L->desc[i].gb_map) return false;  // boundary-site maps: the HBM kernel
     // packed doubled coordinates: 11 bits for x and y, 10 for z
     if (g.L[0] > 1023 || g.L[1] > 1023 || g.L[2] > 512) return false;
     return plain_lds_bytes(L, i) <= std::min(batch_lds_bound(L), 65536);
@@ -1050,7 +1089,7 @@ static fkmc_status plan_batch(fkmc_lattice* L, const std::vector<int32_t>& ids)
         D.resident = small ? 1 : 0;
         // one fragment, in LDS, at most 32 vacancies: a block of lanes per vacancy
         // (packed doubled coordinates give z 10 bits)
-        D.fast = small && !L->group_override && D.nf[0] == 1 && D.nf[1] == 1 && D.nf[2] == 1 &&
+        D.fast = small && !L->group_override && !D.gb_map && D.nf[0] == 1 && D.nf[1] == 1 && D.nf[2] == 1 &&
                          g.L[2] <= 512 && L->n_vac[i] <= 32
                      ? 1
                      : 0;
@@ -1373,6 +1412,8 @@ fkmc_status fkmc_advance_atomic(fkmc_lattice* L, uint32_t n_frg, uint64_t n_stag
         const fkmc_geometry& g = L->geo[i];
         if (L->desc[i].site_window >= 0)
             return fail(FKMC_E_UNSUPPORTED, "lattice %u: the atom-selection scheme has no site energies", i);
+        if (L->desc[i].gb_map)
+            return fail(FKMC_E_UNSUPPORTED, "lattice %u: the atom-selection scheme has no boundary-site map", i);
         if (!L->desc[i].plain)
             return fail(FKMC_E_UNSUPPORTED, "lattice %u: the atom-selection scheme runs unfragmented lattices", i);
         const int64_t b = plain_lds_bytes(L, i);

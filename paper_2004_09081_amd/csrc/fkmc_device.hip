@@ -197,6 +197,29 @@ __device__ __forceinline__ int is_gb(const LatDesc& D, int t, int cell_t)
     return (D.gb_period > 0 && ((D.gb_mask >> t) & 1) && (cell_t % D.gb_period) == 0) ? 1 : 0;
 }
 
+// Bit n of a boundary-site map (canonical site index).
+__device__ __forceinline__ int gb_bit(const uint32_t* m, int64_t n)
+{
+    return (int)((m[n >> 5] >> (n & 31)) & 1u);
+}
+
+__device__ __forceinline__ int64_t canon_site(int L0, int L1, int i, int j, int k, int t)
+{
+    return (((int64_t)k * L1 + j) * L0 + i) * 3 + t;
+}
+
+// Boundary flag of the edge between site (i,j,k,t) and site (i2,j2,k2,t2):
+// from the lattice's site map when it has one, else from its planes (cs, ct:
+// the two sites' cell indices along their own type's axis).
+__device__ __forceinline__ int edge_gb(const LatDesc& D, int i, int j, int k, int t, int i2, int j2, int k2,
+                                       int t2, int cs, int ct)
+{
+    if (D.gb_map)
+        return gb_bit(D.gb_map, canon_site(D.L[0], D.L[1], i, j, k, t)) |
+               gb_bit(D.gb_map, canon_site(D.L[0], D.L[1], i2, j2, k2, t2));
+    return is_gb(D, t, cs) | is_gb(D, t2, ct);
+}
+
 // ----------------------------------------------------------------------------
 // Inclusive wavefront prefix sum of a binary64 value with DPP moves of its
 // two 32-bit halves: row_shr 1,2,4,8 inside each 16-lane row, then
@@ -365,6 +388,7 @@ struct RateCtx {
     int L0, L1, L2;
     int gbp, gbm;
     const double* k12;
+    const uint32_t* gbmap;  // boundary-site map (replaces the planes), or nullptr
 };
 
 __device__ __forceinline__ int gb_flag(const RateCtx& C, int t, int cell)
@@ -376,6 +400,16 @@ __device__ __forceinline__ int gb_flag(const RateCtx& C, int t, int cell)
 // Rate of event d of the vacancy at packed local doubled coordinates xyz:
 // 0 when the hop edge's midpoint is outside the sub-block or the target
 // holds a vacancy; else the table entry for (ion species, z step, boundary).
+// Occupancy of the site at LDS position pos: one byte per site, or, with PK,
+// 2 bits per site (16 per 32-bit word: word pos >> 4, bits 2 (pos & 15)).
+template <bool PK>
+__device__ __forceinline__ int occ_at(const unsigned char* occl, int pos)
+{
+    if (PK) return (int)((((const uint32_t*)occl)[pos >> 4] >> ((pos & 15) << 1)) & 3u);
+    return occl[pos];
+}
+
+template <bool PK = false>
 __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned char* occl,
                                             const RateCtx& C, uint32_t xyz, int d)
 {
@@ -392,9 +426,25 @@ __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned cha
     // (an active edge's target is in the footprint; an inactive edge reads
     // the first brick byte instead, so every address stays in bounds)
     const int lds0 = G.lds0;
-    const int sp = occl[in ? seg_lds(G, seg) + li : lds0];
+    const int sp = occ_at<PK>(occl, in ? seg_lds(G, seg) + li : lds0);
     int g = 0;
-    if (C.gbp > 0) {
+    if (C.gbmap) {
+        int si = G.ox + (X >> 1), sj = G.oy + (Y >> 1), sk = G.oz + (Z >> 1);
+        int ti = G.ox + (tX >> 1), tj = G.oy + (tY >> 1), tk = G.oz + (tZ >> 1);
+        si -= si >= C.L0 ? C.L0 : 0;
+        sj -= sj >= C.L1 ? C.L1 : 0;
+        sk -= sk >= C.L2 ? C.L2 : 0;
+        ti -= ti >= C.L0 ? C.L0 : 0;
+        tj -= tj >= C.L1 ? C.L1 : 0;
+        tk -= tk >= C.L2 ? C.L2 : 0;
+        // (an inactive edge may point outside the footprint: clamp its
+        // indices into the lattice; its rate is 0 either way)
+        ti = ti < 0 ? 0 : ti;
+        tj = tj < 0 ? 0 : tj;
+        tk = tk < 0 ? 0 : tk;
+        g = gb_bit(C.gbmap, canon_site(C.L0, C.L1, si, sj, sk, t)) |
+            gb_bit(C.gbmap, canon_site(C.L0, C.L1, ti, tj, tk, tt));
+    } else if (C.gbp > 0) {
         int cs = pick3(t, G.ox + (X >> 1), G.oy + (Y >> 1), G.oz + (Z >> 1));
         int ct = pick3(tt, G.ox + (tX >> 1), G.oy + (tY >> 1), G.oz + (tZ >> 1));
         const int Ls = pick3(t, C.L0, C.L1, C.L2);
@@ -916,7 +966,7 @@ struct GroupCall {
 // allows), each caching the rates of 8/G consecutive events; K = 1 with
 // n > 64 recomputes the rates from LDS at every step.  After a hop only the
 // events whose vacancy moved or whose target changed are recomputed.
-template <int K, int E, bool TR>
+template <int K, int E, bool TR, bool PK = false>
 __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, unsigned char* occl,
                                           uint32_t* sxyz, int n, uint32_t f, const GroupCall& X,
                                           int lane, Rec& rec, RecCtl& rc, uint32_t& ho, uint32_t& hh)
@@ -949,7 +999,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
 #pragma unroll
         for (int j = 0; j < E; j++) {
             if (j < epl) {
-                kk[j] = tile_rate(G, occl, C, my_xyz, my_d0 + j);
+                kk[j] = tile_rate<PK>(G, occl, C, my_xyz, my_d0 + j);
                 ls += kk[j];
             }
         }
@@ -991,7 +1041,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             ls = 0.0;
             for (int s = s0; s < s1; s++) {
                 const uint32_t xyz = sxyz[s];
-                for (int d = 0; d < 8; d++) ls += tile_rate(G, occl, C, xyz, d);
+                for (int d = 0; d < 8; d++) ls += tile_rate<PK>(G, occl, C, xyz, d);
             }
         }
         const double lsv = active ? ls : 0.0;
@@ -1046,7 +1096,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
                 for (int s = s0; s < s1 && found < 0; s++) {
                     const uint32_t xyz = sxyz[s];
                     for (int d = 0; d < 8; d++) {
-                        const double k = tile_rate(G, occl, C, xyz, d);
+                        const double k = tile_rate<PK>(G, occl, C, xyz, d);
                         if (k > 0.0) { last = s * 8 + d; lx = xyz; }
                         Cc += k;
                         if (!fb && Cc > y) { found = s * 8 + d; lx = xyz; break; }
@@ -1073,14 +1123,19 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         int sk, sli, tk, tli;
         const int spos = xyz_lds(G, sx, sk, sli);
         const int tpos = xyz_lds(G, tx, tk, tli);
-        const int sp = occl[tpos];
+        const int sp = occ_at<PK>(occl, tpos);
         wave_lds_order();
         int64_t sst = 0, tst = 0;  // storage offsets, in the lanes that apply a hop
         if (go && sl == 0) {
             sst = seg_st(G, sk) + sli;
             tst = seg_st(G, tk) + tli;
-            occl[spos] = (unsigned char)sp;
-            occl[tpos] = (unsigned char)kSpV;
+            if (PK) {
+                pk_set((uint32_t*)occl, spos, sp);
+                pk_set((uint32_t*)occl, tpos, kSpV);
+            } else {
+                occl[spos] = (unsigned char)sp;
+                occl[tpos] = (unsigned char)kSpV;
+            }
             sxyz[pslot] = tx;
             if (X.write_occ) {
                 X.occ[sst] = (int8_t)sp;
@@ -1112,7 +1167,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             // first 8, pulled by the lanes that cache them
             if (__ballot(mover)) {
                 double nk = 0.0;
-                if (go && sl < 8) nk = tile_rate(G, occl, C, tx, sl);
+                if (go && sl < 8) nk = tile_rate<PK>(G, occl, C, tx, sl);
 #pragma unroll
                 for (int j = 0; j < E; j++) {
                     const double v = lane_pull(nk, sb + ((my_d0 + j) & 7));
@@ -1184,7 +1239,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
         }
         gb_live = __ballot(hit) != 0;
     }
-    const RateCtx C = {D.L[0], D.L[1], D.L[2], gb_live ? D.gb_period : 0, D.gb_mask, W.k12};
+    const RateCtx C = {D.L[0], D.L[1], D.L[2], gb_live ? D.gb_period : 0, D.gb_mask, W.k12, D.gb_map};
     int n_seg = 0;
     if (!single) {
         if (resident) {
@@ -2512,7 +2567,7 @@ __device__ __forceinline__ double plain_rate(const LatDesc& D, const DevPtrs& P,
     if (sp == kSpV) return 0.0;
     const int cs = t == 0 ? i : (t == 1 ? j : k);
     const int ct = tt == 0 ? (X >> 1) : (tt == 1 ? (Y >> 1) : (Z >> 1));
-    const int g = is_gb(D, t, cs) | is_gb(D, tt, ct);
+    const int g = edge_gb(D, i, j, k, t, X >> 1, Y >> 1, Z >> 1, tt, cs, ct);
     return D.k12[(sp * 3 + hz + 1) * 2 + g];
 }
 
@@ -2872,7 +2927,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain_site(DevPtrs P, const i
             const int sp = occ[ts];
             const int cs = t == 0 ? i : (t == 1 ? j : k);
             const int ct = tt == 0 ? (X >> 1) : (tt == 1 ? (Y >> 1) : (Z >> 1));
-            const int g = is_gb(D, t, cs) | is_gb(D, tt, ct);
+            const int g = edge_gb(D, i, j, k, t, X >> 1, Y >> 1, Z >> 1, tt, cs, ct);
             tpk[tid] = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) | ((uint64_t)(Z >> 1) << 32) |
                        ((uint64_t)tt << 48);
             tsp[tid] = sp;

@@ -63,6 +63,9 @@ struct LatDesc {
     int32_t site_pad;
     const uint32_t* site_fe;   // Fe bitmap, one bit per cell (canonical cell order)
     const double* site_table;  // quantised rates [(X*3 + dz+1)*2 + g][dE + window]
+    // boundary sites as a map (Voronoi grains): one bit per site in canonical
+    // order; when set it replaces the planes (nullptr: planes)
+    const uint32_t* gb_map;
 };
 
 // Per-call parameters.

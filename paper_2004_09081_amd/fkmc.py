@@ -120,6 +120,8 @@ _SIGS = {
     "fkmc_phase_timing": [C.c_void_p, _P(C.c_double), _P(C.c_uint64)],
     "fkmc_quantisation": [C.c_void_p, C.c_uint32, _P(C.c_double), _P(C.c_double)],
     "fkmc_site_model_bytes": [C.c_void_p, C.c_uint32, C.c_int32, _P(C.c_size_t)],
+    "fkmc_gb_map_bytes": [C.c_void_p, C.c_uint32, _P(C.c_size_t)],
+    "fkmc_set_gb_map": [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t],
     "fkmc_set_site_model": [C.c_void_p, C.c_uint32, C.c_void_p, _P(C.c_int32), _P(C.c_int32), C.c_int32,
                             C.c_void_p, C.c_size_t],
     "fkmc_last_error": [],
@@ -255,6 +257,22 @@ class LatticeSet:
         if not hasattr(self, "_site_bufs"):
             self._site_bufs = {}
         self._site_bufs[int(i)] = buf
+
+    def set_gb_map(self, i: int, gb_map):
+        """Boundary sites of lattice i as a map (fkmc_set_gb_map): one byte
+        per site in canonical order; None removes it."""
+        import torch
+        if gb_map is None:
+            _check(lib().fkmc_set_gb_map(self._h, int(i), None, None, 0))
+            return
+        n = C.c_size_t()
+        _check(lib().fkmc_gb_map_bytes(self._h, int(i), C.byref(n)))
+        buf = torch.empty(max(n.value, 1), dtype=torch.uint8, device=self.device)
+        m = np.ascontiguousarray(gb_map, dtype=np.uint8).reshape(-1)
+        _check(lib().fkmc_set_gb_map(self._h, int(i), m.ctypes.data, buf.data_ptr(), n.value))
+        if not hasattr(self, "_gb_bufs"):
+            self._gb_bufs = {}
+        self._gb_bufs[int(i)] = buf
 
     def set_rate_table(self, i: int, k12):
         _check(lib().fkmc_set_rate_table(self._h, i, _dbl(k12), 12))

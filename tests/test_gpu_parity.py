@@ -792,3 +792,58 @@ def test_transfers_larger_than_one_stage_chunk():
     lat.advance(t_sync, max_cycles=1)
     assert_same_state(h, 0, lat, "restored from checkpoint")
     assert_same_state(g, 0, lat, "uninterrupted")
+
+
+# Voronoi grain boundaries as a site map (the micro-scale model's grains):
+# fragment lattices held in LDS and staged, a plain lattice (HBM kernel)
+VORONOI_CASES = [
+    (Case((18, 16, 20), (6, 6, 6), seed=81, lattice_id=0, nv=60, nh=300, T=650.0, Ea_O=0.6, Ea_H=0.45,
+          E_z=2e8, gb_dE=0.2), 6),
+    (Case((34, 32, 30), (8, 8, 8), seed=81, lattice_id=1, nv=200, nh=0, T=600.0, Ea_O=0.55, E_z=1e8,
+          gb_dE=0.2), 10),
+    (Case((12, 10, 14), (12, 10, 14), seed=81, lattice_id=2, nv=20, nh=40, T=650.0, Ea_O=0.6, Ea_H=0.45,
+          gb_dE=0.15), 3),
+    (Case((10, 9, 11), seed=81, lattice_id=3, nv=30, nh=60, T=650.0, Ea_O=0.6, Ea_H=0.45, E_z=1e8,
+          gb_dE=0.2), 4),
+]
+
+
+def _voronoi_oracle(c, n_grains):
+    from paper_2004_09081_amd import workloads as W
+    gmap = W.voronoi_boundary_map(c.L, n_grains, 1.0, c.lattice_id)
+    g = O.Geometry(L=c.L, frag=c.frag, a_angstrom=c.a, seed=c.seed, lattice_id=c.lattice_id, gb_map=gmap)
+    lat = O.Lattice(g)
+    lat.init_random(c.nv, c.nh)
+    lat.set_rates(O.RateParams(**c.rp))
+    return lat, gmap
+
+
+@pytest.mark.parametrize("schedule,group", [("lockstep", 0), ("persistent", 0), ("persistent", 8),
+                                            ("persistent", 1)])
+def test_voronoi_boundary_map_matches_oracle(schedule, group):
+    """Grain boundaries from a Voronoi site map (barrier +gb_dE on every
+    edge touching a boundary site) under both schedules and several tile
+    groups, resident and staged fragments, one fragment, and plain BKL: the
+    oracle's trajectories bit for bit."""
+    say("Voronoi boundary map", schedule, group)
+    cases = [c for c, _ in VORONOI_CASES]
+    pairs = [_voronoi_oracle(c, n) for c, n in VORONOI_CASES]
+    g = gpu_set(cases)
+    for i, (_, gmap) in enumerate(pairs):
+        g.set_gb_map(i, gmap)
+    g.set_schedule(schedule, 4)
+    g.set_group(group)
+    ts = [0.0 if c.frag[0] == 0 else 1.3 / (8.0 * lat.k12[0]) for c, (lat, _) in zip(cases, pairs)]
+    for max_cycles, min_hops in ((3, 0), (10**6, 1500)):
+        # (plain members make exactly min_hops hops)
+        for c, (lat, _), t in zip(cases, pairs, ts):
+            if c.frag[0] == 0:
+                lat.advance_plain(min_hops)
+            else:
+                lat.advance(t, max_cycles=max_cycles, min_hops=min_hops)
+        g.advance(ts, max_cycles=max_cycles, min_hops=min_hops)
+        st = g.read_stats()
+        for i, (lat, _) in enumerate(pairs):
+            what = "voronoi member %d %s" % (i, cases[i].L)
+            assert st[i]["t"] == lat.t and st[i]["hops"].tolist() == [int(x) for x in lat.hops], what
+            assert_same_state(g, i, lat, what)

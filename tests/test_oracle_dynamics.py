@@ -325,3 +325,47 @@ def test_diffusion_across_boundary_planes_matches_projected_chain(axis):
     se = x2.std(ddof=1) / math.sqrt(R)
     assert abs(est - msd_ref) < 4 * se, (est, msd_ref, se)
     assert abs(msd_free - msd_ref) > 10 * se, (msd_free, msd_ref, se)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_boundary_site_map_of_planes_equals_planes(plain):
+    """A boundary-site map that marks exactly the plane sites (type-a sites
+    of the cells whose index along a masked axis a is a multiple of the
+    period) gives the plane model's trajectories bit for bit, in fragment
+    cycles and in plain BKL: the map path inherits the planes' pins."""
+    L, frag, P, mask = (9, 8, 10), ((0, 0, 0) if plain else (4, 4, 5)), 3, 5
+    rp = O.RateParams(T=650.0, Ea_O=0.6, Ea_H=0.45, E_z=1e8, gb_period_cells=P, gb_axes_mask=mask,
+                      gb_dE=0.1)
+    gmap = np.zeros(3 * L[0] * L[1] * L[2], np.uint8)
+    for k in range(L[2]):
+        for j in range(L[1]):
+            for i in range(L[0]):
+                for t, c in enumerate((i, j, k)):
+                    if (mask >> t) & 1 and c % P == 0:
+                        gmap[((k * L[1] + j) * L[0] + i) * 3 + t] = 1
+    lats = []
+    for m in (None, gmap):
+        lat = O.Lattice(O.Geometry(L=L, frag=frag, seed=3, lattice_id=1, gb_period_cells=P, gb_axes_mask=mask,
+                                   gb_map=m))
+        lat.init_random(25, 60)
+        lat.set_rates(rp)
+        lats.append(lat)
+    for _ in range(2):
+        for lat in lats:
+            if plain:
+                lat.advance_plain(800)
+            else:
+                lat.advance(2.0 / (8 * lat.k12[0]), max_cycles=3)
+    a, b = lats
+    assert a.t == b.t and np.array_equal(a.occ, b.occ) and np.array_equal(a.disp, b.disp)
+    assert int(a.hops.sum()) > 0
+    # a different map changes the trajectory
+    c = O.Lattice(O.Geometry(L=L, frag=frag, seed=3, lattice_id=1, gb_map=np.roll(gmap, 1)))
+    c.init_random(25, 60)
+    c.set_rates(rp)
+    for _ in range(2):
+        if plain:
+            c.advance_plain(800)
+        else:
+            c.advance(2.0 / (8 * c.k12[0]), max_cycles=3)
+    assert not np.array_equal(a.occ, c.occ)

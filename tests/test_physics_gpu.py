@@ -220,3 +220,44 @@ def test_cfg3_drift_and_diffusion_tensor():
     say("  D tensor of V (A^2/s, xx yy zz xy xz yz): %s" % np.array2string(st["Dtensor"][2], precision=4))
     assert abs(vV[2] - v_ref) < 3 * se_v[2] + 0.01 * abs(v_ref)
     assert abs(vV[0]) < 4 * se_v[0] and abs(vV[1]) < 4 * se_v[1]
+
+
+@pytest.mark.parametrize("field", [False, True])
+def test_voronoi_boundaries_hold_vacancies_only_under_a_field(field):
+    """Grains from a Voronoi site map with a +0.2 eV boundary layer (the
+    micro-scale model's grain boundaries), 32 lattices of 48 x 16 x 64
+    cells, 0.2 % vacancies, 650 K, about 2,000 hops per vacancy.  The
+    barrier is symmetric, so without a field the uniform law stays
+    stationary and the vacancies sit on boundary sites as often as those
+    sites occur (within 4 sigma); with a field along -z the boundary layers
+    slow the drifting vacancies, which then gather there (at least twice the
+    site fraction)."""
+    from paper_2004_09081_amd import workloads as W
+    from paper_2004_09081_amd import fkmc as F
+    L, R, T = (48, 16, 64), 32, 650.0
+    nv, _ = W.counts(3 * 48 * 16 * 64, 0.002, 0.0)
+    E = -1e8 if field else 0.0
+    cases = [Case(L, (16, 16, 16), seed=91, lattice_id=i, nv=nv, nh=0, T=T, Ea_O=0.6, E_z=E, gb_dE=0.2)
+             for i in range(R)]
+    maps = [W.voronoi_boundary_map(L, 5, 1.0, i) for i in range(R)]
+    say("Voronoi boundaries, field" if field else "Voronoi boundaries, no field")
+    g = gpu_set(cases)
+    for i, m in enumerate(maps):
+        g.set_gb_map(i, m)
+    k0 = 1e13 * math.exp(-0.6 / (KB * T))
+    t_sync = 1.0 / (8 * k0)
+    g.advance([t_sync] * R, max_cycles=2000, min_hops=0)
+    on, frac = [], []
+    for i in range(R):
+        occ, _ = g.read_state(i, with_disp=False)
+        v = occ == 2
+        on.append(float(maps[i][v].mean()))
+        frac.append(float(maps[i].mean()))
+    on, frac = np.array(on), np.array(frac)
+    ratio = on / frac
+    se = ratio.std(ddof=1) / math.sqrt(R)
+    say("  vacancies on boundary sites / boundary site fraction: %.3f +- %.3f" % (ratio.mean(), se))
+    if field:
+        assert ratio.mean() > 2.0
+    else:
+        assert abs(ratio.mean() - 1.0) < 4 * se + 0.02
