@@ -162,15 +162,17 @@ def voronoi_boundary_map(L, n_grains: int, width: float, seed: int) -> np.ndarra
     return out
 
 
-def micro(L=(200, 50, 300), frag: int = 16, n_grains: int = 6, width: float = 1.0, seed: int = 0):
+def micro(L=(200, 50, 300), frag: int = 8, n_grains: int = 6, width: float = 1.0, seed: int = 0):
     """Reduced micro-scale BaTiO3 model (Sec. "Oxygen diffusion in
     micro-scale BaTiO3 model"): Voronoi grains separated by a boundary layer
     whose hops carry +0.2 eV (0.9 eV through the boundary against 0.7 eV in
     the grains), 0.1 % vacancies, the bias of the paper's model (20 V over
     962.4 nm along z, top +10 V: the field points to -z), open z boundary as
-    periodic with unwrapped displacements, 450 K, 16^3-cell fragments.  The
-    box is 200 x 50 x 300 cells (78 x 20 x 117 nm) instead of the paper's
-    1600 x 400 x 2400.  Returns the spec and its boundary-site map."""
+    periodic with unwrapped displacements, 450 K, 8^3-cell fragments (the
+    vacancies pile up at the boundaries, past the 128 a BKL domain holds in
+    16^3-cell fragments).  The box is 200 x 50 x 300 cells (78 x 20 x
+    117 nm) instead of the paper's 1600 x 400 x 2400.  Returns the spec and
+    its boundary-site map."""
     nv, _ = counts(3 * L[0] * L[1] * L[2], 0.001, 0.0)
     ts = window_one_hop(450.0, 0.70, 0.25, 0.0, 0.001)
     spec = LatticeSpec(L=tuple(L), frag=(frag,) * 3, seed=seed, lattice_id=0, n_vac=nv, n_h=0, T=450.0,
