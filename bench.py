@@ -56,7 +56,7 @@ KERNEL_SOURCES = ("paper_2004_09081_amd/csrc/fkmc_device.hip",
                   "paper_2004_09081_amd/csrc/fkmc_api.hip",
                   "paper_2004_09081_amd/autotune.py")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.md")
-PLAIN_MAX_VACANCIES = 4096
+PLAIN_MAX_VACANCIES = 8192
 
 
 def log(*a):
@@ -446,7 +446,7 @@ def atomic_leg(F, specs, n_frg, stages):
 
 
 def atomic_hbm_leg(F, specs, n_frg, stages):
-    """The atom-selection scheme on the ensemble lattices of at most 4096
+    """The atom-selection scheme on the ensemble lattices of at most 8192
     vacancies that the persistent kernel does not hold in LDS (more than
     512 vacancies, or an occupancy too large for its LDS share), all in one
     call, against plain BKL making the same mean number of hops from the
@@ -456,7 +456,7 @@ def atomic_hbm_leg(F, specs, n_frg, stages):
     from paper_2004_09081_amd.autotune import plain_if_sparse
     sel = []
     for sp in specs:
-        if plain_if_sparse(sp) != 0 and sp.n_vac <= 4096:
+        if plain_if_sparse(sp) != 0 and sp.n_vac <= PLAIN_MAX_VACANCIES:
             q = copy.copy(sp)
             q.frag = (0, 0, 0)
             q.t_sync = 0.0
@@ -486,7 +486,7 @@ def atomic_hbm_leg(F, specs, n_frg, stages):
            "us_per_stage": 1e3 * max(x["busy_ms"] for x in st_a) / stages,
            "bkl_same_lattices": {"value": float(hops_b.sum() / t_b), "unit": "hops/s",
                                  "hops_per_lattice": target},
-           "sample": "%d of %d ensemble lattices (at most 4096 vacancies, not held in LDS by the "
+           "sample": "%d of %d ensemble lattices (at most 8192 vacancies, not held in LDS by the "
                      "persistent kernel; unfragmented), %d stages of %d selections; BKL the same mean "
                      "hop count" % (len(sel), len(specs), stages, n_frg)}
     log("atom selection on lattices past the persistent kernel's LDS (N_frg %d): %.4g hops/s on %d lattices, %.2f hops per stage, "

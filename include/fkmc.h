@@ -271,7 +271,7 @@ fkmc_status fkmc_max_domain_sites(const fkmc_geometry* g, uint64_t* out);
  * t_sync may be NULL for plain-only sets (no horizon).
  * FKMC_E_RANGE when a BKL domain (a fragment lattice's sub-block plus its
  * three +faces) holds more than 128 vacancies, or a plain lattice on the
- * HBM kernel more than 4096; such a domain makes no hop in that phase, so
+ * HBM kernel more than 8192; such a domain makes no hop in that phase, so
  * the trajectory no longer follows the method.  The error stays set: every
  * later advance, sync or read of the set reports it until fkmc_init_random
  * or fkmc_set_occupancy initialises that lattice again. */
@@ -280,7 +280,7 @@ fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_c
 
 /* Atom-selection fragment kMC with null events (Sec. "Atomic-based fragment
  * kMC method", Eqs. AtomP and TimeStepFrg), for sets whose lattices are all
- * plain (fragment edge 0) with at most 4096 vacancies.  Runs n_stages
+ * plain (fragment edge 0) with at most 8192 vacancies.  Runs n_stages
  * stages on every lattice (fewer when no event is possible), one workgroup
  * per lattice: a lattice that fits in LDS (at most 512 vacancies, occupancy
  * at 2 bits per site plus the rate table within 64 KB) runs there on one
@@ -299,7 +299,7 @@ fkmc_status fkmc_advance(fkmc_lattice* lat, const double* t_sync, uint64_t max_c
  * counter is the lattice's draw counter (fkmc_stats.draws).  With n_frg = 1
  * the trajectory is an exact kMC trajectory; with more, simultaneous
  * selections make it the paper's parallel approximation.  Synchronous.
- * FKMC_E_UNSUPPORTED for a fragment lattice or one of more than 4096
+ * FKMC_E_UNSUPPORTED for a fragment lattice or one of more than 8192
  * vacancies; FKMC_E_STATE when rates are not set. */
 fkmc_status fkmc_advance_atomic(fkmc_lattice* lat, uint32_t n_frg, uint64_t n_stages);
 

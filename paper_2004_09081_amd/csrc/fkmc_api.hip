@@ -963,6 +963,16 @@ static int pick_group(double lam, int fp_stride, int lds, bool all)
     return 1;
 }
 
+// Vacancy slots a launch of the HBM plain kernels holds in LDS: the largest
+// vacancy count among its lattices, rounded up to 256 (at most
+// kMaxPlainSlots; a lattice past that reports FKMC_E_RANGE from the kernel).
+static int plain_slot_cap(const fkmc_lattice* L, const int32_t* ids, size_t n)
+{
+    uint64_t mx = 1;
+    for (size_t k = 0; k < n; k++) mx = std::max<uint64_t>(mx, L->n_vac[ids[k]]);
+    return (int)std::min<uint64_t>((uint64_t)kMaxPlainSlots, (mx + 255) & ~(uint64_t)255);
+}
+
 static double mean_footprint_vacancies(const fkmc_lattice* L, uint32_t i)
 {
     return (double)L->n_vac[i] * (double)max_footprint(L->geo[i]) / (double)L->desc[i].n_sites;
@@ -1189,7 +1199,8 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         HIP_OK(hipMemcpyAsync(L->d_site_ids, site.data(), site.size() * 4, hipMemcpyHostToDevice, L->stream));
     fkmc_status s = prepare_call(L, t_sync, max_cycles, min_hops, true);
     if (s) return s;
-    LAUNCH_OK(launch_plain(L->P, L->d_plain_ids, (int)slow.size(), L->stream));
+    LAUNCH_OK(launch_plain(L->P, L->d_plain_ids, (int)slow.size(), plain_slot_cap(L, slow.data(), slow.size()),
+                           L->stream));
     LAUNCH_OK(launch_plain_site(L->P, L->d_site_ids, (int)site.size(), L->stream));
     size_t ev_used = 0;
     if (L->timing && any_frag && L->ev.empty()) {
@@ -1451,8 +1462,8 @@ fkmc_status fkmc_advance_atomic(fkmc_lattice* L, uint32_t n_frg, uint64_t n_stag
     L->last_persistent = false;
     LAUNCH_OK(launch_atomic(L->P, L->d_plain_ids, (int)in_lds.size(), (size_t)((lds + 15) & ~15), n_frg,
                             n_stages, L->stream));
-    LAUNCH_OK(launch_atomic_hbm(L->P, L->d_plain_ids + in_lds.size(), (int)in_hbm.size(), n_frg, n_stages,
-                                L->stream));
+    LAUNCH_OK(launch_atomic_hbm(L->P, L->d_plain_ids + in_lds.size(), (int)in_hbm.size(),
+                                plain_slot_cap(L, in_hbm.data(), in_hbm.size()), n_frg, n_stages, L->stream));
     return read_states(L);
 }
 

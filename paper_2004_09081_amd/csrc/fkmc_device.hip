@@ -400,16 +400,6 @@ __device__ __forceinline__ int gb_flag(const RateCtx& C, int t, int cell)
 // Rate of event d of the vacancy at packed local doubled coordinates xyz:
 // 0 when the hop edge's midpoint is outside the sub-block or the target
 // holds a vacancy; else the table entry for (ion species, z step, boundary).
-// Occupancy of the site at LDS position pos: one byte per site, or, with PK,
-// 2 bits per site (16 per 32-bit word: word pos >> 4, bits 2 (pos & 15)).
-template <bool PK>
-__device__ __forceinline__ int occ_at(const unsigned char* occl, int pos)
-{
-    if (PK) return (int)((((const uint32_t*)occl)[pos >> 4] >> ((pos & 15) << 1)) & 3u);
-    return occl[pos];
-}
-
-template <bool PK = false>
 __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned char* occl,
                                             const RateCtx& C, uint32_t xyz, int d)
 {
@@ -426,7 +416,7 @@ __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned cha
     // (an active edge's target is in the footprint; an inactive edge reads
     // the first brick byte instead, so every address stays in bounds)
     const int lds0 = G.lds0;
-    const int sp = occ_at<PK>(occl, in ? seg_lds(G, seg) + li : lds0);
+    const int sp = occl[in ? seg_lds(G, seg) + li : lds0];
     int g = 0;
     if (C.gbmap) {
         int si = G.ox + (X >> 1), sj = G.oy + (Y >> 1), sk = G.oz + (Z >> 1);
@@ -966,7 +956,7 @@ struct GroupCall {
 // allows), each caching the rates of 8/G consecutive events; K = 1 with
 // n > 64 recomputes the rates from LDS at every step.  After a hop only the
 // events whose vacancy moved or whose target changed are recomputed.
-template <int K, int E, bool TR, bool PK = false>
+template <int K, int E, bool TR>
 __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, unsigned char* occl,
                                           uint32_t* sxyz, int n, uint32_t f, const GroupCall& X,
                                           int lane, Rec& rec, RecCtl& rc, uint32_t& ho, uint32_t& hh)
@@ -999,7 +989,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
 #pragma unroll
         for (int j = 0; j < E; j++) {
             if (j < epl) {
-                kk[j] = tile_rate<PK>(G, occl, C, my_xyz, my_d0 + j);
+                kk[j] = tile_rate(G, occl, C, my_xyz, my_d0 + j);
                 ls += kk[j];
             }
         }
@@ -1041,7 +1031,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             ls = 0.0;
             for (int s = s0; s < s1; s++) {
                 const uint32_t xyz = sxyz[s];
-                for (int d = 0; d < 8; d++) ls += tile_rate<PK>(G, occl, C, xyz, d);
+                for (int d = 0; d < 8; d++) ls += tile_rate(G, occl, C, xyz, d);
             }
         }
         const double lsv = active ? ls : 0.0;
@@ -1096,7 +1086,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
                 for (int s = s0; s < s1 && found < 0; s++) {
                     const uint32_t xyz = sxyz[s];
                     for (int d = 0; d < 8; d++) {
-                        const double k = tile_rate<PK>(G, occl, C, xyz, d);
+                        const double k = tile_rate(G, occl, C, xyz, d);
                         if (k > 0.0) { last = s * 8 + d; lx = xyz; }
                         Cc += k;
                         if (!fb && Cc > y) { found = s * 8 + d; lx = xyz; break; }
@@ -1123,19 +1113,14 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         int sk, sli, tk, tli;
         const int spos = xyz_lds(G, sx, sk, sli);
         const int tpos = xyz_lds(G, tx, tk, tli);
-        const int sp = occ_at<PK>(occl, tpos);
+        const int sp = occl[tpos];
         wave_lds_order();
         int64_t sst = 0, tst = 0;  // storage offsets, in the lanes that apply a hop
         if (go && sl == 0) {
             sst = seg_st(G, sk) + sli;
             tst = seg_st(G, tk) + tli;
-            if (PK) {
-                pk_set((uint32_t*)occl, spos, sp);
-                pk_set((uint32_t*)occl, tpos, kSpV);
-            } else {
-                occl[spos] = (unsigned char)sp;
-                occl[tpos] = (unsigned char)kSpV;
-            }
+            occl[spos] = (unsigned char)sp;
+            occl[tpos] = (unsigned char)kSpV;
             sxyz[pslot] = tx;
             if (X.write_occ) {
                 X.occ[sst] = (int8_t)sp;
@@ -1167,7 +1152,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             // first 8, pulled by the lanes that cache them
             if (__ballot(mover)) {
                 double nk = 0.0;
-                if (go && sl < 8) nk = tile_rate<PK>(G, occl, C, tx, sl);
+                if (go && sl < 8) nk = tile_rate(G, occl, C, tx, sl);
 #pragma unroll
                 for (int j = 0; j < E; j++) {
                     const double v = lane_pull(nk, sb + ((my_d0 + j) & 7));
@@ -2588,14 +2573,14 @@ __device__ __forceinline__ bool plain_adjacent(const LatDesc& D, uint64_t a, uin
 }
 
 // Each thread owns a contiguous range of slots; the total rate of every
-// slot is kept in LDS, so a step sums m <= 16 totals per thread, scans the
+// slot is kept in LDS, so a step sums m <= 32 totals per thread, scans the
 // workgroup, evaluates the 8 rates of the selected slot only, and after the
 // hop re-evaluates just the slots next to its two sites.
 // Vacancy slots of a plain lattice in ascending canonical index, as packed
-// cell/type positions (at most kMaxPlainSlots are stored); every thread of
-// the workgroup calls it and gets the vacancy count.
+// cell/type positions (at most cap are stored); every thread of the
+// workgroup calls it and gets the vacancy count.
 __device__ int plain_collect_slots(const LatDesc& D, const DevPtrs& P, uint64_t* slots, int* wcount,
-                                   int* n_sh, int tid, int cap = kMaxPlainSlots)
+                                   int* n_sh, int tid, int cap)
 {
     const int lane = tid & 63, wv = tid >> 6;
     constexpr int NW = kPlainThreads / 64;
@@ -2635,11 +2620,11 @@ __device__ int plain_collect_slots(const LatDesc& D, const DevPtrs& P, uint64_t*
     return *n_sh;
 }
 
-__global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_t* ids)
+__global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_t* ids, int cap)
 {
     extern __shared__ __align__(16) unsigned char psm[];
-    uint64_t* slots = (uint64_t*)psm;                     // [kMaxPlainSlots]
-    double* stot = (double*)(psm + 8 * kMaxPlainSlots);   // [kMaxPlainSlots]
+    uint64_t* slots = (uint64_t*)psm;                     // [cap]
+    double* stot = (double*)(psm + 8 * (size_t)cap);      // [cap]
     __shared__ int wcount[kPlainThreads / 64];
     __shared__ double wsum[kPlainThreads / 64];
     __shared__ uint64_t wmask[kPlainThreads / 64];
@@ -2656,8 +2641,8 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain(DevPtrs P, const int32_
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     constexpr int NW = kPlainThreads / 64;
 
-    const int n = plain_collect_slots(D, P, slots, wcount, &n_sh, tid);
-    if (n > kMaxPlainSlots) {
+    const int n = plain_collect_slots(D, P, slots, wcount, &n_sh, tid, cap);
+    if (n > cap) {
         if (tid == 0) atomicOr(&S->err, 1u);
         return;
     }
@@ -3132,14 +3117,14 @@ static_assert(kMaxPlainSlots <= 65536, "slot indices of the refresh list are 16-
 // their sites; the next stage recomputes the totals of the slots in marked
 // cells only.  Two mark bitmaps alternate, so that one is cleared while the
 // other is written.
-__global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const int32_t* ids,
+__global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const int32_t* ids, int cap,
                                                               uint32_t n_frg, uint64_t n_stages)
 {
     extern __shared__ __align__(16) unsigned char psm[];
-    uint64_t* slots = (uint64_t*)psm;                         // [kMaxPlainSlots]
-    double* stot = (double*)(psm + 8 * kMaxPlainSlots);       // [kMaxPlainSlots]
-    uint32_t* marks = (uint32_t*)(psm + 16 * kMaxPlainSlots); // [2][kMarkWords]
-    uint16_t* fresh = (uint16_t*)(marks + 2 * kMarkWords);   // [kMaxPlainSlots] slots to recompute
+    uint64_t* slots = (uint64_t*)psm;                           // [cap]
+    double* stot = (double*)(psm + 8 * (size_t)cap);            // [cap]
+    uint32_t* marks = (uint32_t*)(psm + 16 * (size_t)cap);      // [2][kMarkWords]
+    uint16_t* fresh = (uint16_t*)(marks + 2 * kMarkWords);     // [cap] slots to recompute
     __shared__ int n_fresh;
     __shared__ int wcount[kPlainThreads / 64];
     __shared__ double wsum[kPlainThreads / 64];
@@ -3151,8 +3136,8 @@ __global__ __launch_bounds__(kPlainThreads) void k_atomic_hbm(DevPtrs P, const i
     LatState* S = P.state + lat;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     constexpr int NW = kPlainThreads / 64;
-    const int n = plain_collect_slots(D, P, slots, wcount, &n_sh, tid);
-    if (n > kMaxPlainSlots) {
+    const int n = plain_collect_slots(D, P, slots, wcount, &n_sh, tid, cap);
+    if (n > cap) {
         if (tid == 0) atomicOr(&S->err, 1u);
         return;
     }
@@ -3547,15 +3532,16 @@ int launch_cycle_begin(const DevPtrs& P, void* stream)
     return (int)hipGetLastError();
 }
 
-int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void* stream)
+int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, int cap, void* stream)
 {
     if (n_plain == 0) return 0;
-    const size_t lds = (size_t)16 * kMaxPlainSlots;
+    if (cap < 1 || cap > kMaxPlainSlots) return (int)hipErrorInvalidValue;
+    const size_t lds = (size_t)16 * cap;
     hipError_t e = hipFuncSetAttribute((const void*)k_plain, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(k_plain, dim3(n_plain), dim3(kPlainThreads), lds, (hipStream_t)stream, P,
-                       d_plain_ids);
+                       d_plain_ids, cap);
     return (int)hipGetLastError();
 }
 
@@ -3570,16 +3556,17 @@ int launch_plain_site(const DevPtrs& P, const int32_t* d_ids, int n, void* strea
     return (int)hipGetLastError();
 }
 
-int launch_atomic_hbm(const DevPtrs& P, const int32_t* d_ids, int n, uint32_t n_frg, uint64_t n_stages,
-                      void* stream)
+int launch_atomic_hbm(const DevPtrs& P, const int32_t* d_ids, int n, int cap, uint32_t n_frg,
+                      uint64_t n_stages, void* stream)
 {
     if (n == 0) return 0;
-    const size_t lds = (size_t)18 * kMaxPlainSlots + (size_t)8 * kMarkWords;
+    if (cap < 1 || cap > kMaxPlainSlots) return (int)hipErrorInvalidValue;
+    const size_t lds = (size_t)18 * cap + (size_t)8 * kMarkWords;
     hipError_t e = hipFuncSetAttribute((const void*)k_atomic_hbm, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(k_atomic_hbm, dim3(n), dim3(kPlainThreads), lds, (hipStream_t)stream, P, d_ids,
-                       n_frg, n_stages);
+                       cap, n_frg, n_stages);
     return (int)hipGetLastError();
 }
 

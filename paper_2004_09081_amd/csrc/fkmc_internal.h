@@ -25,7 +25,10 @@ constexpr int kSpV = 2;
 constexpr int kMaxWidth = 100;      // largest sub-block edge (cells)
 constexpr int kMaxLdsPerBlock = 65536;  // dynamic LDS of one phase workgroup
 constexpr int kMaxSlots = 128;      // vacancies per fragment-mode footprint
-constexpr int kMaxPlainSlots = 4096;  // vacancies per plain-mode lattice
+// vacancies per plain-mode lattice in the HBM kernels (their slots and
+// totals sit in LDS, 16-18 bytes each, sized per launch for its largest
+// lattice: 8192 slots take 128-148 KB of the 160 KB of a compute unit)
+constexpr int kMaxPlainSlots = 8192;
 constexpr int kPlainLdsSlots = 512;
 constexpr int kAtomMarkBits = 13;     // hashed cell bitmap of the LDS atom-selection kernel
 constexpr int kAtomMarkWords = 1 << (kAtomMarkBits - 5);   // vacancies per plain lattice held in LDS
@@ -141,13 +144,13 @@ int launch_init(const DevPtrs& P, const uint64_t* d_counts, int n_lat, void* str
 int launch_phase(const DevPtrs& P, int colour, int group, void* stream);
 int launch_cycle_begin(const DevPtrs& P, void* stream);
 int launch_cycle_end(const DevPtrs& P, void* stream);
-int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, void* stream);
+int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, int cap, void* stream);
 // Plain BKL with site-energy interactions, one workgroup per listed lattice.
 constexpr int kMaxSiteSlots = 2048;
 constexpr int kMaxSiteWindow = 2047;  // meV: table indices stay below 2^16
 int launch_plain_site(const DevPtrs& P, const int32_t* d_ids, int n, void* stream);
-int launch_atomic_hbm(const DevPtrs& P, const int32_t* d_ids, int n, uint32_t n_frg, uint64_t n_stages,
-                      void* stream);
+int launch_atomic_hbm(const DevPtrs& P, const int32_t* d_ids, int n, int cap, uint32_t n_frg,
+                      uint64_t n_stages, void* stream);
 int launch_stats(const DevPtrs& P, int lat, int64_t n_sites, void* stream);
 // Canonical <-> storage order over canonical sites [begin, begin + count) of
 // one lattice; the canonical arrays hold exactly those sites.

@@ -153,6 +153,55 @@ def test_plain_matches_oracle(name, lds):
     assert_same_state(g, 0, lat, name + " horizon")
 
 
+# plain lattices past 4096 vacancies (the densest ensemble lattices hold up
+# to 7,350): the HBM kernel sizes its LDS slot list per launch
+PLAIN_BIG_CASES = [
+    Case((16, 16, 17), seed=31, lattice_id=0, nv=4097, nh=800, T=620.0, Ea_O=0.6, Ea_H=0.45),
+    Case((20, 20, 20), seed=32, lattice_id=1, nv=7350, nh=3000, T=600.0, Ea_O=0.6, Ea_H=0.45, E_z=1e8,
+         gb_period=6, gb_dE=0.05),
+    Case((20, 20, 21), seed=33, lattice_id=2, nv=8192, nh=0, T=650.0, Ea_O=0.6),
+    Case((8, 7, 6), seed=34, lattice_id=3, nv=600, nh=40, T=650.0, Ea_O=0.6, Ea_H=0.45),
+]
+
+
+def test_plain_past_4096_vacancies_matches_oracle():
+    """Plain BKL on the HBM kernel with 4097, 7350 and 8192 vacancies in one
+    launch (slot list sized for the largest) beside a small lattice: draws,
+    clock, hops and state equal the oracle's after two calls and a call
+    stopped by its horizon; one vacancy more than the kernel holds is
+    reported as FKMC_E_RANGE."""
+    from paper_2004_09081_amd import fkmc as F
+    say("plain parity past 4096 vacancies")
+    lats = [c.oracle() for c in PLAIN_BIG_CASES]
+    g = gpu_set(PLAIN_BIG_CASES)
+    for n_hops in (800, 1200):
+        for lat in lats:
+            lat.advance_plain(n_hops)
+        g.advance([0.0] * len(lats), 0, n_hops)
+        stats = g.read_stats()
+        for i, lat in enumerate(lats):
+            assert stats[i]["lds_resident"] == 0
+            assert stats[i]["draws"] == lat.draws and stats[i]["t"] == lat.t, i
+            assert stats[i]["hops"].tolist() == [int(x) for x in lat.hops], i
+            assert_same_state(g, i, lat, "plain big %d" % i)
+    # about 300 hops' worth of time on each lattice
+    hz = [300.0 / (8 * lat.k12[0] * c.nv) for lat, c in zip(lats, PLAIN_BIG_CASES)]
+    h0 = [int(lat.hops.sum()) for lat in lats]
+    for lat, h in zip(lats, hz):
+        lat.advance_plain(10**9, t_horizon=h)
+    g.advance(hz, 0, 10**9)
+    stats = g.read_stats()
+    for i, lat in enumerate(lats):
+        assert 0 < int(lat.hops.sum()) - h0[i] < 20000
+        assert stats[i]["draws"] == lat.draws and stats[i]["t"] == lat.t, i
+        assert_same_state(g, i, lat, "plain big %d horizon" % i)
+    g.close()
+    g = gpu_set([Case((20, 20, 21), seed=2, nv=8193)])
+    with pytest.raises(F.FkmcError) as e:
+        g.advance([0.0], 0, 10)
+    assert e.value.code == -4
+
+
 # plain-mode degenerate cases: one vacancy, none, no ion to hop onto (no
 # event at all), and a call ended by the horizon rather than the hop count
 PLAIN_EDGE_CASES = {
@@ -212,6 +261,8 @@ ATOMIC_CASES = [
     Case((40, 30, 20), seed=23, lattice_id=12, nv=1200, nh=3000, T=650.0, Ea_O=0.6, Ea_H=0.45,
          E_z=1e8, gb_period=7, gb_dE=0.08),
     Case((16, 16, 16), seed=24, lattice_id=13, nv=4096, nh=0, T=600.0, Ea_O=0.6),
+    # the largest slot count of the HBM kernel (one vacancy in three sites)
+    Case((20, 20, 21), seed=25, lattice_id=14, nv=8192, nh=2000, T=600.0, Ea_O=0.6, Ea_H=0.45, E_z=5e7),
 ]
 
 
@@ -299,7 +350,7 @@ def test_atomic_rejects_what_it_cannot_run():
     g = gpu_set([ATOMIC_CASES[0], Case((6, 6, 6), (3, 3, 3), seed=1, nv=4)])
     with pytest.raises(F.FkmcError):
         g.advance_atomic(1, 1)
-    g = gpu_set([Case((16, 16, 17), seed=2, nv=4097)])
+    g = gpu_set([Case((20, 20, 21), seed=2, nv=8193)])
     with pytest.raises(F.FkmcError) as e:
         g.advance_atomic(1, 1)
     assert e.value.code == -6
