@@ -1646,7 +1646,7 @@ __device__ __forceinline__ int plain_nb(const RateCtx& C, uint32_t p, int d, uin
     if (TZ >= 2 * C.L2) TZ -= 2 * C.L2;
     np = pack_dbl(TX, TY, TZ);
     int g = 0;
-    if (C.gbp > 0) {
+    if (__builtin_expect(C.gbp > 0, 0)) {
         const int tt = site_type(TX, TY);
         g = gb_flag(C, t, pick3(t, X >> 1, Y >> 1, Z >> 1)) |
             gb_flag(C, tt, pick3(tt, TX >> 1, TY >> 1, TZ >> 1));
@@ -1720,24 +1720,17 @@ __device__ __forceinline__ void prec_hop(PlainRec& r, int4* disp, int64_t disp_o
 {
     uint64_t mv = __ballot(r.cur == cs);
     uint64_t mi = __ballot(r.cur == ct);
-    if (r.n + (mv == 0) + (mi == 0) > 64) {
+    if (__builtin_expect(r.n + (mv == 0) + (mi == 0) > 64, 0)) {
         prec_flush(r, disp, disp_off, L0, L1, L2);
         mv = 0;
         mi = 0;
     }
-    int lv, li;
-    if (mv) {
-        lv = __ffsll((unsigned long long)mv) - 1;
-    } else {
-        lv = r.n++;
-        if (lane == lv) r.orig = cs;
-    }
-    if (mi) {
-        li = __ffsll((unsigned long long)mi) - 1;
-    } else {
-        li = r.n++;
-        if (lane == li) r.orig = ct;
-    }
+    // a site without a record opens one in the next free lane (selects)
+    const int lv = mv ? __ffsll((unsigned long long)mv) - 1 : r.n;
+    const int n1 = r.n + (mv == 0);
+    const int li = mi ? __ffsll((unsigned long long)mi) - 1 : n1;
+    r.n = n1 + (mi == 0);
+    r.orig = lane == lv && mv == 0 ? cs : (lane == li && mi == 0 ? ct : r.orig);
     const int sv = lane == lv ? 1 : (lane == li ? -1 : 0);
     r.cur = lane == lv ? ct : (lane == li ? cs : r.cur);
     r.ax += sv * hx;
@@ -1866,7 +1859,13 @@ __device__ __forceinline__ void plain_rank_slots(uint32_t* vlist, int nv, int L0
 // inclusive prefix of the block totals over the lanes, so a selection is
 // one ballot over the prefixes (the block), one read of the block's rates
 // into lanes 0 .. 8P-1, their prefix sum and a second ballot (the event).
-template <int P>
+// HZ: the call has a horizon (t_sync > 0), so every step needs its clock.
+// Without one, a step records its total rate in the lane of its draw, and
+// the clock takes the steps' increments -ln(u)/R every 64 steps (and at the
+// end), one division for all of them and the additions in step order: the
+// same operations in the same order, with the divisions off the path from
+// one selection to the next.
+template <int P, bool HZ>
 __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint32_t* vlist, int nv,
                                            double* krate, unsigned char* kspec, const RateCtx& C, int4* disp,
                                            LatState* St, const LatCall* Cl, int lane)
@@ -1918,9 +1917,17 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
     unsigned long long ho = 0, hh = 0;
     int sl = 64;
     double dr_sel = 0.0, dr_ln = 0.0;  // draw sl + (draws at the refill) is in lane sl
+    double r_step = 0.0;               // (no horizon) total rate of the step that used this lane's draw
+    int n_pend = 0;                    // (no horizon) steps whose clock increment is pending
+    auto settle = [&]() {
+        const double dtl = -dr_ln / r_step;
+        for (int l = 0; l < n_pend; l++) t += lane_value(dtl, l);
+        n_pend = 0;
+    };
     while (done < target) {
         if (R == 0.0) break;
         if (sl == 64) {
+            if (!HZ) settle();
             const uint64_t di = draws + (uint64_t)lane;
             uint32_t x0, x1, x2, x3;
             philox10((uint32_t)di, (uint32_t)(di >> 32), 0xFFFFFFFFu, 3u, seed, lid, x0, x1, x2, x3);
@@ -1929,42 +1936,67 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             sl = 0;
         }
         const double u_sel = lane_value(dr_sel, sl);
-        const double dt = -lane_value(dr_ln, sl) / R;
+        if (HZ) {
+            const double tn = t + -lane_value(dr_ln, sl) / R;
+            if (tn > t_end) {
+                t = t_end;
+                draws++;
+                break;
+            }
+            t = tn;
+        } else {
+            r_step = lane == sl ? R : r_step;
+            n_pend++;
+        }
         sl++;
         draws++;
-        const double tn = t + dt;
-        if (horizon > 0.0 && tn > t_end) {
-            t = t_end;
-            break;
-        }
-        t = tn;
         // the event whose inclusive prefix first exceeds y: its block from
         // one ballot, then the event inside the block from a second; when y
         // rounded up to R, the last event with a positive rate
+        // (both ballots of each choice are taken, and the choice is a
+        // select: the step runs without branches)
         const double y = u_sel * R;
         const uint64_t mb = __ballot(bincl > y);
+        const uint64_t nzb = __ballot(bsum > 0.0);
         const bool fb = mb == 0;
-        const int r = fb ? 63 - __clzll((long long)__ballot(bsum > 0.0)) : __ffsll((unsigned long long)mb) - 1;
+        const int r = fb ? 63 - __clzll((long long)nzb) : __ffsll((unsigned long long)mb) - 1;
         const double c0 = lane_value(bincl, r) - lane_value(bsum, r);
+        // lane l < NE: event l of the block (its slot's position, rate and
+        // target species); every lane reads inside the block (lanes past NE
+        // repeat it and are masked by value), and a slot past the last
+        // vacancy, whose events have zero rates, takes position 0
         const int eb = r * NE;
-        const double kv = lane < NE ? krate[eb + lane] : 0.0;
-        const int kspv = lane < NE ? (int)kspec[eb + lane] : 0;
-        const uint32_t pvv = lane < P && r * P + lane < nv ? vlist[r * P + lane] : 0u;
-        const double cs = seg_scan<NE>(kv, lane & (NE - 1)) + c0;
-        const uint64_t me = fb ? 0ull : __ballot(lane < NE && cs > y);
-        const int e = me ? __ffsll((unsigned long long)me) - 1
-                         : 63 - __clzll((long long)__ballot(lane < NE && kv > 0.0));
-        const int j = e >> 3, d = e & 7;
+        const int le = lane & (NE - 1);
+        const bool in_blk = NE == 64 || lane < NE;
+        const double kraw = krate[eb + le];
+        const double kv = in_blk ? kraw : 0.0;
+        const int kspv = (int)kspec[eb + le];
+        const int slot_l = r * P + (le >> 3);
+        const uint32_t pv_l = vlist[slot_l];
+        const uint32_t pos = slot_l < nv ? pv_l : 0u;
+        // every lane works out its event's target while the scan runs: the
+        // selected one is then read from its lane
+        uint32_t np_l;
+        int col_l, hx_l, hy_l, hz_l;
+        const int ct_l = plain_nb(C, pos, le & 7, np_l, col_l, hx_l, hy_l, hz_l);
+        const int cs_l = canon_dbl(L0, L1, pos & 2047, (pos >> 11) & 2047, pos >> 22);
+        const int hv_l = (hx_l + 1) | ((hy_l + 1) << 2) | ((hz_l + 1) << 4);
+        const double cs = seg_scan<NE>(kv, le) + c0;
+        const uint64_t me = __ballot(in_blk && cs > y);
+        const uint64_t nze = __ballot(in_blk && kv > 0.0);
+        const int e = !fb && me ? __ffsll((unsigned long long)me) - 1 : 63 - __clzll((long long)nze);
+        const int j = e >> 3;
         const int slot = r * P + j;
         const int sp = __builtin_amdgcn_readlane(kspv, e);
         // the slot's old total: its 8 events in the block's prefix sum
-        const double tot_old = lane_value(cs, (j << 3) | 7) - (j ? lane_value(cs, (j << 3) - 1) : c0);
-        const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)pvv, j);
-        uint32_t tx;
-        int colx, hx, hy, hz;
-        const int ct_i = plain_nb(C, sx, d, tx, colx, hx, hy, hz);
-        const int SX = sx & 2047, SY = (sx >> 11) & 2047, SZ = sx >> 22;
-        const int cs_i = canon_dbl(L0, L1, SX, SY, SZ);
+        const double cs_hi = lane_value(cs, (j << 3) | 7), cs_lo = lane_value(cs, j ? (j << 3) - 1 : 0);
+        const double tot_old = cs_hi - (j ? cs_lo : c0);
+        const uint32_t sx = (uint32_t)__builtin_amdgcn_readlane((int)pos, e);
+        const uint32_t tx = (uint32_t)__builtin_amdgcn_readlane((int)np_l, e);
+        const int ct_i = __builtin_amdgcn_readlane(ct_l, e);
+        const int cs_i = __builtin_amdgcn_readlane(cs_l, e);
+        const int hv = __builtin_amdgcn_readlane(hv_l, e);
+        const int hx = (hv & 3) - 1, hy = ((hv >> 2) & 3) - 1, hz = ((hv >> 4) & 3) - 1;
         if (lane == 0) {
             pk_set(ps, cs_i, sp);
             pk_set(ps, ct_i, kSpV);
@@ -1984,13 +2016,14 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
         if (lane < 16) {
             int col;
             const int cn = plain_nb(C, lane < 8 ? tx : sx, lane & 7, nb, col);
+            // (the rate table entries in all 16 lanes: read with the
+            // occupancy word, one LDS round trip)
             kn = plain_rate_of(C, ps, cn, col, spn);
-            if (lane < 8) {
-                krate[slot * 8 + lane] = kn;
-                kspec[slot * 8 + lane] = (unsigned char)spn;
-            } else {
-                kn = 0.0;
-            }
+        }
+        kn = lane < 8 ? kn : 0.0;
+        if (lane < 8) {
+            krate[slot * 8 + lane] = kn;
+            kspec[slot * 8 + lane] = (unsigned char)spn;
         }
         {
             const double delta = lane_value(seg_scan<8>(kn, lane & 7), 7) - tot_old;
@@ -2021,6 +2054,7 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
             }
         }
     }
+    if (!HZ) settle();
     prec_flush(pr, disp, disp_off, L0, L1, L2);
     if (lane == 0) {
         St->t = t;
@@ -2028,6 +2062,15 @@ __device__ __forceinline__ void solo_plain(const LatDesc& D, uint32_t* ps, uint3
         St->hops[0] += ho;
         St->hops[1] += hh;
     }
+}
+
+template <int P>
+__device__ __forceinline__ void solo_plain_call(const LatDesc& D, uint32_t* ps, uint32_t* vlist, int nv,
+                                                double* krate, unsigned char* kspec, const RateCtx& C,
+                                                int4* disp, LatState* St, const LatCall* Cl, int lane)
+{
+    if (Cl->t_sync > 0.0) solo_plain<P, true>(D, ps, vlist, nv, krate, kspec, C, disp, St, Cl, lane);
+    else solo_plain<P, false>(D, ps, vlist, nv, krate, kspec, C, disp, St, Cl, lane);
 }
 
 // ----------------------------------------------------------------------------
@@ -2396,13 +2439,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             double* krate = (double*)c2s;
             unsigned char* kspec = (unsigned char*)(krate + 8 * plain_slots);
             if (plain_slots == 64)
-                solo_plain<1>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
+                solo_plain_call<1>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
             else if (plain_slots == 128)
-                solo_plain<2>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
+                solo_plain_call<2>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
             else if (plain_slots == 256)
-                solo_plain<4>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
+                solo_plain_call<4>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
             else
-                solo_plain<8>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
+                solo_plain_call<8>(D, pslab, vlist, nv_list, krate, kspec, C, P.disp, St, Cl, lane);
         }
     } else if (fast) {
         if (wv == 0) {
