@@ -669,7 +669,7 @@ def main():
             m = fr == f
             j = int(np.argmax(np.where(m, busy, -1.0)))
             log("  edge %d: %d lattices, busiest %d at %.1f ms (%.3f us/hop)" % (
-                f, int(m.sum()), j, busy[j], 1e3 * busy[j] / max(int(hops_each[j]), 1)))
+                f, int(m.sum()), j, busy[j], 1e3 * busy[j] * args.steps / max(int(hops_each[j]), 1)))
         for i in np.argsort(-busy)[:8]:
             sp = specs[i]
             log("  lattice %d: busy %.1f ms, L=%d F=%d n_V=%d n_H=%d T=%.0f cycles=%d resident=%d" % (

@@ -1042,12 +1042,13 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         const double lnu = S == 64 ? lane_value(dr_ln, dl) : lane_pull(dr_ln, sb + (dl & (S - 1)));
         const double dt = -lnu / R;
         const double tn = tau + dt;
-        const bool go = active && R != 0.0 && tn <= X.t_sync;
-        active = go;
-        if (go) tau = tn;
+        // the event is chosen for every tile that can still hop (act), and
+        // taken only by those whose next event lands inside the window
+        // (go): the choice does not wait for the clock's division
+        const bool act = active && R != 0.0;
         const double y = u_sel * R;
-        const uint64_t mk_all = __ballot(go && incl > y);
-        const uint64_t nz_all = __ballot(go && lsv > 0.0);
+        const uint64_t mk_all = __ballot(act && incl > y);
+        const uint64_t nz_all = __ballot(act && lsv > 0.0);
         bool fb;
         int sel;
         if (S < 64) {
@@ -1067,7 +1068,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         }
         // the selected lane of each segment picks the event
         int pick = 0, pslot = 0;
-        if (go && lane == sel) {
+        if (act && lane == sel) {
             double Cc = incl - lsv;
             int found = -1, last = -1;
             if (cached) {
@@ -1104,6 +1105,10 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             pick = lane_pull(pick, sel);
             pslot = lane_pull(pslot, sel);
         }
+        const bool go = act && tn <= X.t_sync;
+        active = go;
+        if (go) tau = tn;
+        pick = go ? pick : 0;
         const uint32_t sx = (uint32_t)pick & 0x1FFFFFFFu;
         const int d = (int)((uint32_t)pick >> 29);
         int hx, hy, hz;
