@@ -234,7 +234,8 @@ def cpu_baseline(specs, budget_s: float, hop_target: int, workers: int):
     wall = time.perf_counter() - t0
     allc = {"value": float(sum(h / t for h, t, _ in res)), "processes": len(jobs),
             "hops": int(sum(h for h, _, _ in res)), "wall_s": wall,
-            "finished": int(sum(1 for _, _, f in res if f))}
+            "finished": int(sum(1 for _, _, f in res if f)),
+            "per_process": [float(h / t) if t > 0 else 0.0 for h, t, _ in res]}
     return one, allc
 
 
@@ -269,8 +270,11 @@ def cpu_leg(args):
                       % (one["lattices"], one["hops"], one["seconds"],
                          " (last one partial)" if one["partial"] else ""),
             "all_cores": {"value": allc["value"], "unit": "hops/s", "cores": allc["processes"],
+                          "per_lattice": allc["per_process"],
                           "sample": "first %d lattices, one process each, up to %.0f s each (%d "
-                                    "reached the hop target); rate = sum of per-process rates"
+                                    "reached the hop target); rate = sum of per-process rates; "
+                                    "per_lattice: each process's rate in lattice order (cfg2: one "
+                                    "per temperature, 300-800 K)"
                                     % (allc["processes"], args.cpu_budget, allc["finished"])}}
 
 

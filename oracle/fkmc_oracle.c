@@ -471,6 +471,7 @@ static int in_footprint(const or_geom* g, const int c[3], int t, const int lo[3]
  * owner cell lies in box [lo,hi), or always when box == NULL) and the target
  * holds an ion (O or H). */
 typedef struct site_ctx site_ctx;
+static int site_failed(const site_ctx* X);
 
 typedef struct {
     const or_geom* g;
@@ -578,8 +579,20 @@ static int cmp_i64(const void* a, const void* b)
  * owner cell or in its +1 neighbour along one axis, so the footprint is
  * contained in the box [lo, hi] (one extra cell layer, periodic); the
  * candidates are taken from that box and filtered by in_footprint(). */
+static int phase_run(const or_geom* g, const double k12[12], site_ctx* X, int8_t* occ, int32_t* disp,
+                     double t_sync, uint64_t n, int c, int f, uint64_t hops[2], uint64_t* steps_out);
+
 int or_phase(const or_geom* g, const double k12[12], int8_t* occ, int32_t* disp, double t_sync,
              uint64_t n, int c, int f, uint64_t hops[2], uint64_t* steps_out)
+{
+    return phase_run(g, k12, NULL, occ, disp, t_sync, n, c, f, hops, steps_out);
+}
+
+/* The phase itself; with a site-energy context X the rates are those of the
+ * site model (k12 unused), and the phase ends early when an event's |dE|
+ * exceeded the window (X->err). */
+static int phase_run(const or_geom* g, const double k12[12], site_ctx* X, int8_t* occ, int32_t* disp,
+                     double t_sync, uint64_t n, int c, int f, uint64_t hops[2], uint64_t* steps_out)
 {
     int lo[3], hi[3], a, cc[3], t, ext[3], i, j, k, w;
     int n_slots = 0, cap = 64, m;
@@ -617,7 +630,7 @@ int or_phase(const or_geom* g, const double k12[12], int8_t* occ, int32_t* disp,
         if (w == 0 || slots[w - 1] != slots[m]) slots[w++] = slots[m];
     n_slots = w;
     S.g = g; S.k12 = k12; S.occ = occ; S.disp = disp;
-    S.slot_site = slots; S.n_slots = n_slots; S.lo = lo; S.hi = hi; S.site = NULL;
+    S.slot_site = slots; S.n_slots = n_slots; S.lo = lo; S.hi = hi; S.site = X;
     key[0] = g->seed; key[1] = g->lattice_id;
     for (;;) {
         int r;
@@ -625,6 +638,7 @@ int or_phase(const or_geom* g, const double k12[12], int8_t* occ, int32_t* disp,
         r = bkl_step(&S, ctr, key, &tau, t_sync, hops);
         if (r != 0) break;
         step++;
+        if (X && site_failed(X)) break;
     }
     if (steps_out) *steps_out = step;
     free(slots);
@@ -1038,6 +1052,85 @@ int or_advance_plain_site(const or_geom* g, const double raw12[12], const double
     }
     free(slots);
     return rc;
+}
+
+static int site_failed(const site_ctx* X)
+{
+    return X->err;
+}
+
+/* Squared doubled distance of the farthest vacancy-vacancy shell with a
+ * nonzero energy (0 when there is none). */
+int or_site_vv_reach(const or_site_params* sp)
+{
+    static const int N[6] = {2, 4, 6, 8, 10, 16};
+    int k, r = 0;
+    for (k = 0; k < 6; k++)
+        if (sp->e_vv[k] != 0) r = N[k];
+    return r;
+}
+
+/* Fragment kMC (or_advance_frag: the same cycles, phases, draws and clock)
+ * with the site-energy interactions of or_advance_plain_site.  The rates of
+ * a sub-block's edges read site energies at its footprint's sites, which
+ * sum over vacancies within the vacancy-vacancy reach (the Fe dopants do
+ * not move).  Along an axis, a footprint spans doubled coordinates
+ * [2o, 2o + 2w] and the nearest footprint of the same colour begins 2w'
+ * further on, w' the width of the sub-block between them; when 4 w'^2
+ * exceeds the reach for every sub-block, no sub-block's rates read a site
+ * that another sub-block of the same colour changes, and the sub-blocks of
+ * a phase are independent (any order of them gives the same result)
+ * without a frozen halo.  Returns 0; -1 when a sub-block is too narrow for
+ * the reach; -4 when an event's |dE| exceeded the window (its rate was
+ * taken as 0; the call stops after that phase, and the trajectory no
+ * longer follows the method). */
+int or_advance_frag_site(const or_geom* g, const double raw12[12], const double* f, double q,
+                         const uint8_t* fe, const or_site_params* sp, int8_t* occ, int32_t* disp,
+                         double t_sync, uint64_t cycle0, uint64_t max_cycles, uint64_t min_hops,
+                         uint64_t hops[2], uint64_t* cycles_done)
+{
+    int nf = or_num_fragments(g), c, fi, a, k, reach = or_site_vv_reach(sp);
+    uint64_t n = 0;
+    site_ctx X;
+    *cycles_done = 0;
+    hops[0] = hops[1] = 0;
+    for (a = 0; a < 3; a++) {
+        int nfa = frag_count(g->L[a], g->frag[a]);
+        for (k = 0; k < nfa; k++) {
+            int flo, fhi, w;
+            frag_range(g->L[a], g->frag[a], k, &flo, &fhi);
+            w = (fhi - flo) / 2;  /* the narrower sub-block of the fragment */
+            if (4 * w * w <= reach) return -1;
+        }
+    }
+    X.fe = fe; X.sp = sp; X.raw12 = raw12; X.f = f; X.q = q; X.err = 0;
+    while (n < max_cycles) {
+        for (c = 0; c < 8; c++) {
+            for (fi = 0; fi < nf; fi++) phase_run(g, NULL, &X, occ, disp, t_sync, cycle0 + n, c, fi, hops, NULL);
+            if (X.err) {
+                *cycles_done = n;
+                return -4;
+            }
+        }
+        n++;
+        if (min_hops > 0 && hops[0] + hops[1] >= min_hops) break;
+    }
+    *cycles_done = n;
+    return 0;
+}
+
+/* One phase of or_advance_frag_site (sub-block of fragment f, colour c,
+ * cycle n), for tests of the order of a phase's sub-blocks; no width check.
+ * Returns 0, or -4 when an event's |dE| exceeded the window. */
+int or_phase_site(const or_geom* g, const double raw12[12], const double* f, double q, const uint8_t* fe,
+                  const or_site_params* sp, int8_t* occ, int32_t* disp, double t_sync, uint64_t n, int c,
+                  int fi, uint64_t hops[2])
+{
+    site_ctx X;
+    X.fe = fe; X.sp = sp; X.raw12 = raw12; X.f = f; X.q = q; X.err = 0;
+    hops[0] = hops[1] = 0;
+    phase_run(g, NULL, &X, occ, disp, t_sync, n, c, fi, hops, NULL);
+    return X.err ? -4 : 0;
 }
 
 /* Rate of event d of the vacancy on site s under the site-energy model

@@ -98,6 +98,13 @@ def lib():
                                                C.c_void_p, P(_SiteParams), C.c_void_p, C.c_void_p,
                                                P(C.c_uint64), P(C.c_double), C.c_double, C.c_uint64,
                                                P(C.c_uint64)]
+        _lib.or_advance_frag_site.argtypes = [P(_Geom), P(C.c_double), P(C.c_double), C.c_double,
+                                              C.c_void_p, P(_SiteParams), C.c_void_p, C.c_void_p,
+                                              C.c_double, C.c_uint64, C.c_uint64, C.c_uint64,
+                                              P(C.c_uint64), P(C.c_uint64)]
+        _lib.or_phase_site.argtypes = [P(_Geom), P(C.c_double), P(C.c_double), C.c_double, C.c_void_p,
+                                       P(_SiteParams), C.c_void_p, C.c_void_p, C.c_double, C.c_uint64,
+                                       C.c_int, C.c_int, P(C.c_uint64)]
         _lib.or_site_rate.argtypes = [P(_Geom), P(C.c_double), P(C.c_double), C.c_double, C.c_void_p,
                                       P(_SiteParams), C.c_void_p, C.c_int64, C.c_int]
         _lib.or_site_rate.restype = C.c_double
@@ -400,6 +407,37 @@ class Lattice:
         self.draws = d.value
         self.t = t.value
         self.hops += np.array([h[0], h[1]], dtype=np.uint64)
+        if rc != 0:
+            raise ValueError("site-energy difference outside the window (%d)" % rc)
+        return (h[0], h[1])
+
+    def advance_site(self, t_sync: float, max_cycles: int = 1, min_hops: int = 0):
+        """Fragment kMC with site energies: the cycles, phases, draws and
+        clock of advance, the rates of advance_plain_site.  Every sub-block
+        width w must satisfy 4 w^2 > the vacancy-vacancy reach (squared
+        doubled distance of the farthest nonzero shell)."""
+        h = (C.c_uint64 * 2)()
+        n = C.c_uint64()
+        rc = lib().or_advance_frag_site(C.byref(self._gc), _dp(self.site_raw), _dp(self.site_f), self.site_q,
+                                        self.fe.ctypes.data, C.byref(self._spc), self.occ.ctypes.data,
+                                        self.disp.ctypes.data, float(t_sync), self.cycles, int(max_cycles),
+                                        int(min_hops), h, C.byref(n))
+        if rc == -1:
+            raise ValueError("a sub-block is too narrow for the vacancy-vacancy reach")
+        self.cycles += n.value
+        self.t = self.t + float(n.value) * float(t_sync)
+        self.hops += np.array([h[0], h[1]], dtype=np.uint64)
+        if rc != 0:
+            raise ValueError("site-energy difference outside the window (%d)" % rc)
+        return n.value, (h[0], h[1])
+
+    def phase_site(self, t_sync: float, cycle: int, colour: int, frag_index: int):
+        """One phase of advance_site (no sub-block width check)."""
+        h = (C.c_uint64 * 2)()
+        rc = lib().or_phase_site(C.byref(self._gc), _dp(self.site_raw), _dp(self.site_f), self.site_q,
+                                 self.fe.ctypes.data, C.byref(self._spc), self.occ.ctypes.data,
+                                 self.disp.ctypes.data, float(t_sync), int(cycle), int(colour),
+                                 int(frag_index), h)
         if rc != 0:
             raise ValueError("site-energy difference outside the window (%d)" % rc)
         return (h[0], h[1])

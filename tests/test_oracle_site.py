@@ -221,3 +221,117 @@ def test_two_vacancies_visit_pair_shells_with_boltzmann_weights():
     for e, x in w.items():
         m, se = res.get(e, (0.0, 0.0))
         assert abs(m - x / Z) < 4.5 * se + 2e-3, (e, m, x / Z, se)
+
+
+# --------------------------------------------------------------------------- fragment kMC
+def _frag_pair(L, frag, nv, nh, rp, window, fe_frac=0.1, seed=9, **g):
+    mk = lambda: O.Lattice(O.Geometry(L=L, frag=frag, seed=seed, lattice_id=3, **g))
+    a, b = mk(), mk()
+    a.init_random(nv, nh)
+    b.init_random(nv, nh)
+    return a, b
+
+
+def test_zero_pair_energies_give_fragment_kmc_bit_for_bit():
+    """Fragment kMC with site energies and every pair energy zero follows
+    fragment kMC without them bit for bit (6- and 7-cell fragments: sub-blocks
+    of 3 and 4 cells; field, boundary planes, H).  With nv below the smallest
+    footprint's site count, both quanta come from n_ev = 8 nv."""
+    L, frag = (12, 12, 13), (6, 6, 6)
+    rp = dict(T=650.0, Ea_O=0.6, Ea_H=0.45, E_z=1e8, gb_period_cells=4, gb_axes_mask=6, gb_dE=0.05)
+    a, b = _frag_pair(L, frag, 20, 60, rp, 0, gb_period_cells=4, gb_axes_mask=6)
+    a.set_rates(O.RateParams(**rp))
+    b.set_site_model(W.fe_map(L, 0.1, 4), O.SiteParams(window=0), O.RateParams(**rp))
+    assert a.q == b.site_q and np.array_equal(a.k12, np.rint(b.site_raw / b.site_q) * b.site_q)
+    t_sync = 2.0 / (8 * a.k12[0])
+    for cyc in (3, 5):
+        a.advance(t_sync, cyc)
+        b.advance_site(t_sync, cyc)
+        assert a.cycles == b.cycles and a.t == b.t
+        assert np.array_equal(a.hops, b.hops) and int(a.hops.sum()) > 20
+        assert np.array_equal(a.occ, b.occ) and np.array_equal(a.disp, b.disp)
+
+
+def test_fragment_site_refuses_sub_blocks_within_the_vacancy_reach():
+    """The paper's table reaches squared doubled distance 10 (the 6th
+    vacancy-vacancy shell is 0): 1-cell sub-blocks are refused, 2-cell ones
+    run; with a nonzero 6th shell (16) 2-cell sub-blocks are refused too."""
+    L = (8, 8, 8)
+    far = O.SiteParams(e_fe=W.SITE_E_FE_MEV, e_vv=W.SITE_E_VV_MEV[:5] + (60,), window=1500)
+    for frag, sp, ok in (((2, 4, 4), TABLE, False), ((4, 4, 4), TABLE, True), ((4, 4, 4), far, False),
+                         ((8, 8, 8), far, True)):
+        lat = O.Lattice(O.Geometry(L=L, frag=frag, seed=2))
+        lat.init_random(6, 0)
+        lat.set_site_model(W.fe_map(L, 0.05, 2), sp, O.RateParams(T=900.0, Ea_O=0.6))
+        if ok:
+            lat.advance_site(1e-9, 1)
+        else:
+            with pytest.raises(ValueError, match="too narrow"):
+                lat.advance_site(1e-9, 1)
+
+
+def _phase_orders(L, frag, nv, seed, sp=TABLE, T=1100.0):
+    """One cycle of site-model phases with each colour's sub-blocks taken in
+    ascending and in descending fragment order; returns both final states."""
+    out = []
+    for order in (1, -1):
+        lat = O.Lattice(O.Geometry(L=L, frag=frag, seed=seed))
+        lat.init_random(nv, 0)
+        lat.set_site_model(W.fe_map(L, 0.08, seed), sp, O.RateParams(T=T, Ea_O=0.6))
+        t_sync = 40.0 / (8 * 1e13 * math.exp(-0.6 / (KB * T)))
+        nf = lat.n_fragments
+        for c in range(8):
+            for f in range(nf)[::order]:
+                lat.phase_site(t_sync, 0, c, f)
+        out.append((lat.occ.copy(), lat.disp.copy()))
+    return out
+
+
+def test_sub_blocks_of_a_phase_are_independent_beyond_the_reach():
+    """When every sub-block is wide enough for the vacancy-vacancy reach, no
+    rate of a sub-block reads a site that another sub-block of the same
+    colour changes, so the order in which a phase takes its sub-blocks does
+    not matter: a cycle in ascending and in descending order ends in the
+    same state (3- and 2-cell sub-blocks with the paper's table).  Within the
+    reach (1-cell sub-blocks, or 2-cell ones with a nonzero 6th shell) the
+    two orders differ."""
+    far = O.SiteParams(e_fe=W.SITE_E_FE_MEV, e_vv=W.SITE_E_VV_MEV[:5] + (60,), window=1500)
+    for L, frag, sp, same in (((12, 12, 12), (6, 6, 6), TABLE, True), ((8, 8, 8), (4, 4, 4), TABLE, True),
+                              ((8, 8, 8), (4, 4, 4), far, False), ((8, 8, 8), (2, 2, 2), TABLE, False)):
+        (o1, d1), (o2, d2) = _phase_orders(L, frag, 120, 5, sp)
+        assert (np.array_equal(o1, o2) and np.array_equal(d1, d2)) == same, (L, frag, sp.e_vv)
+
+
+def test_fragment_site_cycle_ends_sample_the_boltzmann_law():
+    """Each phase is an exact BKL process on its edges whose rates obey
+    detailed balance with respect to exp(-U/k_B T), so every phase, and the
+    cycle, keeps that law: one vacancy among two Fe dopants on a 6^3 lattice
+    (3-cell sub-blocks) at 1500 K, sampled at cycle ends, sits at each site
+    energy with the Boltzmann weights."""
+    L, T = (6, 6, 6), 1500.0
+    lat = O.Lattice(O.Geometry(L=L, frag=(6, 6, 6), seed=13))
+    lat.init_random(1, 0)
+    fe = np.zeros(216, np.uint8)
+    fe[[0, 129]] = 1
+    lat.set_site_model(fe, TABLE, O.RateParams(T=T, Ea_O=0.6))
+    n_sites = 3 * 216
+    E = np.array([brute_energy(L, np.zeros(n_sites, np.int8), fe, TABLE, s) for s in range(n_sites)])
+    w = {}
+    for e in E:
+        w[int(e)] = w.get(int(e), 0.0) + math.exp(-e * 1e-3 / (KB * T))
+    Z = sum(w.values())
+    t_sync = 3.0 / (8 * 1e13 * math.exp(-0.6 / (KB * T)))
+    batches, per = 20, 1500
+    frac = []
+    for _ in range(batches):
+        acc = {}
+        for _ in range(per):
+            lat.advance_site(t_sync, 1)
+            e = int(E[int(np.nonzero(lat.occ == 2)[0][0])])
+            acc[e] = acc.get(e, 0) + 1
+        frac.append({k: v / per for k, v in acc.items()})
+    assert len(w) >= 4
+    for e, x in w.items():
+        v = np.array([f.get(e, 0.0) for f in frac])
+        m, se = v.mean(), v.std(ddof=1) / math.sqrt(batches)
+        assert abs(m - x / Z) < 4.5 * se + 3e-3, (e, m, x / Z, se)
