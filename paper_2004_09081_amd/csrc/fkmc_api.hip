@@ -808,12 +808,32 @@ fkmc_status fkmc_set_site_model(fkmc_lattice* L, uint32_t i, const uint8_t* fe, 
     fkmc_status st = fkmc_site_model_bytes(L, i, window_meV, &need);
     if (st) return st;
     const fkmc_geometry& g = L->geo[i];
-    if (!L->desc[i].plain) return fail(FKMC_E_UNSUPPORTED, "lattice %u: site energies need a plain lattice", i);
     for (int a = 0; a < 3; a++)
         if (g.L[a] < 5) return fail(FKMC_E_UNSUPPORTED, "lattice %u: site energies need L >= 5 cells", i);
-    if (L->n_vac[i] > (uint64_t)kMaxSiteSlots)
-        return fail(FKMC_E_UNSUPPORTED, "lattice %u: %llu vacancies, site energies hold %d", i,
-                    (unsigned long long)L->n_vac[i], kMaxSiteSlots);
+    if (L->desc[i].plain) {
+        if (L->n_vac[i] > (uint64_t)kMaxSiteSlots)
+            return fail(FKMC_E_UNSUPPORTED, "lattice %u: %llu vacancies, site energies hold %d", i,
+                        (unsigned long long)L->n_vac[i], kMaxSiteSlots);
+    } else {
+        // every sub-block wider than the vacancy-vacancy reach (the squared
+        // doubled distance of the farthest shell with a nonzero energy), so
+        // that the sub-blocks of a phase never read each other's sites
+        static const int kShellN2[6] = {2, 4, 6, 8, 10, 16};
+        int reach = 0;
+        for (int k = 0; k < 6; k++)
+            if (e_vv[k] != 0) reach = kShellN2[k];
+        for (int a = 0; a < 3; a++) {
+            const std::vector<int32_t>& b = L->Y.bounds[a][i];
+            for (size_t k = 0; k + 1 < b.size(); k++) {
+                const int w = b[k + 1] - b[k];
+                if (4 * w * w <= reach)
+                    return fail(FKMC_E_UNSUPPORTED,
+                                "lattice %u: a %d-cell sub-block lies within the vacancy-vacancy reach "
+                                "(squared doubled distance %d): site energies on fragments need 4 w^2 > reach",
+                                i, w, reach);
+            }
+        }
+    }
     if (!L->rates_ok[i] || !L->have_params[i])
         return fail(FKMC_E_STATE, "lattice %u: set the rates with fkmc_set_rates first", i);
     if (bytes < need || ((uintptr_t)dev & 255)) return fail(FKMC_E_NOMEM, "site buffer: need %zu bytes, 256-aligned", need);
@@ -873,6 +893,12 @@ fkmc_status fkmc_set_site_model(fkmc_lattice* L, uint32_t i, const uint8_t* fe, 
     if (st) {
         L->desc[i] = backup;
         return st;
+    }
+    // a fragment lattice moves from the tile groups to the site-model list
+    L->phase_group = 0;
+    if (L->graph) {
+        (void)hipGraphExecDestroy(L->graph);
+        L->graph = nullptr;
     }
     return FKMC_OK;
 }
@@ -991,17 +1017,26 @@ static fkmc_status prepare_lockstep(fkmc_lattice* L)
         g = std::min(g, pick_group(mean_footprint_vacancies(L, i), L->fp_stride, 32768 - kWaveScratchStaged, true));
     if (L->group_override) g = L->group_override;
     while (g > 1 && kWaveScratchStaged + g * L->fp_stride > 65536) g /= 2;
-    std::vector<int2> groups;
+    // lattices with a site model: one entry per sub-block, after the groups
+    std::vector<int2> groups, site_groups;
     for (int32_t i : L->batch_ids) {
         const LatDesc& D = L->desc[i];
         const int nt = D.nf[0] * D.nf[1] * D.nf[2];
+        if (D.site_window >= 0) {
+            for (int f = 0; f < nt; f++) site_groups.push_back(make_int2(i, f));
+            continue;
+        }
         for (int f0 = 0; f0 < nt; f0 += g) groups.push_back(make_int2(i, f0));
     }
+    const size_t ng = groups.size();
+    groups.insert(groups.end(), site_groups.begin(), site_groups.end());
     if (!groups.empty())
         HIP_OK(hipMemcpyAsync(L->d_groups, groups.data(), groups.size() * sizeof(int2),
                               hipMemcpyHostToDevice, L->stream));
     HIP_OK(hipStreamSynchronize(L->stream));
-    L->P.n_groups = (int32_t)groups.size();
+    L->P.n_groups = (int32_t)ng;
+    L->P.site_groups = L->d_groups + ng;
+    L->P.n_site_groups = (int32_t)site_groups.size();
     L->P.lds_wave_bytes = kWaveScratchStaged + g * L->fp_stride;
     if (L->graph) {
         (void)hipGraphExecDestroy(L->graph);
@@ -1016,10 +1051,12 @@ static fkmc_status record_phase(fkmc_lattice* L, int colour, size_t& ev_used)
     if (L->timing && ev_used + 2 <= L->ev.size()) {
         HIP_OK(hipEventRecord(L->ev[ev_used], L->stream));
         LAUNCH_OK(launch_phase(L->P, colour, L->phase_group, L->stream));
+        LAUNCH_OK(launch_phase_site(L->P, colour, L->stream));
         HIP_OK(hipEventRecord(L->ev[ev_used + 1], L->stream));
         ev_used += 2;
     } else {
         LAUNCH_OK(launch_phase(L->P, colour, L->phase_group, L->stream));
+        LAUNCH_OK(launch_phase_site(L->P, colour, L->stream));
     }
     return FKMC_OK;
 }
@@ -1137,6 +1174,9 @@ static fkmc_status plan_batch(fkmc_lattice* L, const std::vector<int32_t>& ids)
 static bool use_persistent(const fkmc_lattice* L)
 {
     if (L->batch_ids.empty()) return false;
+    // fragment lattices with a site model run one phase per launch
+    for (int32_t i : L->batch_ids)
+        if (L->desc[i].site_window >= 0) return false;
     if (L->schedule == FKMC_SCHEDULE_LOCKSTEP) return false;
     if (L->schedule == FKMC_SCHEDULE_PERSISTENT) return true;
     if (L->batch_ids.size() < 2) return false;
@@ -1229,7 +1269,7 @@ fkmc_status fkmc_advance(fkmc_lattice* L, const double* t_sync, uint64_t max_cyc
         // it reaches its target, after which its kernels return at once, so
         // cycles enqueued beyond the target change nothing.  Without event
         // timing, whole batches of cycles are replayed from a prebuilt graph.
-        const bool graph = L->use_graph && !L->timing;
+        const bool graph = L->use_graph && !L->timing && L->P.n_site_groups == 0;
         if (graph && !L->graph) {
             LAUNCH_OK(build_cycle_graph(L->P, L->phase_group, kGraphCycles, &L->graph));
         }
@@ -1507,6 +1547,7 @@ fkmc_status fkmc_run_phase(fkmc_lattice* L, const double* t_sync, int32_t colour
     s = prepare_lockstep(L);
     if (s) return s;
     LAUNCH_OK(launch_phase(L->P, colour, L->phase_group, L->stream));
+    LAUNCH_OK(launch_phase_site(L->P, colour, L->stream));
     return read_states(L);
 }
 

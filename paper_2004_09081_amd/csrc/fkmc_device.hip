@@ -2884,6 +2884,34 @@ __device__ __forceinline__ int plain_dist2(const LatDesc& D, uint64_t a, uint64_
     return r;
 }
 
+// The interacting lattice points of each anion type as packed offsets (the
+// order is irrelevant: the energies are integer sums); n_off zeroed and
+// published by the caller's barriers.  Every thread of the workgroup calls it.
+__device__ __forceinline__ void site_offsets(const LatDesc& D, uint16_t* offs, int* n_off, int tid)
+{
+    for (int c = tid; c < 729; c += kPlainThreads) {
+        const int dX = c % 9 - 4, dY = (c / 9) % 9 - 4, dZ = c / 81 - 4;
+        const int n = dX * dX + dY * dY + dZ * dZ;
+        if (n == 0 || n > 16) continue;
+        for (int t = 0; t < 3; t++) {
+            const int odd = ((t != 0) + dX) & 1;
+            const int odd_y = ((t != 1) + dY) & 1;
+            const int odd_z = ((t != 2) + dZ) & 1;
+            const int nodd = odd + odd_y + odd_z;
+            const bool bsite = nodd == 3;
+            if (nodd < 2) continue;
+            const int sh = site_shell(bsite, n);
+            if (sh < 0) continue;
+            const int e = bsite ? D.site_e_fe[sh] : D.site_e_vv[sh];
+            if (e == 0) continue;
+            const int k = atomicAdd(&n_off[t], 1);
+            if (k < kSiteOffsets)
+                offs[t * kSiteOffsets + k] =
+                    (uint16_t)((dX + 4) | ((dY + 4) << 4) | ((dZ + 4) << 8) | ((bsite ? 1 : 0) << 12) | (sh << 13));
+        }
+    }
+}
+
 __global__ __launch_bounds__(kPlainThreads) void k_plain_site(DevPtrs P, const int32_t* ids)
 {
     extern __shared__ __align__(16) unsigned char psm[];
@@ -2909,31 +2937,10 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain_site(DevPtrs P, const i
     const int WW = 2 * W + 1;
     const int8_t* occ = P.occ + D.occ_off;
 
-    // interacting lattice points of each anion type (order is irrelevant: integer sums)
     if (tid < 3) n_off[tid] = 0;
     if (tid == 0) err_sh = 0;
     __syncthreads();
-    for (int c = tid; c < 729; c += kPlainThreads) {
-        const int dX = c % 9 - 4, dY = (c / 9) % 9 - 4, dZ = c / 81 - 4;
-        const int n = dX * dX + dY * dY + dZ * dZ;
-        if (n == 0 || n > 16) continue;
-        for (int t = 0; t < 3; t++) {
-            const int odd = ((t != 0) + dX) & 1;
-            const int odd_y = ((t != 1) + dY) & 1;
-            const int odd_z = ((t != 2) + dZ) & 1;
-            const int nodd = odd + odd_y + odd_z;
-            const bool bsite = nodd == 3;
-            if (nodd < 2) continue;
-            const int sh = site_shell(bsite, n);
-            if (sh < 0) continue;
-            const int e = bsite ? D.site_e_fe[sh] : D.site_e_vv[sh];
-            if (e == 0) continue;
-            const int k = atomicAdd(&n_off[t], 1);
-            if (k < kSiteOffsets)
-                offs[t * kSiteOffsets + k] =
-                    (uint16_t)((dX + 4) | ((dY + 4) << 4) | ((dZ + 4) << 8) | ((bsite ? 1 : 0) << 12) | (sh << 13));
-        }
-    }
+    site_offsets(D, offs, n_off, tid);
     const int n = plain_collect_slots(D, P, slots, wcount, &n_sh, tid, kMaxSiteSlots);
     if (n > kMaxSiteSlots) {
         if (tid == 0) atomicOr(&S->err, 1u);
@@ -3147,6 +3154,298 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain_site(DevPtrs P, const i
         S->hops[0] += ho;
         S->hops[1] += hh;
         S->busy_ticks = __builtin_amdgcn_s_memrealtime() - t_begin;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Fragment kMC with site energies, one phase per launch: one 256-thread
+// workgroup per sub-block of colour `colour` of a lattice with a site model
+// (P.site_groups: lattice, fragment).  Its BKL domain is the sub-block's
+// edges (an edge belongs to the sub-block that holds its midpoint cell),
+// its slots the footprint's vacancies in canonical order, its draws the
+// fragment's Philox stream (step, f, cycle, colour * 256 + 2) and its clock
+// the phase's own, ending at t_sync (Eqs. TransitionProb, eventSelection,
+// TimeStep); every rate is the site-model table entry of k_plain_site,
+// evaluated from the occupancy in HBM.  The host admits a site model on a
+// fragment lattice only when every sub-block is wider than the
+// vacancy-vacancy reach (4 w^2 above the squared doubled distance of the
+// farthest nonzero shell): no rate of a sub-block then reads a site that
+// another sub-block of the phase changes, so the workgroups need no frozen
+// halo and no order.
+constexpr int kSiteTileSlots = 256;  // vacancies per footprint
+
+__global__ __launch_bounds__(kPlainThreads) void k_phase_site(DevPtrs P, int colour)
+{
+    __shared__ uint64_t slots[kSiteTileSlots];  // packed positions, canonical order
+    __shared__ uint64_t ukey[kSiteTileSlots];   // canonical index, collection order
+    __shared__ uint64_t upos[kSiteTileSlots];
+    __shared__ double stot[kSiteTileSlots];
+    __shared__ uint16_t eidx[kSiteTileSlots * 8];
+    __shared__ uint16_t offs[3 * kSiteOffsets];
+    __shared__ double wsum[kPlainThreads / 64];
+    __shared__ uint64_t wmask[kPlainThreads / 64];
+    __shared__ uint64_t wnz[kPlainThreads / 64];
+    __shared__ int n_sh, ev_sh, hop_slot, n_off[3], Eacc[9], tsp[8], tcol[8], n_aff, err_sh;
+    __shared__ uint64_t hop_s, hop_t, tpk[8];
+    __shared__ int16_t aff[kPlainThreads];
+    const int2 gr = P.site_groups[blockIdx.x];
+    const int lat = gr.x, f = gr.y;
+    const LatDesc& D = P.desc[lat];
+    LatState* S = P.state + lat;
+    if (S->done) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int NW = kPlainThreads / 64;
+    const int W = D.site_window;
+    const int WW = 2 * W + 1;
+    const int L0 = D.L[0], L1 = D.L[1], L2 = D.L[2];
+    const TileRec& T = P.tiles[(size_t)colour * P.n_tiles + D.tile0 + f];
+    const int o0 = T.ox, o1 = T.oy, o2 = T.oz, w0 = T.wx, w1 = T.wy, w2 = T.wz;
+    int8_t* occ = P.occ + D.occ_off;
+    auto store = [&](int i, int j, int k, int t) { return store_index(D, P.bounds, P.c2s, i, j, k, t); };
+
+    if (tid < 3) n_off[tid] = 0;
+    if (tid == 0) {
+        err_sh = 0;
+        n_sh = 0;
+    }
+    __syncthreads();
+    site_offsets(D, offs, n_off, tid);
+    // the footprint's vacancies: the sub-block's sites and the +face of each
+    // axis (type a at cell o_a + w_a), from the box of (w+1)^3 cells
+    const int e0 = w0 + 1, e1 = w1 + 1, e2 = w2 + 1;
+    const int nbox = 3 * e0 * e1 * e2;
+    for (int m = tid; m < nbox; m += kPlainThreads) {
+        const int t = m % 3, c = m / 3;
+        const int di = c % e0, dj = (c / e0) % e1, dk = c / (e0 * e1);
+        const int fx = di == w0, fy = dj == w1, fz = dk == w2;
+        const bool in = fx + fy + fz == 0 || (fx + fy + fz == 1 && (t == 0 ? fx : (t == 1 ? fy : fz)));
+        if (!in) continue;
+        int i = o0 + di, j = o1 + dj, k = o2 + dk;
+        i -= i >= L0 ? L0 : 0;
+        j -= j >= L1 ? L1 : 0;
+        k -= k >= L2 ? L2 : 0;
+        if (occ[store(i, j, k, t)] != kSpV) continue;
+        const int a = atomicAdd(&n_sh, 1);
+        if (a < kSiteTileSlots) {
+            ukey[a] = (uint64_t)canon_site(L0, L1, i, j, k, t);
+            upos[a] = (uint64_t)i | ((uint64_t)j << 16) | ((uint64_t)k << 32) | ((uint64_t)t << 48);
+        }
+    }
+    __syncthreads();
+    const int n = n_sh;
+    if (n > kSiteTileSlots) {
+        if (tid == 0) atomicOr(&S->err, 1u);
+        return;
+    }
+    // canonical order: each slot's rank among the distinct keys
+    for (int a = tid; a < n; a += kPlainThreads) {
+        int r = 0;
+        for (int b = 0; b < n; b++) r += ukey[b] < ukey[a] ? 1 : 0;
+        slots[r] = upos[a];
+    }
+    __syncthreads();
+    const int noff_max = max(n_off[0], max(n_off[1], n_off[2]));
+
+    // events of slot sidx (as k_plain_site): an event whose edge the
+    // sub-block does not own, or whose target holds a vacancy, has no rate
+    auto eval_slot = [&](int sidx) {
+        const uint64_t pk = slots[sidx];
+        if (tid < 9) Eacc[tid] = 0;
+        if (tid < 8) {
+            const int i = (int)(pk & 0xffff), j = (int)((pk >> 16) & 0xffff), k = (int)((pk >> 32) & 0xffff);
+            const int t = (int)(pk >> 48);
+            int hx, hy, hz;
+            hop_vec(t, tid, hx, hy, hz);
+            const int X0 = 2 * i + (t != 0), Y0 = 2 * j + (t != 1), Z0 = 2 * k + (t != 2);
+            // the edge's midpoint cell, relative to the sub-block's origin
+            int ox = ((2 * X0 + hx) >> 2) - o0, oy = ((2 * Y0 + hy) >> 2) - o1, oz = ((2 * Z0 + hz) >> 2) - o2;
+            ox += ox < 0 ? L0 : 0;
+            oy += oy < 0 ? L1 : 0;
+            oz += oz < 0 ? L2 : 0;
+            ox -= ox >= L0 ? L0 : 0;
+            oy -= oy >= L1 ? L1 : 0;
+            oz -= oz >= L2 ? L2 : 0;
+            const bool own = ox < w0 && oy < w1 && oz < w2;
+            const int X = wrap2(X0 + hx, 2 * L0), Y = wrap2(Y0 + hy, 2 * L1), Z = wrap2(Z0 + hz, 2 * L2);
+            const int tt = site_type(X, Y);
+            const int sp = own ? (int)occ[store(X >> 1, Y >> 1, Z >> 1, tt)] : kSpV;
+            const int cs = t == 0 ? i : (t == 1 ? j : k);
+            const int ct = tt == 0 ? (X >> 1) : (tt == 1 ? (Y >> 1) : (Z >> 1));
+            const int g = edge_gb(D, i, j, k, t, X >> 1, Y >> 1, Z >> 1, tt, cs, ct);
+            tpk[tid] = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) | ((uint64_t)(Z >> 1) << 32) |
+                       ((uint64_t)tt << 48);
+            tsp[tid] = sp;
+            tcol[tid] = (sp * 3 + hz + 1) * 2 + g;
+        }
+        __syncthreads();
+        for (int w = tid; w < 9 * noff_max; w += kPlainThreads) {
+            const int c = w / noff_max, kk = w - c * noff_max;
+            if (c > 0 && tsp[c - 1] == kSpV) continue;
+            const uint64_t ck = c == 0 ? pk : tpk[c - 1];
+            const int t = (int)(ck >> 48);
+            if (kk >= n_off[t]) continue;
+            const int o = offs[t * kSiteOffsets + kk];
+            const int X = wrap2(2 * (int)(ck & 0xffff) + (t != 0) + (o & 15) - 4, 2 * L0);
+            const int Y = wrap2(2 * (int)((ck >> 16) & 0xffff) + (t != 1) + ((o >> 4) & 15) - 4, 2 * L1);
+            const int Z = wrap2(2 * (int)((ck >> 32) & 0xffff) + (t != 2) + ((o >> 8) & 15) - 4, 2 * L2);
+            const int sh = o >> 13;
+            int e = 0;
+            if ((o >> 12) & 1) {
+                const int64_t cell = ((int64_t)(Z >> 1) * L1 + (Y >> 1)) * L0 + (X >> 1);
+                if ((D.site_fe[cell >> 5] >> (cell & 31)) & 1u) e = D.site_e_fe[sh];
+            } else {
+                const int tt = site_type(X, Y);
+                // the origin's own vacancy is never a partner (it is the one hopping)
+                const uint64_t upk = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) |
+                                     ((uint64_t)(Z >> 1) << 32) | ((uint64_t)tt << 48);
+                if (upk != pk && occ[store(X >> 1, Y >> 1, Z >> 1, tt)] == kSpV) e = D.site_e_vv[sh];
+            }
+            if (e) atomicAdd(&Eacc[c], e);
+        }
+        __syncthreads();
+        if (tid < 8) {
+            int ix = 0xFFFF;
+            if (tsp[tid] != kSpV) {
+                const int dE = Eacc[1 + tid] - Eacc[0];
+                if (dE < -W || dE > W) err_sh = 1;
+                else ix = tcol[tid] * WW + dE + W;
+            }
+            eidx[sidx * 8 + tid] = (uint16_t)ix;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double r = 0.0;
+            for (int d = 0; d < 8; d++) {
+                const int ix = eidx[sidx * 8 + d];
+                r += ix == 0xFFFF ? 0.0 : D.site_table[ix];
+            }
+            stot[sidx] = r;
+        }
+        __syncthreads();
+    };
+    for (int sidx = 0; sidx < n; sidx++) eval_slot(sidx);
+
+    const int m = (n + kPlainThreads - 1) / kPlainThreads;
+    const int s0 = tid * m < n ? tid * m : n;
+    const int s1 = s0 + m < n ? s0 + m : n;
+    const double t_sync = P.call[lat].t_sync;
+    const uint32_t cyc = (uint32_t)S->cycles;
+    const uint32_t ctag = ((uint32_t)colour << 8) | 2u;
+    double tau = 0.0;
+    uint32_t step = 0;
+    unsigned long long ho = 0, hh = 0;
+    while (!err_sh) {
+        double ls = 0.0;
+        for (int sidx = s0; sidx < s1; sidx++) ls += stot[sidx];
+        double incl = wave_incl_scan(ls, lane);
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        double before = 0.0, R = 0.0;
+        for (int w = 0; w < NW; w++) {
+            if (w < wv) before += wsum[w];
+            R += wsum[w];
+        }
+        incl += before;
+        if (R == 0.0) break;
+        uint32_t x0, x1, x2, x3;
+        philox10(step, (uint32_t)f, cyc, ctag, D.seed, D.lattice_id, x0, x1, x2, x3);
+        const double u_sel = u53_lo(x0, x1);
+        const double tn = tau + -clock_ln(u53_hi(x2, x3)) / R;
+        if (tn > t_sync) break;
+        tau = tn;
+        const double y = u_sel * R;
+        const uint64_t mk = __ballot(incl > y);
+        const uint64_t nz = __ballot(ls > 0.0);
+        if (lane == 0) {
+            wmask[wv] = mk;
+            wnz[wv] = nz;
+        }
+        __syncthreads();
+        int sel = -1;
+        bool fallback = false;
+        for (int w = 0; w < NW && sel < 0; w++)
+            if (wmask[w]) sel = w * 64 + __ffsll((unsigned long long)wmask[w]) - 1;
+        if (sel < 0) {
+            fallback = true;
+            for (int w = NW - 1; w >= 0 && sel < 0; w--)
+                if (wnz[w]) sel = w * 64 + 63 - __clzll((long long)wnz[w]);
+        }
+        if (tid == sel) {
+            double Cc = incl - ls;
+            int sp_slot = -1, last = -1;
+            for (int sidx = s0; sidx < s1; sidx++) {
+                if (stot[sidx] > 0.0) last = sidx;
+                if (!fallback && sp_slot < 0 && Cc + stot[sidx] > y) {
+                    sp_slot = sidx;
+                    break;
+                }
+                Cc += stot[sidx];
+            }
+            if (sp_slot < 0) sp_slot = last;
+            int dsel = -1, dlast = -1;
+            for (int d = 0; d < 8; d++) {
+                const int ix = eidx[sp_slot * 8 + d];
+                const double k = ix == 0xFFFF ? 0.0 : D.site_table[ix];
+                if (k > 0.0) dlast = d;
+                Cc += k;
+                if (!fallback && dsel < 0 && Cc > y) dsel = d;
+            }
+            const int d = dsel >= 0 ? dsel : dlast;
+            const uint64_t pk = slots[sp_slot];
+            const int i = (int)(pk & 0xffff), j = (int)((pk >> 16) & 0xffff), k = (int)((pk >> 32) & 0xffff);
+            const int tp = (int)(pk >> 48);
+            int hx, hy, hz;
+            hop_vec(tp, d, hx, hy, hz);
+            const int X = wrap2(2 * i + (tp != 0) + hx, 2 * L0);
+            const int Y = wrap2(2 * j + (tp != 1) + hy, 2 * L1);
+            const int Z = wrap2(2 * k + (tp != 2) + hz, 2 * L2);
+            const int tt = site_type(X, Y);
+            const int64_t ss = store(i, j, k, tp);
+            const int64_t ts = store(X >> 1, Y >> 1, Z >> 1, tt);
+            const int sp = occ[ts];
+            occ[ss] = (int8_t)sp;
+            occ[ts] = (int8_t)kSpV;
+            int4* dsrc = P.disp + (D.disp_off + ss);
+            int4* dtgt = P.disp + (D.disp_off + ts);
+            const int4 dv = *dsrc;
+            const int4 di = *dtgt;
+            *dtgt = make_int4(dv.x + hx, dv.y + hy, dv.z + hz, 0);
+            *dsrc = make_int4(di.x - hx, di.y - hy, di.z - hz, 0);
+            const uint64_t npk = (uint64_t)(X >> 1) | ((uint64_t)(Y >> 1) << 16) | ((uint64_t)(Z >> 1) << 32) |
+                                 ((uint64_t)tt << 48);
+            slots[sp_slot] = npk;
+            hop_slot = sp_slot;
+            hop_s = pk;
+            hop_t = npk;
+            ev_sh = sp;
+        }
+        if (tid == 0) n_aff = 0;
+        // the barrier's workgroup-scope fence makes the hop's HBM writes
+        // visible to every wave of this workgroup, the only readers
+        __syncthreads();
+        if (ev_sh == kSpO) ho++;
+        else hh++;
+        step++;
+        // slots whose events can have changed: within squared doubled
+        // distance 29 of either site (energies reach 16, a target is 2 away)
+        const uint64_t ps = hop_s, pt = hop_t;
+        for (int sidx = s0; sidx < s1; sidx++)
+            if (sidx == hop_slot || plain_dist2(D, slots[sidx], ps) <= 29 || plain_dist2(D, slots[sidx], pt) <= 29) {
+                const int a = atomicAdd(&n_aff, 1);
+                if (a < kPlainThreads) aff[a] = (int16_t)sidx;
+            }
+        __syncthreads();
+        const int na = n_aff;
+        for (int a = 0; a < na; a++) eval_slot(aff[a]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (err_sh) atomicOr(&S->err, 4u);
+        if (ho | hh) {
+            unsigned long long* b = P.buckets + ((size_t)lat * kHopBuckets + (f & (kHopBuckets - 1))) * 2;
+            if (ho) atomicAdd(b, ho);
+            if (hh) atomicAdd(b + 1, hh);
+        }
     }
 }
 
@@ -3601,6 +3900,14 @@ int launch_plain_site(const DevPtrs& P, const int32_t* d_ids, int n, void* strea
                                        (int)lds);
     if (e != hipSuccess) return (int)e;
     hipLaunchKernelGGL(k_plain_site, dim3(n), dim3(kPlainThreads), lds, (hipStream_t)stream, P, d_ids);
+    return (int)hipGetLastError();
+}
+
+int launch_phase_site(const DevPtrs& P, int colour, void* stream)
+{
+    if (P.n_site_groups == 0) return 0;
+    hipLaunchKernelGGL(k_phase_site, dim3(P.n_site_groups), dim3(kPlainThreads), 0, (hipStream_t)stream, P,
+                       colour);
     return (int)hipGetLastError();
 }
 

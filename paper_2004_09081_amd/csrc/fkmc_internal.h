@@ -119,9 +119,9 @@ struct DevPtrs {
     const int32_t* batch_ids;      // lattices run by the persistent kernel
     const int2* groups;            // lockstep kernel: (lattice, first fragment) per wave
     int32_t n_groups;
-    int32_t fp_stride;             // Zero `bytes` bytes at p (a fill kernel: 16-byte stores, byte tail).
-int launch_fill_zero(void* p, size_t bytes, void* stream);
-// LDS bytes of one staged footprint
+    const int2* site_groups;       // lockstep site-model kernel: (lattice, fragment) per workgroup
+    int32_t n_site_groups;
+    int32_t fp_stride;             // LDS bytes of one staged footprint
     int32_t lds_region_bytes;      // persistent kernel: resident slab or staged footprints
     int32_t lds_wave_bytes;        // lockstep kernel: per-wave scratch plus footprints
 };
@@ -142,6 +142,8 @@ constexpr int64_t kStageSites = 1 << 19;
 // Kernel launchers (fkmc_device.hip).  All return a hipError_t value.
 int launch_init(const DevPtrs& P, const uint64_t* d_counts, int n_lat, void* stream);
 int launch_phase(const DevPtrs& P, int colour, int group, void* stream);
+// Fragment lattices with a site model: one workgroup per sub-block of the colour.
+int launch_phase_site(const DevPtrs& P, int colour, void* stream);
 int launch_cycle_begin(const DevPtrs& P, void* stream);
 int launch_cycle_end(const DevPtrs& P, void* stream);
 int launch_plain(const DevPtrs& P, const int32_t* d_plain_ids, int n_plain, int cap, void* stream);
