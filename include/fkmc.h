@@ -199,8 +199,9 @@ fkmc_status fkmc_set_rate_table(fkmc_lattice* lat, uint32_t i, const double* k12
 
 /* Site-energy interactions (Sec. "Oxygen vacancy diffusion with dopant and
  * defect interaction", with the pair energies of its Table TABLEadd01 as
- * inputs), for plain lattices of at least 5 cells per axis with at most 2048
- * vacancies.  The rate of a hop becomes
+ * inputs), for lattices of at least 5 cells per axis: plain lattices with at
+ * most 2048 vacancies, and fragment lattices whose sub-blocks are all wider
+ * than the vacancy-vacancy reach (below).  The rate of a hop becomes
  * k = nu exp(-(Ea_X + dE/2 + g dE_gb + dE_site/2)/(k_B T)) with dE_site the
  * vacancy's site energy at the target minus that at its origin.  The site
  * energy of an anion site sums integer pair energies (meV) over the Fe
@@ -212,21 +213,37 @@ fkmc_status fkmc_set_rate_table(fkmc_lattice* lat, uint32_t i, const double* k12
  * largest (FKMC_E_RANGE when a rate would keep fewer than 10 bits: narrow
  * the window).  A hop whose |dE_site| exceeds the window sets FKMC_E_RANGE
  * (the event counted as impossible; the trajectory no longer follows the
- * method).  Draws, clock and selection are plain BKL's (fkmc_advance), so
- * with all pair energies zero the run equals plain BKL bit for bit.
+ * method).  Draws, clock and selection are those of the lattice's mode in
+ * fkmc_advance (plain BKL, or the fragment cycle: phase c of cycle n in
+ * fragment f, step s uses Philox counter (s, f, n, c*256 + 2), the domain a
+ * sub-block's edges and its slots its footprint's vacancies), so with all
+ * pair energies zero the run equals the same mode without them bit for bit
+ * (fragment lattices: when the quanta agree, i.e. N_V is at most the
+ * smallest footprint's site count).  A fragment lattice with a site model
+ * runs the lockstep schedule whatever fkmc_set_schedule chose, one
+ * workgroup per sub-block and phase, its occupancy in HBM; a footprint with
+ * more than 256 vacancies sets FKMC_E_RANGE.  The rates of a sub-block read
+ * site energies at its footprint's sites, which reach the vacancies within
+ * the squared doubled distance of the farthest vacancy-vacancy shell with a
+ * nonzero energy (the reach: 16 when e_vv[5] != 0, 10 when only e_vv[0..4]
+ * are nonzero, ...); the footprint of the next sub-block of the same colour
+ * lies 2w doubled units away, w the width of the sub-block between them, so
+ * 4 w^2 > reach for every sub-block keeps the sub-blocks of a phase from
+ * reading each other's sites (no frozen halo is needed).
  * Returns the bytes of the caller-owned device buffer that holds lattice
  * i's Fe bitmap and rate table for a given window. */
 fkmc_status fkmc_site_model_bytes(const fkmc_lattice* lat, uint32_t i, int32_t window_meV, size_t* bytes);
 
-/* Enable site energies on plain lattice i: fe (host, L0 L1 L2 bytes in
+/* Enable site energies on lattice i: fe (host, L0 L1 L2 bytes in
  * canonical cell order (k L1 + j) L0 + i, 1 = Fe on that cell's B site),
  * pair energies and window as above, dev a caller-owned device buffer of
  * fkmc_site_model_bytes bytes (256-byte aligned) that must outlive the
  * model.  Call after fkmc_set_rates (FKMC_E_STATE otherwise; the table
  * uses those parameters); fkmc_set_rates, fkmc_set_rate_table,
  * fkmc_init_random, fkmc_set_occupancy and fkmc_restore remove it.
- * FKMC_E_UNSUPPORTED for fragment lattices, L < 5 or more than 2048
- * vacancies; fkmc_advance_atomic refuses such lattices. */
+ * FKMC_E_UNSUPPORTED for L < 5, a plain lattice of more than 2048
+ * vacancies, or a fragment lattice with a sub-block of width w and
+ * 4 w^2 <= the reach; fkmc_advance_atomic refuses lattices with a model. */
 fkmc_status fkmc_set_site_model(fkmc_lattice* lat, uint32_t i, const uint8_t* fe, const int32_t e_fe[4],
                                 const int32_t e_vv[6], int32_t window_meV, void* dev, size_t bytes);
 

@@ -242,7 +242,7 @@ class LatticeSet:
         _check(lib().fkmc_set_rates(self._h, arr))
 
     def set_site_model(self, i: int, fe, e_fe, e_vv, window_meV: int):
-        """Site energies on plain lattice i (fkmc_set_site_model): Fe map of
+        """Site energies on lattice i (fkmc_set_site_model): Fe map of
         one byte per cell, pair energies in meV; the device buffer is
         allocated here and kept with the set."""
         import torch

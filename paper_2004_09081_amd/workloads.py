@@ -132,17 +132,19 @@ def fe_map(L, x_fe: float, seed: int) -> np.ndarray:
 
 
 def voronoi_boundary_map(L, n_grains: int, width: float, seed: int) -> np.ndarray:
-    """Grain-boundary sites of a periodic Voronoi tessellation (the grain
-    geometry of the paper's micro-scale BaTiO3 model): n_grains seeds drawn
-    uniformly in the periodic box; an anion site belongs to the boundary
-    layer when its distance to the second-nearest seed exceeds that to the
-    nearest by less than `width` (cells), a layer about `width` cells thick
-    along every face between two grains.  One byte per site in canonical
-    order ((k L1 + j) L0 + i) 3 + type, 1 = boundary site.  Built slab by
-    slab along z."""
+    """Grain-boundary sites of a periodic Voronoi tessellation of the x-z
+    plane, extruded along y (the grain geometry of the paper's micro-scale
+    BaTiO3 model, which it builds in two dimensions and runs in three):
+    n_grains seeds drawn uniformly in the periodic x-z box; an anion site
+    belongs to the boundary layer when its in-plane distance to the
+    second-nearest seed exceeds that to the nearest by less than `width`
+    (cells), a layer about `width` cells thick along every face between two
+    grains.  One byte per site in canonical order ((k L1 + j) L0 + i) 3 +
+    type, 1 = boundary site.  Built slab by slab along z."""
     rng = np.random.default_rng(0x6B00 + int(seed))
     Lv = np.array(L, dtype=np.float64)
     seeds = rng.random((int(n_grains), 3)) * Lv
+    seeds[:, 1] = 0.0
     off = np.array([[0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]])
     out = np.empty(3 * L[0] * L[1] * L[2], dtype=np.uint8)
     per_k = 3 * L[0] * L[1]
@@ -156,6 +158,7 @@ def voronoi_boundary_map(L, n_grains: int, width: float, seed: int) -> np.ndarra
         for g in range(int(n_grains)):
             d = pos - seeds[g]
             d -= Lv * np.round(d / Lv)
+            d[:, 1] = 0.0  # in-plane (x-z) distance
             r[:, g] = np.sqrt((d * d).sum(axis=1))
         r.sort(axis=1)
         out[k0 * per_k:k1 * per_k] = ((r[:, 1] - r[:, 0]) < width).astype(np.uint8)

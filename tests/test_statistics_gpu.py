@@ -183,3 +183,46 @@ def test_cfg2_fragments_match_unfragmented_at_every_temperature(F):
                         bad.append((T, dv, nm, sg))
                 prev = r
     assert not bad, bad
+
+
+def test_fragment_site_energies_match_unfragmented_within_3_sigma(F):
+    """The accuracy criterion on the site model (Table TABLEadd01 energies,
+    vacancy-Fe and vacancy-vacancy): 24^3 cells, 0.2 % vacancies and Fe, 1000
+    K, 32 seeds; fragment kMC in 12^3 and 8^3-cell fragments (6- and 4-cell
+    sub-blocks, window about one hop per vacancy) against plain BKL with the
+    same energies, all from the same initial lattices to the same simulated
+    time: D_V agrees within 3 sigma of the difference."""
+    from paper_2004_09081_amd import workloads as W
+    L, T, xv, xfe, R = (24, 24, 24), 1000.0, 0.002, 0.002, 32
+    nv, _ = W.counts(3 * 24**3, xv, 0.0)
+    k0 = 1e13 * math.exp(-0.6 / (8.617333262e-5 * T))
+    t_sync = 1.0 / (8 * k0)
+    n_cyc = 300
+    t_end = n_cyc * t_sync
+    rp = F.RateParams.make(T=T, Ea_O=0.6)
+    sets = {}
+    for frag in (0, 12, 8):
+        geoms = [F.Geometry.make(L, (frag,) * 3, 3.905, s, 0) for s in range(R)]
+        S = F.LatticeSet(geoms)
+        S.init_random([nv] * R, [0] * R)
+        S.set_rates([rp] * R)
+        for s in range(R):
+            S.set_site_model(s, W.fe_map(L, xfe, s), W.SITE_E_FE_MEV, W.SITE_E_VV_MEV, 1200)
+        if frag == 0:
+            S.advance([t_end] * R, 0, 10**12)
+        else:
+            S.advance([t_sync] * R, max_cycles=n_cyc)
+        st = S.read_stats()
+        S.close()
+        assert all(abs(x["t"] - t_end) <= 1e-12 * t_end for x in st)
+        sets[frag] = np.array([x["D"][2] for x in st]), sum(int(x["hops"].sum()) for x in st)
+    Dp = sets[0][0]
+    for frag in (12, 8):
+        Df = sets[frag][0]
+        se = math.sqrt(Df.var(ddof=1) / R + Dp.var(ddof=1) / R)
+        diff = Df.mean() - Dp.mean()
+        say("  site model, %d^3 fragments: D_V %.5g vs %.5g A^2/us unfragmented (%+.2f sigma, %+.2f %%), "
+            "%d hops" % (frag, 1e-6 * Df.mean(), 1e-6 * Dp.mean(), diff / se, 100 * diff / Dp.mean(),
+                         sets[frag][1]))
+        assert abs(diff) < 3 * se, (frag, Df.mean(), Dp.mean(), se)
+        assert se < 0.05 * Dp.mean()
