@@ -13,6 +13,13 @@ per-lattice busy timer and hop counters give the device time per hop, so
 the time to reach the hop target is predicted per lattice, and each lattice
 gets the candidate with the smallest prediction.  The critical path of the
 ensemble is the slowest lattice, so the choice is made lattice by lattice.
+
+The unfragmented candidate wins near ties (within PLAIN_MARGIN of the best
+prediction, and still clear of the ensemble's slowest prediction): plain
+BKL has no splitting error, and its cost per hop does not depend on how the
+hops spread over tiles, which drifts as a lattice evolves from its initial
+state (at low temperature the hops gather around the vacancies next to H
+ions), while a short trial from the initial state sees only the start.
 """
 from __future__ import annotations
 
@@ -30,6 +37,8 @@ ENSEMBLE_EDGES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned
 
 PLAIN_LDS_VACANCIES = 512
 PLAIN_LDS_BYTES = 62_000
+PLAIN_MARGIN = 0.05  # the unfragmented candidate wins within 5 % of the best prediction
+PLAIN_CLEARANCE = 0.95  # ... when it stays below 95 % of the slowest lattice's prediction
 
 
 def whole_if_sparse(spec) -> int:
@@ -125,6 +134,7 @@ def tune(make_specs, hop_target: int, candidates=DEFAULT_CANDIDATES, cycles: int
     n = len(base)
     best_t = np.full(n, np.inf)
     best_f = np.full(n, 8, dtype=np.int64)
+    plain_t = np.full(n, np.inf)
     report = {}
     for c in candidates:
         label = c.__name__ if callable(c) else str(c)
@@ -149,9 +159,17 @@ def tune(make_specs, hop_target: int, candidates=DEFAULT_CANDIDATES, cycles: int
         better = pred < best_t
         best_t[better] = pred[better]
         best_f[better] = used[better]
+        plain_t = np.where(used == 0, np.minimum(plain_t, pred), plain_t)
         report[label] = {"max_pred_ms": float(pred.max()), "median_pred_ms": float(np.median(pred))}
         if log:
             log("autotune F=%s: slowest lattice predicted %.0f ms" % (label, pred.max()))
+    near = (best_f != 0) & (plain_t <= best_t * (1.0 + PLAIN_MARGIN)) & \
+        (plain_t <= PLAIN_CLEARANCE * best_t.max())
+    best_f[near] = 0
+    best_t[near] = plain_t[near]
+    report["plain_near_ties"] = int(near.sum())
+    if log:
+        log("autotune: %d lattices take the unfragmented candidate on a near tie" % int(near.sum()))
     report["chosen_max_pred_ms"] = float(best_t.max())
     report["histogram"] = {int(k): int(v) for k, v in zip(*np.unique(best_f, return_counts=True))}
     return best_f, report
