@@ -938,6 +938,14 @@ fkmc_status fkmc_set_gb_map(fkmc_lattice* L, uint32_t i, const uint8_t* map, voi
         L->desc[i] = backup;
         return st;
     }
+    // the lockstep kernel with the map branch only while some lattice has a map
+    int32_t any = 0;
+    for (uint32_t k = 0; k < L->n; k++) any |= L->desc[k].gb_map ? 1 : 0;
+    if (any != L->P.gb_maps && L->graph) {
+        (void)hipGraphExecDestroy(L->graph);
+        L->graph = nullptr;
+    }
+    L->P.gb_maps = any;
     return FKMC_OK;
 }
 

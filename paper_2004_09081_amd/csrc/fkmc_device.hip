@@ -400,6 +400,9 @@ __device__ __forceinline__ int gb_flag(const RateCtx& C, int t, int cell)
 // Rate of event d of the vacancy at packed local doubled coordinates xyz:
 // 0 when the hop edge's midpoint is outside the sub-block or the target
 // holds a vacancy; else the table entry for (ion species, z step, boundary).
+// MAP: the lattice may have a boundary-site map (C.gbmap); without it the
+// map branch is compiled out (the lockstep kernel keeps 128 VGPRs).
+template <bool MAP = true>
 __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned char* occl,
                                             const RateCtx& C, uint32_t xyz, int d)
 {
@@ -418,7 +421,7 @@ __device__ __forceinline__ double tile_rate(const TileGeo& G, const unsigned cha
     const int lds0 = G.lds0;
     const int sp = occl[in ? seg_lds(G, seg) + li : lds0];
     int g = 0;
-    if (C.gbmap) {
+    if (MAP && C.gbmap) {
         int si = G.ox + (X >> 1), sj = G.oy + (Y >> 1), sk = G.oz + (Z >> 1);
         int ti = G.ox + (tX >> 1), tj = G.oy + (tY >> 1), tk = G.oz + (tZ >> 1);
         si -= si >= C.L0 ? C.L0 : 0;
@@ -956,7 +959,7 @@ struct GroupCall {
 // allows), each caching the rates of 8/G consecutive events; K = 1 with
 // n > 64 recomputes the rates from LDS at every step.  After a hop only the
 // events whose vacancy moved or whose target changed are recomputed.
-template <int K, int E, bool TR>
+template <int K, int E, bool TR, bool MAP = true>
 __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, unsigned char* occl,
                                           uint32_t* sxyz, int n, uint32_t f, const GroupCall& X,
                                           int lane, Rec& rec, RecCtl& rc, uint32_t& ho, uint32_t& hh)
@@ -989,7 +992,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
 #pragma unroll
         for (int j = 0; j < E; j++) {
             if (j < epl) {
-                kk[j] = tile_rate(G, occl, C, my_xyz, my_d0 + j);
+                kk[j] = tile_rate<MAP>(G, occl, C, my_xyz, my_d0 + j);
                 ls += kk[j];
             }
         }
@@ -1031,7 +1034,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             ls = 0.0;
             for (int s = s0; s < s1; s++) {
                 const uint32_t xyz = sxyz[s];
-                for (int d = 0; d < 8; d++) ls += tile_rate(G, occl, C, xyz, d);
+                for (int d = 0; d < 8; d++) ls += tile_rate<MAP>(G, occl, C, xyz, d);
             }
         }
         const double lsv = active ? ls : 0.0;
@@ -1087,7 +1090,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
                 for (int s = s0; s < s1 && found < 0; s++) {
                     const uint32_t xyz = sxyz[s];
                     for (int d = 0; d < 8; d++) {
-                        const double k = tile_rate(G, occl, C, xyz, d);
+                        const double k = tile_rate<MAP>(G, occl, C, xyz, d);
                         if (k > 0.0) { last = s * 8 + d; lx = xyz; }
                         Cc += k;
                         if (!fb && Cc > y) { found = s * 8 + d; lx = xyz; break; }
@@ -1157,7 +1160,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             // first 8, pulled by the lanes that cache them
             if (__ballot(mover)) {
                 double nk = 0.0;
-                if (go && sl < 8) nk = tile_rate(G, occl, C, tx, sl);
+                if (go && sl < 8) nk = tile_rate<MAP>(G, occl, C, tx, sl);
 #pragma unroll
                 for (int j = 0; j < E; j++) {
                     const double v = lane_pull(nk, sb + ((my_d0 + j) & 7));
@@ -1191,7 +1194,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
 // (E1 cached events per lane there).
 // With `single`, every tile runs on the whole wave, one after another, and
 // a streamed lattice stages one footprint at a time.
-template <int K, int E1, bool TR>
+template <int K, int E1, bool TR, bool MAP = true>
 __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, int f0, int nt, int colour,
                                           const GroupCall& X, const WaveLds& W, unsigned char* lds0,
                                           int fp, int fps, bool resident, bool single, uint32_t* vlist,
@@ -1253,7 +1256,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
         if (n_seg <= FIT && sl < n_seg) sort_list(W, seg * S, n_seg, sl, resident);
         wave_lds_fence();
         const int n_run = n_seg <= FIT ? n_seg : 0;
-        group_bkl<K, 4, TR>(G, C, lds0, W.xyz + seg * S, n_run, (uint32_t)(f0 + seg), X, lane, rec, rc, ho,
+        group_bkl<K, 4, TR, MAP>(G, C, lds0, W.xyz + seg * S, n_run, (uint32_t)(f0 + seg), X, lane, rec, rc, ho,
                         hh);
         wave_lds_fence();
         if (resident && sl < n_run) list_update(W, G, D, vlist, seg * S, sl);
@@ -1290,7 +1293,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
         }
         for (int l = lane; l < n1; l += 64) sort_list(W, 0, n1, l, resident);
         wave_lds_fence();
-        group_bkl<1, E1, TR>(T, C, lds0, W.xyz, n1, (uint32_t)(f0 + q), X, lane, rec, rc, ho, hh);
+        group_bkl<1, E1, TR, MAP>(T, C, lds0, W.xyz, n1, (uint32_t)(f0 + q), X, lane, rec, rc, ho, hh);
         wave_lds_fence();
         if (resident)
             for (int l = lane; l < n1; l += 64) list_update(W, T, D, vlist, 0, l);
@@ -1301,7 +1304,7 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
 // ----------------------------------------------------------------------------
 // Lockstep phase kernel: one wave per group of K tiles of colour `colour`
 // (P.groups: lattice and first fragment), footprints staged HBM -> LDS.
-template <int K>
+template <int K, bool MAP>
 __global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colour)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1336,7 +1339,7 @@ __global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colou
     uint32_t ho = 0, hh = 0;
     bool err = false;
     if (lane < 12) W.k12[lane] = D.k12[lane];
-    run_group<KG, 4, false>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratchStaged, P.fp_stride,
+    run_group<KG, 4, false, MAP>(P, D, f0, nt, colour, X, W, smem, (int)(base - smem) + kWaveScratchStaged, P.fp_stride,
                   false, K == 1, nullptr, 0, nullptr, nullptr, lane, rec, rc, ho, hh, err);
     rec_flush(rec, rc, P.disp);
     constexpr int S = K == 1 ? 64 : 64 / K;
@@ -3763,19 +3766,25 @@ int launch_init(const DevPtrs& P, const uint64_t* d_counts, int n_lat, void* str
 
 using PhaseFn = void (*)(DevPtrs, int);
 
-static PhaseFn phase_fn(int group)
+// The lockstep kernel for a group size; the variant with the boundary-site
+// map branch only when a lattice of the set has a map.
+static PhaseFn phase_fn(int group, bool map)
 {
-    return group == 8 ? k_phase<8> : (group == 4 ? k_phase<4> : (group == 2 ? k_phase<2> : k_phase<1>));
+    if (map)
+        return group == 8 ? k_phase<8, true>
+                          : (group == 4 ? k_phase<4, true> : (group == 2 ? k_phase<2, true> : k_phase<1, true>));
+    return group == 8 ? k_phase<8, false>
+                      : (group == 4 ? k_phase<4, false> : (group == 2 ? k_phase<2, false> : k_phase<1, false>));
 }
 
 // Allow the lockstep workgroup's dynamic LDS beyond the default 64 KB.
-static hipError_t phase_lds_attr(int group, size_t lds)
+static hipError_t phase_lds_attr(int group, bool map, size_t lds)
 {
-    static size_t granted[9] = {0};
-    if (lds <= 65536 || lds <= granted[group]) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute((const void*)phase_fn(group),
+    static size_t granted[2][9] = {{0}};
+    if (lds <= 65536 || lds <= granted[map][group]) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)phase_fn(group, map),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e == hipSuccess) granted[group] = lds;
+    if (e == hipSuccess) granted[map][group] = lds;
     return e;
 }
 
@@ -3791,10 +3800,10 @@ int launch_phase(const DevPtrs& P, int colour, int group, void* stream)
     if (P.n_groups == 0) return 0;
     const int wpb = phase_waves(P);
     const size_t lds = (size_t)P.lds_wave_bytes * wpb;
-    hipError_t e = phase_lds_attr(group, lds);
+    hipError_t e = phase_lds_attr(group, P.gb_maps != 0, lds);
     if (e != hipSuccess) return (int)e;
     const int blocks = (P.n_groups + wpb - 1) / wpb;
-    hipLaunchKernelGGL(phase_fn(group), dim3(blocks), dim3(64 * wpb), lds, (hipStream_t)stream, P,
+    hipLaunchKernelGGL(phase_fn(group, P.gb_maps != 0), dim3(blocks), dim3(64 * wpb), lds, (hipStream_t)stream, P,
                        colour);
     return (int)hipGetLastError();
 }
@@ -3828,7 +3837,7 @@ int build_cycle_graph(const DevPtrs& P, int group, int cycles, hipGraphExec_t* o
 {
     const int wpb = phase_waves(P);
     const size_t lds = (size_t)P.lds_wave_bytes * wpb;
-    hipError_t e = phase_lds_attr(group, lds);
+    hipError_t e = phase_lds_attr(group, P.gb_maps != 0, lds);
     if (e != hipSuccess) return (int)e;
     hipGraph_t g;
     e = hipGraphCreate(&g, 0);
@@ -3844,7 +3853,7 @@ int build_cycle_graph(const DevPtrs& P, int group, int cycles, hipGraphExec_t* o
             argv[0] = &args_p;
             if (col < 8) {
                 argv[1] = &colours[col];
-                kp.func = (void*)phase_fn(group);
+                kp.func = (void*)phase_fn(group, P.gb_maps != 0);
                 kp.gridDim = dim3((P.n_groups + wpb - 1) / wpb);
                 kp.blockDim = dim3(64 * wpb);
                 kp.sharedMemBytes = (unsigned)lds;

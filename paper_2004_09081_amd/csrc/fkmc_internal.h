@@ -121,6 +121,7 @@ struct DevPtrs {
     int32_t n_groups;
     const int2* site_groups;       // lockstep site-model kernel: (lattice, fragment) per workgroup
     int32_t n_site_groups;
+    int32_t gb_maps;               // nonzero when a lattice of the set has a boundary-site map
     int32_t fp_stride;             // LDS bytes of one staged footprint
     int32_t lds_region_bytes;      // persistent kernel: resident slab or staged footprints
     int32_t lds_wave_bytes;        // lockstep kernel: per-wave scratch plus footprints
