@@ -2342,6 +2342,7 @@ __global__ __launch_bounds__(256) void k_atomic(DevPtrs P, const int32_t* ids, u
 // lattice whose phase is one group runs on wave 0 alone, without barriers,
 // and keeps its displacement records across phases.  Plain lattices held in
 // LDS run plain BKL on wave 0.
+template <bool MAP>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_batch(DevPtrs P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -2476,11 +2477,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                     const int f0 = g * K;
                     const int nt = ntiles - f0 < K ? ntiles - f0 : K;
                     if (K == 4)
-                        run_group<4, 8, true>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, false,
+                        run_group<4, 8, true, MAP>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, false,
                                         vlist, nv_list, c2s, solo ? rcache + colour * ntiles : nullptr,
                                         lane, rec, rc, ho, hh, err);
                     else
-                        run_group<8, 8, true>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
+                        run_group<8, 8, true, MAP>(P, D, f0, nt, colour, X, W, occl, fp, D.fp_stride, resident, K == 1,
                                         vlist, nv_list, c2s, solo ? rcache + colour * ntiles : nullptr,
                                         lane, rec, rc, ho, hh, err);
                 }
@@ -3823,10 +3824,11 @@ int launch_batch(const DevPtrs& P, int n_batch, int waves, void* stream)
 {
     if (n_batch == 0) return 0;
     const size_t lds = (size_t)P.lds_region_bytes + (size_t)waves * kWaveScratch + kRecCache;
-    hipError_t e = hipFuncSetAttribute((const void*)k_batch,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // the variant with the boundary-site map branch only when a lattice has a map
+    const auto fn = P.gb_maps ? k_batch<true> : k_batch<false>;
+    hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return (int)e;
-    hipLaunchKernelGGL(k_batch, dim3(n_batch), dim3(64 * waves), lds, (hipStream_t)stream, P);
+    hipLaunchKernelGGL(fn, dim3(n_batch), dim3(64 * waves), lds, (hipStream_t)stream, P);
     return (int)hipGetLastError();
 }
 
