@@ -1045,13 +1045,16 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         const double lnu = S == 64 ? lane_value(dr_ln, dl) : lane_pull(dr_ln, sb + (dl & (S - 1)));
         const double dt = -lnu / R;
         const double tn = tau + dt;
-        // the event is chosen for every tile that can still hop (act), and
-        // taken only by those whose next event lands inside the window
-        // (go): the choice does not wait for the clock's division
-        const bool act = active && R != 0.0;
+        // a tile hops when it has an event (R > 0) and its next event lands
+        // inside the window; the step that finds no tile hopping ends the
+        // loop before any selection work
+        const bool go = active && R != 0.0 && tn <= X.t_sync;
+        active = go;
+        if (__ballot(go) == 0) break;
+        if (go) tau = tn;
         const double y = u_sel * R;
-        const uint64_t mk_all = __ballot(act && incl > y);
-        const uint64_t nz_all = __ballot(act && lsv > 0.0);
+        const uint64_t mk_all = __ballot(go && incl > y);
+        const uint64_t nz_all = __ballot(go && lsv > 0.0);
         bool fb;
         int sel;
         if (S < 64) {
@@ -1071,7 +1074,7 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
         }
         // the selected lane of each segment picks the event
         int pick = 0, pslot = 0;
-        if (act && lane == sel) {
+        if (go && lane == sel) {
             double Cc = incl - lsv;
             int found = -1, last = -1;
             if (cached) {
@@ -1108,9 +1111,6 @@ __device__ __forceinline__ void group_bkl(const TileGeo& G, const RateCtx& C, un
             pick = lane_pull(pick, sel);
             pslot = lane_pull(pslot, sel);
         }
-        const bool go = act && tn <= X.t_sync;
-        active = go;
-        if (go) tau = tn;
         pick = go ? pick : 0;
         const uint32_t sx = (uint32_t)pick & 0x1FFFFFFFu;
         const int d = (int)((uint32_t)pick >> 29);
@@ -1304,8 +1304,11 @@ __device__ __forceinline__ void run_group(const DevPtrs& P, const LatDesc& D, in
 // ----------------------------------------------------------------------------
 // Lockstep phase kernel: one wave per group of K tiles of colour `colour`
 // (P.groups: lattice and first fragment), footprints staged HBM -> LDS.
+// Without the boundary-site map branch the kernel is held to 128 VGPRs, so
+// that 4 wavefronts share a SIMD (it fits without scratch).
 template <int K, bool MAP>
-__global__ __launch_bounds__(64 * kPhaseWaves) void k_phase(DevPtrs P, int colour)
+__global__ __launch_bounds__(64 * kPhaseWaves) __attribute__((amdgpu_waves_per_eu(MAP ? 1 : 4)))
+void k_phase(DevPtrs P, int colour)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
