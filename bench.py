@@ -377,22 +377,26 @@ def one_per_launch(F, specs, idx, hop_target):
     return ph, pt
 
 
-def atomic_leg(F, specs, n_frg, stages):
+def atomic_leg(F, specs, n_frg, stages, replicas=1):
     """The paper's atom-selection scheme with null events (Eqs. AtomP and
     TimeStepFrg) on every ensemble lattice that fits in LDS unfragmented,
     all in one launch, against BKL on the same lattices from the same
     initial states: hops/s of both, and the ratio of the vacancy tracer D
     for n_frg selections per stage (the paper's parallel approximation) and
-    for one (an exact kMC, so its ratio checks the estimator)."""
+    for one (an exact kMC, so its ratio checks the estimator).  With
+    replicas > 1 every such lattice runs that many times with its own
+    random streams (lattice ids 512 apart), which narrows the D ratios."""
     import torch
     from paper_2004_09081_amd.autotune import plain_if_sparse
     sel = []
-    for sp in specs:
-        if plain_if_sparse(sp) == 0:
-            q = copy.copy(sp)
-            q.frag = (0, 0, 0)
-            q.t_sync = 0.0
-            sel.append(q)
+    for r in range(replicas):
+        for sp in specs:
+            if plain_if_sparse(sp) == 0:
+                q = copy.copy(sp)
+                q.frag = (0, 0, 0)
+                q.t_sync = 0.0
+                q.lattice_id = sp.lattice_id + 512 * r
+                sel.append(q)
     n = len(sel)
 
     def run(fn):
@@ -440,8 +444,9 @@ def atomic_leg(F, specs, n_frg, stages):
                              "D_vacancy_ratio_to_bkl": r1},
            "estimator": "D ratio = sum over lattices of D_V / the same sum for BKL run to the same "
                         "simulated time on each lattice",
-           "sample": "%d of %d ensemble lattices (those held in LDS unfragmented), %d stages of %d "
-                     "selections (and of 1), each against BKL to the same times" % (n, len(specs), stages, n_frg)}
+           "sample": "%d of %d ensemble lattices (those held in LDS unfragmented) x %d replica(s), %d stages "
+                     "of %d selections (and of 1), each against BKL to the same times"
+                     % (n // replicas, len(specs), replicas, stages, n_frg)}
     log("atom selection (N_frg %d): %.4g hops/s on %d lattices, %.2f hops per stage, D_V ratio to BKL "
         "%.4f +- %.4f; N_frg 1: %.4g hops/s, D_V ratio %.4f +- %.4f; BKL on the same lattices %.4g hops/s"
         % (n_frg, rep["value"], n, rep["hops_per_stage"], ra["value"], ra["stderr"],
@@ -528,6 +533,8 @@ def main():
     ap.add_argument("--atomic-stages", type=int, default=20000,
                     help="stages of the atom-selection leg (0: skip)")
     ap.add_argument("--atomic-frg", type=int, default=64, help="selections per stage of that leg")
+    ap.add_argument("--atomic-replicas", type=int, default=1,
+                    help="runs of each of that leg's lattices with their own random streams")
     ap.add_argument("--atomic-hbm-stages", type=int, default=2000,
                     help="stages of the atom-selection leg on lattices past the LDS kernel (0: skip)")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -743,7 +750,7 @@ def main():
         log("fragment kMC one-per-launch: %.4g hops/s (batched/one = %.1f)" % (frag_rate, value / frag_rate))
 
     if args.workload == "cfg4" and args.atomic_stages > 0:
-        out["atom_selection"] = atomic_leg(F, specs, args.atomic_frg, args.atomic_stages)
+        out["atom_selection"] = atomic_leg(F, specs, args.atomic_frg, args.atomic_stages, args.atomic_replicas)
         if args.atomic_hbm_stages > 0:
             out["atom_selection_hbm"] = atomic_hbm_leg(F, specs, args.atomic_frg, args.atomic_hbm_stages)
 
