@@ -321,7 +321,7 @@ class LatticeSet:
 
     def advance_atomic(self, n_frg: int, n_stages: int):
         """Atom-selection fragment kMC with null events (Eqs. AtomP and
-        TimeStepFrg) on a set of plain lattices of at most 4096 vacancies:
+        TimeStepFrg) on a set of plain lattices of at most 8192 vacancies:
         n_stages stages of n_frg selected vacancies each."""
         _check(lib().fkmc_advance_atomic(self._h, int(n_frg), int(n_stages)))
 
