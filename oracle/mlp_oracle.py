@@ -9,8 +9,10 @@ the values that the GPU kernels hold in BF16 are rounded to BF16 (round to
 nearest even) at the same points: all three weight matrices, the first
 hidden activation h1 and the back-propagated dz2 entering the two 128x128
 products; everything else is float64 here (float32 on the GPU).  The
-gradient is the plain chain rule of that computation.  Parity unpinned
-beyond: finite differences (emulate=False) and brute-force BF16 rounding.
+gradient is the plain chain rule of that computation.  Pinned by
+single-path networks computed by hand (the forward wiring), finite
+differences (the gradient, emulate=False), brute-force BF16 rounding and
+the closed form of Adam's first step.
 """
 from __future__ import annotations
 

@@ -62,3 +62,29 @@ def test_standardisation_moments():
     for o in range(2):
         t = (Y[M[:, o] != 0, o] - ym[o]) / ys[o]
         assert abs(t.mean()) < 1e-12 and abs(t.std() - 1) < 1e-12
+
+
+def test_forward_single_paths_match_hand_computation():
+    """A network with one nonzero weight per layer computes one scalar path,
+    written out here with math.exp: an input, hidden or output index taken
+    from the wrong axis (a transposed operand) sends the signal elsewhere."""
+    import math
+    rng = np.random.default_rng(4)
+    X = rng.normal(size=(9, 4)) * 2.0
+    for i, j, k, o in ((2, 17, 101, 1), (0, 127, 3, 0), (3, 64, 64, 1)):
+        d = {name: np.zeros(shape) for name, shape in R.SIZES}
+        a, b, c = 0.75, -1.5, 2.25
+        d["W1"][i, j] = a
+        d["W2"][j, k] = b
+        d["W3"][k, o] = c
+        d["b3"][:] = (0.3, -0.7)
+        y, _ = R.forward(R.pack(d), X, emulate=False)
+        for n in range(X.shape[0]):
+            z1 = X[n, i] * a
+            h1 = z1 / (1.0 + math.exp(-z1))
+            z2 = h1 * b
+            h2 = z2 / (1.0 + math.exp(-z2))
+            want = [0.3, -0.7]
+            want[o] += h2 * c
+            assert abs(y[n, o] - want[o]) <= 1e-14 * max(1.0, abs(want[o])), (i, j, k, o, n)
+            assert y[n, 1 - o] == want[1 - o]
