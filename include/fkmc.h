@@ -329,9 +329,14 @@ fkmc_status fkmc_advance_atomic(fkmc_lattice* lat, uint32_t n_frg, uint64_t n_st
  *    workgroup of `waves` wavefronts per lattice running all its cycles,
  *    small lattices held entirely in LDS (best for ensembles);
  *  FKMC_SCHEDULE_AUTO (default): persistent for a set of at least 32
- *    fragment lattices, or of several lattices of at most 49152 sites each;
- *    lockstep otherwise.  waves in 1..8; 0 keeps the current value
- *    (default 4). */
+ *    fragment lattices, of several lattices of at most 49152 sites each, or
+ *    of several lattices that the GPU can give a compute unit each (no
+ *    more lattices than compute units) whose fragment lattices have at most
+ *    128 tiles per colour; lockstep otherwise.
+ *  waves in 1..8; 0 keeps the current value.  Until a value is set the
+ *  persistent workgroups are sized per call: 8 wavefronts for a set that
+ *  has at most one lattice per compute unit and at most 128 tiles per
+ *  colour in each fragment lattice, else 4. */
 #define FKMC_SCHEDULE_AUTO 0
 #define FKMC_SCHEDULE_LOCKSTEP 1
 #define FKMC_SCHEDULE_PERSISTENT 2
