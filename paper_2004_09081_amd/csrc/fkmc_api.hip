@@ -1028,7 +1028,18 @@ static fkmc_status prepare_lockstep(fkmc_lattice* L)
     int g = 4;
     for (int32_t i : L->batch_ids)
         g = std::min(g, pick_group(mean_footprint_vacancies(L, i), L->fp_stride, 32768 - kWaveScratchStaged, true));
-    if (L->group_override) g = L->group_override;
+    if (L->group_override) {
+        g = L->group_override;
+    } else {
+        // few tiles: fewer per wavefront, until a launch has two wavefronts
+        // per SIMD or one tile each (80 wavefronts of 4 tiles leave most of
+        // the GPU idle: the five-lattice 48^3 set takes 1.34 s per 2e6 hops
+        // each that way, 0.81 s with one tile per wavefront)
+        int64_t tiles = 0;
+        for (int32_t i : L->batch_ids)
+            if (L->desc[i].site_window < 0) tiles += (int64_t)L->desc[i].nf[0] * L->desc[i].nf[1] * L->desc[i].nf[2];
+        while (g > 1 && tiles / g < 8 * (int64_t)L->n_cu) g /= 2;
+    }
     while (g > 1 && kWaveScratchStaged + g * L->fp_stride > 65536) g /= 2;
     // lattices with a site model: one entry per sub-block, after the groups
     std::vector<int2> groups, site_groups;
