@@ -345,7 +345,9 @@ fkmc_status fkmc_set_schedule(fkmc_lattice* lat, int32_t schedule, int32_t waves
 /* Tile groups: a wavefront runs `group` tiles of a phase at once, each on
  * 64/group lanes with that many vacancy slots; a tile with more vacancies
  * runs afterwards on the whole wavefront.  group = 0 (default) chooses per
- * lattice from the mean vacancy count of a footprint; otherwise the
+ * lattice from the mean vacancy count of a footprint (the lockstep schedule
+ * then halves it while a launch would have fewer than 8 wavefronts per
+ * compute unit); otherwise the
  * lockstep schedule uses group (1, 2, 4 or 8) and the persistent schedule
  * uses 8 or 4 when group is 8 or 4 and 1 (whole wavefront per tile) for any
  * other value, or when the staged footprints of that many tiles per
