@@ -1194,10 +1194,6 @@ static fkmc_status plan_batch(fkmc_lattice* L, const std::vector<int32_t>& ids)
     return upload_desc(L);
 }
 
-// AUTO: the persistent kernel gives every lattice one workgroup, which pays
-// off for an ensemble (at least 32 lattices, or lattices small enough to sit
-// in LDS); a few large lattices are better served by lockstep launches that
-// spread every lattice's tiles over the whole GPU.
 // A set that the persistent kernel can give one compute unit per lattice
 // (at most as many lattices as compute units), whose fragment lattices have
 // at most 128 tiles per colour (16 per wavefront of 8): each workgroup then
@@ -1222,6 +1218,11 @@ static int auto_waves(const fkmc_lattice* L)
     return small_set(L) ? 8 : 4;
 }
 
+// AUTO: the persistent kernel gives every lattice one workgroup, which pays
+// off for an ensemble (at least 32 lattices, or lattices small enough to sit
+// in LDS); a few large lattices are better served by lockstep launches that
+// spread every lattice's tiles over the whole GPU.  A small set (above)
+// takes the persistent kernel too.
 static bool use_persistent(const fkmc_lattice* L)
 {
     if (L->batch_ids.empty()) return false;
